@@ -1,0 +1,200 @@
+/*
+ * mumode.h -- C ABI of the mu-mode exponential-integrator library for MI355X (gfx950).
+ *
+ * Problem (Sec. 3, eq. (eq:adr) with a scalar diffusion coefficient and constant
+ * velocity, on the unit cube with homogeneous Dirichlet data):
+ *
+ *     u_t = div(a(x) grad u) + beta . grad u + r(u),     r(u) = r0 + r1 u + r2 u^2 + r3 u^3,
+ *
+ * split as u_t = A u + g(u) (eqs. (eq:adr_equiv), (eq:linop), (eq:nonlin)) with the
+ * extracted constant-coefficient operator A = lambda*a_max*Laplacian + beta_bar . grad
+ * and a_max = max over the sampled nodes of a (eq. (eq:amaxbeta)). Second-order centred
+ * finite differences make A a Kronecker sum A_d (+) ... (+) A_1 of tridiagonal 1D
+ * matrices (Sec. 5.2), whose exponential acts on a grid tensor V as the mu-mode
+ * product V x_1 exp(tau A_1) x_2 exp(tau A_2) (x_3 exp(tau A_3)) (Sec. 1, Sec. 5.2).
+ *
+ * Memory layout (all grid functions, device memory, FP64 unless noted):
+ *   interior unknowns u[i3][i2][i1], x1 fastest, n1*n2*n3 values (d = 2: n3 = 1);
+ *   diffusion coefficient a on all nodes including the boundary,
+ *   (n3+2)*(n2+2)*(n1+2) values, x1 fastest; node (i1,i2,i3) sits at (i1 h1, i2 h2, i3 h3),
+ *   h_mu = 1/(n_mu + 1).
+ *
+ * Ownership: the caller owns every grid buffer it passes (u, a, g, F, in, out) and keeps
+ * it alive until the work enqueued on it has finished. The library owns mm_ctx, mm_op
+ * and mm_server and everything they allocate. mumode_setup copies a.
+ *
+ * Errors: every call returns an mm_status; none aborts the process. A message for the
+ * last failure of a context is available from mm_last_error(ctx). Step and apply calls
+ * are stream-ordered and asynchronous: they return MM_OK once the work is enqueued; a
+ * device fault or a non-finite solution surfaces at mm_check(op) or a later call.
+ * An mm_ctx (and any mm_op made from it) must be used from one host thread at a time.
+ * The server calls are thread-safe.
+ */
+#ifndef MUMODE_H
+#define MUMODE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MM_OK = 0,
+  MM_NOT_READY = 1,   /* solve_poll: the request has not finished                  */
+  MM_EINVAL = -1,     /* invalid argument                                          */
+  MM_ENOMEM = -2,     /* device allocation failed, or a request exceeds the budget */
+  MM_EDEVICE = -3,    /* a HIP runtime call failed                                 */
+  MM_EUNSTABLE = -4,  /* the solution became non-finite                            */
+  MM_EBUSY = -5,      /* server queue full                                         */
+  MM_ENOTFOUND = -6   /* unknown request id                                        */
+} mm_status;
+
+/* Arithmetic of the mu-mode contractions. Setup, the remainder stencil and the stage
+ * updates are FP64 in every mode; state between contraction passes is FP64.
+ *   MM_FP64      FP64 MFMA, FP64 accumulation (the plain baseline).
+ *   MM_FP32      operands rounded to FP32 (nearest even), FP32 MFMA over 16-long
+ *                K-chunks, chunk sums accumulated in FP64.
+ *   MM_BF16X3    each operand split x = hi + lo into two BF16 values (nearest even);
+ *                hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 over 32-long K-chunks,
+ *                chunk sums in FP64 ("split-BF16 x3").
+ *   MM_BF16X6    three BF16 slices x = s0 + s1 + s2; the six products s_i*s_j with
+ *                i + j <= 2, same accumulation.                                      */
+typedef enum { MM_FP64 = 0, MM_FP32 = 1, MM_BF16X3 = 2, MM_BF16X6 = 3 } mm_prec;
+
+/* Scheme families and members (Appendix).
+ *   family MM_LAWSON: MM_LAWSON_EULER  u+ = e^{tau A}(u + tau g(u))
+ *                     MM_LAWSON2B      U = e^{tau A}(u + tau g(u)),
+ *                                      u+ = e^{tau A}(u + tau/2 g(u)) + tau/2 g(U)
+ *   family MM_ERK:    MM_ETD2RK        second-order ERK with phi1, c2 = 1, in the form
+ *                                      U = e^{tau A}u + tau phi1(tau A) g(u),
+ *                                      u+ = U + tau/2 phi1(tau A)(g(U) - g(u))
+ *                     MM_ERK2P1        the same scheme in the Appendix form
+ *                                      U = u + tau phi1(tau A) F(u),
+ *                                      u+ = U + tau/2 phi1(tau A)(g(U) - g(u))
+ * phi1(tau A) is replaced by the q-node Gauss-Legendre rule
+ *   phi1(tau A) v ~ sum_j w_j exp(theta_j tau A) v,  theta_j, w_j on [0, 1].         */
+enum { MM_LAWSON = 0, MM_ERK = 1 };
+enum { MM_LAWSON_EULER = 0, MM_LAWSON2B = 1 };
+enum { MM_ETD2RK = 0, MM_ERK2P1 = 1 };
+
+typedef struct {
+  int d;                 /* 2 or 3                                                    */
+  int n[3];              /* interior points per axis, x1 first (n[2] ignored if d=2)  */
+  const double* a;       /* device, nodal diffusion coefficient incl. boundary        */
+  double beta[3];        /* constant velocity                                         */
+  double r[4];           /* reaction coefficients r0..r3                              */
+  double lambda;         /* extraction factor, eq. (eq:linop)                         */
+  double beta_bar[3];    /* advection moved into A, eq. (eq:linop)                    */
+} mm_problem;
+
+typedef struct mm_ctx mm_ctx;
+typedef struct mm_op mm_op;
+typedef struct mm_server mm_server;
+
+/* Create a context on HIP device `device` (it becomes current on the calling thread). */
+mm_status mm_ctx_create(int device, mm_ctx** out);
+void mm_ctx_destroy(mm_ctx* ctx);
+/* Message of the last failure on this context (static storage, never NULL). */
+const char* mm_last_error(const mm_ctx* ctx);
+/* Library version string and the number of exported entry points. */
+const char* mm_version(void);
+
+/* Build the operator for one problem and time step (Sec. 3 extraction, Sec. 5.2
+ * Kronecker factors): a_max by a device reduction, the tridiagonal A_mu, and on the
+ * device in FP64 the dense factors E_mu(c) = exp(c tau A_mu) by [13/13] Pade
+ * scaling-and-squaring for every c the scheme needs (c = 1 and the quadrature nodes
+ * theta_j for MM_ERK), plus FP32 or BF16-slice copies for the mixed modes. Returns
+ * after the setup has finished. quad_nodes (q) is 1..7 for MM_ERK and ignored for
+ * MM_LAWSON. slices is reserved (0). `a` must be complete when the call is made (the
+ * copy runs on the context's own stream, which does not wait for other streams).
+ * Errors: MM_EINVAL (d, n < 1, tau <= 0 or not finite, unknown family/scheme/prec,
+ * a == NULL), MM_ENOMEM, MM_EDEVICE. */
+mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int family, int scheme,
+                       int quad_nodes, int prec, int slices, mm_op** out);
+/* Release the op. Work enqueued with it must have completed (synchronise first). */
+void mumode_destroy(mm_op* op);
+
+/* The extracted maximum a_max and the scaling exponent s used for factor c = 1 along
+ * axis mu (diagnostics). */
+mm_status mumode_info(const mm_op* op, double* a_max, int* squarings);
+
+/* Copy the FP64 factor exp(c tau A_mu) for quadrature index j (j = 0: c = 1; j >= 1:
+ * c = theta_j) of axis mu into host memory (n_mu*n_mu values, row-major E[row][col]). */
+mm_status mumode_get_factor(const mm_op* op, int mu, int j, double* host_out);
+
+/* Remainder (eq. (eq:nonlin)) on the grid, flux-form centred differences, face
+ * coefficient = mean of the two nodal values, zero Dirichlet ghosts:
+ *   g(u) = sum_mu [(abar+ - lambda a_max)(u+ - u) - (abar- - lambda a_max)(u - u-)]/h_mu^2
+ *        + sum_mu (beta_mu - beta_bar_mu)(u+ - u-)/(2 h_mu) + r(u).
+ * F (nullable) receives the unsplit right-hand side F(u) = A u + g(u).
+ * u, g, F: device, n1*n2*n3 values; must not alias. Enqueued on `stream`. */
+mm_status remainder_eval(mm_ctx* ctx, const mm_op* op, const double* u, double* g, double* F,
+                         void* stream);
+
+/* out = exp(c tau A) in with c = 1 (j = 0) or c = theta_j (j >= 1, MM_ERK only), as
+ * three (two) mu-mode passes in the op's precision. in/out: device, may alias. */
+mm_status mumode_expv(mm_ctx* ctx, const mm_op* op, int j, const double* in, double* out,
+                      void* stream);
+
+/* out = sum_j w_j exp(theta_j tau A) in, the q-node quadrature phi1 action (MM_ERK). */
+mm_status mumode_phi1v(mm_ctx* ctx, const mm_op* op, const double* in, double* out, void* stream);
+
+/* Advance u (device, in place) by nsteps Lawson steps (family MM_LAWSON). */
+mm_status lawson_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* stream);
+
+/* Advance u (device, in place) by nsteps ERK steps (family MM_ERK). */
+mm_status erk_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* stream);
+
+/* Wait for the op's work on `stream` and report MM_EUNSTABLE if any step produced a
+ * non-finite value since the op was created (the flag is sticky). */
+mm_status mm_check(mm_ctx* ctx, const mm_op* op, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Serving: a request loop on its own host thread and HIP stream. Requests that arrive
+ * while others run are admitted as slots and device memory allow; admitted requests
+ * advance one Lawson2b step per round, so their kernels interleave on the device;
+ * finished requests are retired and their memory released.
+ * ------------------------------------------------------------------------------- */
+typedef struct {
+  int d;
+  int n[3];
+  const double* a;       /* HOST, nodal coefficient incl. boundary (copied)           */
+  const double* u0;      /* HOST, interior initial data (copied)                      */
+  double beta[3];
+  double r[4];
+  double lambda;
+  double beta_bar[3];
+  double tau;
+  int steps;
+  int prec;              /* mm_prec                                                   */
+} mm_request;
+
+typedef struct {
+  double t_submit;       /* seconds on the server clock                               */
+  double t_admit;
+  double t_done;
+  int64_t bytes;         /* device footprint charged at admission                     */
+  int steps;
+  int status;            /* mm_status of the solve                                    */
+} mm_stats;
+
+/* max_active: concurrent solves on the device; hbm_budget: bytes the active solves may
+ * hold (0 = 90% of free device memory at creation). */
+mm_status mm_server_create(int device, int max_active, int64_t hbm_budget, mm_server** out);
+void mm_server_destroy(mm_server* srv);
+/* Copy the request in and queue it; returns its id. MM_ENOMEM if the request alone
+ * exceeds the budget, MM_EINVAL for a malformed request. */
+mm_status solve_submit(mm_server* srv, const mm_request* req, uint64_t* id);
+/* MM_NOT_READY while queued or running; otherwise the request's final status. On
+ * MM_OK the solution is copied to u_out (HOST, may be NULL) and stats filled (may be
+ * NULL); the request is forgotten after a non-NOT_READY return. */
+mm_status solve_poll(mm_server* srv, uint64_t id, double* u_out, mm_stats* stats);
+/* Seconds on the server clock (same clock as mm_stats). */
+double mm_server_clock(const mm_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MUMODE_H */

@@ -1,0 +1,280 @@
+"""Python binding of the mu-mode exponential-integrator library (libmumode.so, gfx950).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of the
+shared library behind the C ABI declared in include/mumode.h. PyTorch is used for
+device memory (tensors) and streams; nothing here computes on grid data, and there
+is no CPU fallback -- importing the binding raises if the library is missing.
+
+Names follow the C ABI: mumode_setup, remainder_eval, mumode_expv, mumode_phi1v,
+lawson_step, erk_step, mm_check, solve_submit, solve_poll.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, Structure, byref, c_char_p, c_double, c_int, c_int64, c_uint64, c_void_p
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmumode.so")
+
+MM_OK, MM_NOT_READY = 0, 1
+MM_EINVAL, MM_ENOMEM, MM_EDEVICE, MM_EUNSTABLE, MM_EBUSY, MM_ENOTFOUND = -1, -2, -3, -4, -5, -6
+MM_FP64, MM_FP32, MM_BF16X3, MM_BF16X6 = 0, 1, 2, 3
+MM_LAWSON, MM_ERK = 0, 1
+MM_LAWSON_EULER, MM_LAWSON2B = 0, 1
+MM_ETD2RK, MM_ERK2P1 = 0, 1
+
+PRECISIONS = {"fp64": MM_FP64, "fp32": MM_FP32, "bf16x3": MM_BF16X3, "bf16x6": MM_BF16X6}
+SCHEMES = {"le": (MM_LAWSON, MM_LAWSON_EULER), "l2b": (MM_LAWSON, MM_LAWSON2B),
+           "etd2rk": (MM_ERK, MM_ETD2RK), "erk2p1f": (MM_ERK, MM_ERK2P1)}
+STATUS = {0: "MM_OK", 1: "MM_NOT_READY", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EDEVICE",
+          -4: "MM_EUNSTABLE", -5: "MM_EBUSY", -6: "MM_ENOTFOUND"}
+
+# every entry point the header declares
+EXPORTS = ("mm_ctx_create", "mm_ctx_destroy", "mm_last_error", "mm_version", "mumode_setup",
+           "mumode_destroy", "mumode_info", "mumode_get_factor", "remainder_eval", "mumode_expv",
+           "mumode_phi1v", "lawson_step", "erk_step", "mm_check", "mm_server_create",
+           "mm_server_destroy", "solve_submit", "solve_poll", "mm_server_clock")
+
+
+class MMProblem(Structure):
+    _fields_ = [("d", c_int), ("n", c_int * 3), ("a", c_void_p), ("beta", c_double * 3),
+                ("r", c_double * 4), ("lam", c_double), ("beta_bar", c_double * 3)]
+
+
+class MMRequest(Structure):
+    _fields_ = [("d", c_int), ("n", c_int * 3), ("a", c_void_p), ("u0", c_void_p),
+                ("beta", c_double * 3), ("r", c_double * 4), ("lam", c_double),
+                ("beta_bar", c_double * 3), ("tau", c_double), ("steps", c_int), ("prec", c_int)]
+
+
+class MMStats(Structure):
+    _fields_ = [("t_submit", c_double), ("t_admit", c_double), ("t_done", c_double),
+                ("bytes", c_int64), ("steps", c_int), ("status", c_int)]
+
+
+class MumodeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmumode.so and declare its signatures. Raises if it is not built."""
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_2303_15861_amd.build "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i, d = c_void_p, c_int, c_double
+    sig = {
+        "mm_ctx_create": (i, [i, POINTER(vp)]),
+        "mm_ctx_destroy": (None, [vp]),
+        "mm_last_error": (c_char_p, [vp]),
+        "mm_version": (c_char_p, []),
+        "mumode_setup": (i, [vp, POINTER(MMProblem), d, i, i, i, i, i, POINTER(vp)]),
+        "mumode_destroy": (None, [vp]),
+        "mumode_info": (i, [vp, POINTER(c_double), POINTER(c_int)]),
+        "mumode_get_factor": (i, [vp, i, i, vp]),
+        "remainder_eval": (i, [vp, vp, vp, vp, vp, vp]),
+        "mumode_expv": (i, [vp, vp, i, vp, vp, vp]),
+        "mumode_phi1v": (i, [vp, vp, vp, vp, vp]),
+        "lawson_step": (i, [vp, vp, vp, i, vp]),
+        "erk_step": (i, [vp, vp, vp, i, vp]),
+        "mm_check": (i, [vp, vp, vp]),
+        "mm_server_create": (i, [i, i, c_int64, POINTER(vp)]),
+        "mm_server_destroy": (None, [vp]),
+        "solve_submit": (i, [vp, POINTER(MMRequest), POINTER(c_uint64)]),
+        "solve_poll": (i, [vp, c_uint64, vp, POINTER(MMStats)]),
+        "mm_server_clock": (d, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_LIB: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("grid tensors must be contiguous float64 tensors on the GPU")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Context:
+    """An mm_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        self._h = c_void_p()
+        self.device = device
+        st = lib().mm_ctx_create(device, byref(self._h))
+        if st != MM_OK:
+            raise MumodeError(st, f"mm_ctx_create(device={device}) failed")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def error(self) -> str:
+        return lib().mm_last_error(self._h).decode()
+
+    def check(self, st: int, what: str):
+        if st != MM_OK:
+            raise MumodeError(st, f"{what}: {self.error()}")
+
+    def close(self):
+        if self._h:
+            lib().mm_ctx_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Operator:
+    """An mm_op: factors and scratch for one problem, time step and scheme."""
+
+    def __init__(self, ctx: Context, handle: c_void_p, prob, scheme: str, prec: str, q: int):
+        self.ctx, self._h = ctx, handle
+        self.d, self.n = prob.d, tuple(prob.n)
+        self.scheme, self.prec, self.q = scheme, prec, q
+        self.family = SCHEMES[scheme][0]
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def shape(self):
+        return tuple(reversed(self.n))
+
+    def info(self):
+        am = c_double()
+        sq = (c_int * 3)()
+        lib().mumode_info(self._h, byref(am), sq)
+        return am.value, tuple(sq[: self.d])
+
+    def factor(self, mu: int, j: int = 0):
+        import numpy as np
+        n = self.n[mu]
+        out = np.empty((n, n), dtype=np.float64)
+        st = lib().mumode_get_factor(self._h, mu, j, out.ctypes.data)
+        self.ctx.check(st, "mumode_get_factor")
+        return out
+
+    def close(self):
+        if self._h:
+            _torch().cuda.synchronize(self.ctx.device)
+            lib().mumode_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mumode_setup(ctx: Context, d: int, n: Sequence[int], a, beta: Sequence[float], r: Sequence[float],
+                 tau: float, scheme: str = "l2b", prec: str = "fp64", q: int = 4, lam: float = 1.0,
+                 beta_bar: Optional[Sequence[float]] = None) -> Operator:
+    """Build the extracted operator and its factors on the device (see mumode.h)."""
+    prob = MMProblem()
+    prob.d = d
+    for i in range(3):
+        prob.n[i] = int(n[i]) if i < d else 1
+        prob.beta[i] = float(beta[i]) if i < d else 0.0
+        prob.beta_bar[i] = float(beta_bar[i]) if (beta_bar is not None and i < d) else 0.0
+    for i in range(4):
+        prob.r[i] = float(r[i])
+    prob.lam = float(lam)
+    prob.a = _ptr(a)
+    _torch().cuda.current_stream(a.device).synchronize()   # a must be complete
+    fam, sch = SCHEMES[scheme]
+    h = c_void_p()
+    st = lib().mumode_setup(ctx.handle, byref(prob), float(tau), fam, sch, int(q), PRECISIONS[prec], 0,
+                            byref(h))
+    ctx.check(st, "mumode_setup")
+    return Operator(ctx, h, prob, scheme, prec, q if fam == MM_ERK else 0)
+
+
+def remainder_eval(op: Operator, u, g, F=None, stream=None):
+    st = lib().remainder_eval(op.ctx.handle, op.handle, _ptr(u), _ptr(g), _ptr(F), _stream(stream))
+    op.ctx.check(st, "remainder_eval")
+
+
+def mumode_expv(op: Operator, inp, out, j: int = 0, stream=None):
+    st = lib().mumode_expv(op.ctx.handle, op.handle, int(j), _ptr(inp), _ptr(out), _stream(stream))
+    op.ctx.check(st, "mumode_expv")
+
+
+def mumode_phi1v(op: Operator, inp, out, stream=None):
+    st = lib().mumode_phi1v(op.ctx.handle, op.handle, _ptr(inp), _ptr(out), _stream(stream))
+    op.ctx.check(st, "mumode_phi1v")
+
+
+def lawson_step(op: Operator, u, nsteps: int, stream=None):
+    st = lib().lawson_step(op.ctx.handle, op.handle, _ptr(u), int(nsteps), _stream(stream))
+    op.ctx.check(st, "lawson_step")
+
+
+def erk_step(op: Operator, u, nsteps: int, stream=None):
+    st = lib().erk_step(op.ctx.handle, op.handle, _ptr(u), int(nsteps), _stream(stream))
+    op.ctx.check(st, "erk_step")
+
+
+def step(op: Operator, u, nsteps: int, stream=None):
+    """lawson_step or erk_step according to the operator's family."""
+    if op.family == MM_LAWSON:
+        lawson_step(op, u, nsteps, stream)
+    else:
+        erk_step(op, u, nsteps, stream)
+
+
+def mm_check(op: Operator, stream=None) -> int:
+    """Synchronise the stream; returns MM_OK or MM_EUNSTABLE (raises on other errors)."""
+    st = lib().mm_check(op.ctx.handle, op.handle, _stream(stream))
+    if st not in (MM_OK, MM_EUNSTABLE):
+        op.ctx.check(st, "mm_check")
+    return st
+
+
+def setup_problem(ctx: Context, prob, prec: str = "fp64", scheme: Optional[str] = None) -> Operator:
+    """mumode_setup for a ``synth.Problem`` (copies its coefficient to the device)."""
+    torch = _torch()
+    a = torch.from_numpy(prob.a).to(device=f"cuda:{ctx.device}")
+    op = mumode_setup(ctx, prob.d, prob.n, a, prob.beta, prob.r, prob.tau, scheme or prob.scheme, prec,
+                      prob.q, prob.lam, prob.beta_bar)
+    return op
+
+
+from .server import Server, solve_poll, solve_submit  # noqa: E402,F401

@@ -1,0 +1,769 @@
+// Host side of the C ABI: operator setup (extraction, on-device Pade factors),
+// the remainder evaluation, exp / phi1 actions and the Lawson / ERK step sequences.
+// Everything that computes on grid data runs in the kernels of contract.hip and
+// stencil.hip; this file only validates arguments, allocates, and enqueues.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+
+#include "mm_internal.h"
+
+using namespace mm;
+
+namespace {
+
+void set_err(mm_ctx* ctx, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->last_error = buf;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      set_err(ctx, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return MM_EDEVICE;                                                                   \
+    }                                                                                      \
+  } while (0)
+
+// q-point Gauss-Legendre rule on [0, 1]: Newton iteration on the Legendre polynomial
+// P_q (three-term recurrence) from the Chebyshev-like initial guesses.
+void gauss_legendre(int q, double* theta, double* w) {
+  for (int i = 0; i < q; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (q + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= q; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (q == 1) { p1 = x; p0 = 1.0; }
+      dp = q * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= q; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    if (q == 1) { p1 = x; p0 = 1.0; }
+    dp = q * (x * p1 - p0) / (x * x - 1.0);
+    theta[q - 1 - i] = 0.5 * (x + 1.0);
+    w[q - 1 - i] = 1.0 / ((1.0 - x * x) * dp * dp);  // 2/((1-x^2)P'^2) halved for [0,1]
+  }
+}
+
+hipError_t gemm_sq(int n, const double* X, const double* Y, double* Z, hipStream_t s) {
+  GemmArgs g{};
+  g.A[0] = X;
+  g.B[0] = Y;
+  g.C[0] = Z;
+  g.Cadd[0] = nullptr;
+  g.M = g.N = g.K = n;
+  g.lda = g.ldb = g.ldc = n;
+  g.inner = 1;
+  g.groups = 1;
+  g.b_trans = 1;
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  return launch_gemm(MM_FP64, g, s);
+}
+
+// exp(T) for the n x n tridiagonal Toeplitz T = tridiag(sub, diag, sup) by the [13/13]
+// Pade approximant with scaling and squaring (Higham, SIAM J. Matrix Anal. Appl. 26(4),
+// 2005): s = max(0, ceil(log2(||T||_1 / theta_13))), X = r_13(T/2^s), then s squarings.
+// The Pade numerator coefficients are b_j = (26 - j)! / (j! (13 - j)!).
+mm_status pade_expm(mm_ctx* ctx, int n, double sub, double diag, double sup, double* out, int* s_out,
+                    double* ws) {
+  hipStream_t st = ctx->stream;
+  double nrm = std::fabs(diag);
+  if (n == 2) nrm += std::fmax(std::fabs(sub), std::fabs(sup));
+  if (n >= 3) nrm += std::fabs(sub) + std::fabs(sup);
+  const double theta13 = 5.371920351148152;
+  int s = 0;
+  if (nrm > theta13) s = (int)std::ceil(std::log2(nrm / theta13));
+  const double sc = std::ldexp(1.0, -s);
+  double b[14];
+  for (int j = 0; j <= 13; ++j) {
+    unsigned __int128 num = 1;
+    for (int k = 13 - j + 1; k <= 26 - j; ++k) num *= (unsigned __int128)k;  // (26-j)!/(13-j)!
+    unsigned __int128 den = 1;
+    for (int k = 2; k <= j; ++k) den *= (unsigned __int128)k;
+    b[j] = (double)(num / den);
+  }
+  const int64_t nn = (int64_t)n * n;
+  double *A = ws, *A2 = ws + nn, *A4 = ws + 2 * nn, *A6 = ws + 3 * nn, *T1 = ws + 4 * nn, *U = ws + 5 * nn,
+         *V = ws + 6 * nn;
+  HIPCHK(ctx, launch_build_tridiag(A, n, sub * sc, diag * sc, sup * sc, st));
+  HIPCHK(ctx, gemm_sq(n, A, A, A2, st));
+  HIPCHK(ctx, gemm_sq(n, A2, A2, A4, st));
+  HIPCHK(ctx, gemm_sq(n, A4, A2, A6, st));
+  // U = A [A6 (b13 A6 + b11 A4 + b9 A2) + b7 A6 + b5 A4 + b3 A2 + b1 I]
+  HIPCHK(ctx, launch_combo(T1, n, b[13], A6, b[11], A4, b[9], A2, 0.0, nullptr, 0.0, st));
+  HIPCHK(ctx, gemm_sq(n, A6, T1, V, st));
+  HIPCHK(ctx, launch_combo(V, n, 1.0, V, b[7], A6, b[5], A4, b[3], A2, b[1], st));
+  HIPCHK(ctx, gemm_sq(n, A, V, U, st));
+  // V = A6 (b12 A6 + b10 A4 + b8 A2) + b6 A6 + b4 A4 + b2 A2 + b0 I
+  HIPCHK(ctx, launch_combo(T1, n, b[12], A6, b[10], A4, b[8], A2, 0.0, nullptr, 0.0, st));
+  HIPCHK(ctx, gemm_sq(n, A6, T1, V, st));
+  HIPCHK(ctx, launch_combo(V, n, 1.0, V, b[6], A6, b[4], A4, b[2], A2, b[0], st));
+  // (V - U) X = (V + U): P in A2, Q in A4
+  HIPCHK(ctx, launch_combo(A2, n, 1.0, V, 1.0, U, 0.0, nullptr, 0.0, nullptr, 0.0, st));
+  HIPCHK(ctx, launch_combo(A4, n, 1.0, V, -1.0, U, 0.0, nullptr, 0.0, nullptr, 0.0, st));
+  HIPCHK(ctx, launch_lu_solve(A4, A2, n, 1, st));
+  double* X = A2;
+  double* Y = A6;
+  for (int i = 0; i < s; ++i) {
+    HIPCHK(ctx, gemm_sq(n, X, X, Y, st));
+    double* t = X;
+    X = Y;
+    Y = t;
+  }
+  HIPCHK(ctx, hipMemcpyAsync(out, X, nn * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (s_out) *s_out = s;
+  return MM_OK;
+}
+
+template <typename T>
+mm_status dev_alloc(mm_op* op, T** p, int64_t count) {
+  const size_t bytes = (size_t)count * sizeof(T);
+  hipError_t e = hipMalloc((void**)p, bytes);
+  if (e != hipSuccess) {
+    set_err(op->ctx, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    *p = nullptr;
+    return MM_ENOMEM;
+  }
+  op->bytes += (int64_t)bytes;
+  return MM_OK;
+}
+
+int last_axis(const mm_op* op) { return op->d - 1; }
+
+// ---------------------------------------------------------------- mode passes
+// mode 1: C (rows x n1) = A (rows x n1) . E1^T, per group (input, factor, output)
+hipError_t pass_mode1(const mm_op* op, int groups, const double* const* in, const double* const* E,
+                      double* const* out, int rows, hipStream_t s) {
+  GemmArgs g{};
+  for (int i = 0; i < groups; ++i) {
+    g.A[i] = in[i];
+    g.B[i] = E[i];
+    g.C[i] = out[i];
+    g.Cadd[i] = nullptr;
+  }
+  g.M = rows;
+  g.N = op->n[0];
+  g.K = op->n[0];
+  g.lda = g.ldb = g.ldc = op->n[0];
+  g.inner = 1;
+  g.groups = groups;
+  g.b_trans = 0;
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  return launch_gemm(op->prec, g, s);
+}
+
+// mode 2 of a 3D grid: per x3-slab (n2 x n1), C = E2 . slab, `slabs` slabs per group
+hipError_t pass_mode2(const mm_op* op, int groups, const double* const* E, const double* const* in,
+                      double* const* out, int slabs, hipStream_t s) {
+  GemmArgs g{};
+  for (int i = 0; i < groups; ++i) {
+    g.A[i] = E[i];
+    g.B[i] = in[i];
+    g.C[i] = out[i];
+    g.Cadd[i] = nullptr;
+  }
+  g.M = op->n[1];
+  g.N = op->n[0];
+  g.K = op->n[1];
+  g.lda = op->n[1];
+  g.ldb = op->n[0];
+  g.ldc = op->n[0];
+  g.inner = slabs;
+  g.sA = 0;
+  g.sB = g.sC = (int64_t)op->n[0] * op->n[1];
+  g.groups = groups;
+  g.b_trans = 1;
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  return launch_gemm(op->prec, g, s);
+}
+
+// last mode: C (nl x P) = alpha * F (nl x K) . B (K x P) + beta * add, K = kmul * nl,
+// P = dof / nl; `inner` stacked vectors of stride dof (same factor).
+hipError_t pass_last(const mm_op* op, const double* F, int kmul, const double* in, double* out,
+                     const double* add, double alpha, double beta, int inner, hipStream_t s) {
+  const int nl = op->n[last_axis(op)];
+  const int P = (int)(op->dof / nl);
+  GemmArgs g{};
+  g.A[0] = F;
+  g.B[0] = in;
+  g.C[0] = out;
+  g.Cadd[0] = add;
+  g.M = nl;
+  g.N = P;
+  g.K = kmul * nl;
+  g.lda = kmul * nl;
+  g.ldb = P;
+  g.ldc = P;
+  g.inner = inner;
+  g.sA = 0;
+  g.sB = g.sC = op->dof;
+  g.groups = 1;
+  g.b_trans = 1;
+  g.alpha = alpha;
+  g.beta = beta;
+  return launch_gemm(op->prec, g, s);
+}
+
+const double* factor(const mm_op* op, int mu, int j) {
+  return op->fac[mu] + (int64_t)j * op->n[mu] * op->n[mu];
+}
+
+// out = exp(c_j tau A) in for `nvec` stacked vectors (stride dof): in -> t0 [-> t1] -> out
+hipError_t exp_action(const mm_op* op, int j, const double* in, double* out, int nvec, double* t0,
+                      double* t1, hipStream_t s) {
+  const double* E1 = factor(op, 0, j);
+  double* o1 = (op->d == 3) ? t0 : t0;
+  hipError_t e = pass_mode1(op, 1, &in, &E1, &o1, (int)(op->dof / op->n[0]) * nvec, s);
+  if (e != hipSuccess) return e;
+  if (op->d == 3) {
+    const double* E2 = factor(op, 1, j);
+    const double* i2 = t0;
+    e = pass_mode2(op, 1, &E2, &i2, &t1, op->n[2] * nvec, s);
+    if (e != hipSuccess) return e;
+    return pass_last(op, factor(op, 2, j), 1, t1, out, nullptr, 1.0, 0.0, nvec, s);
+  }
+  return pass_last(op, factor(op, 1, j), 1, t0, out, nullptr, 1.0, 0.0, nvec, s);
+}
+
+// out = stacked-last-factor contraction over G groups: group g applies modes 1..d-1 with
+// factor index fidx[g] to input ins[g]; the last mode sums the groups with the
+// stacked factor F3 (nl x G*nl) and adds beta*add.
+hipError_t grouped_action(const mm_op* op, int G, const double* const* ins, const int* fidx,
+                          const double* F3, double* out, const double* add, double beta, double* t0,
+                          double* t1, hipStream_t s) {
+  const double* E1[kMaxGroups];
+  double* o1[kMaxGroups];
+  for (int g = 0; g < G; ++g) {
+    E1[g] = factor(op, 0, fidx[g]);
+    o1[g] = t0 + (int64_t)g * op->dof;
+  }
+  hipError_t e = pass_mode1(op, G, ins, E1, o1, (int)(op->dof / op->n[0]), s);
+  if (e != hipSuccess) return e;
+  if (op->d == 3) {
+    const double* E2[kMaxGroups];
+    const double* i2[kMaxGroups];
+    double* o2[kMaxGroups];
+    for (int g = 0; g < G; ++g) {
+      E2[g] = factor(op, 1, fidx[g]);
+      i2[g] = t0 + (int64_t)g * op->dof;
+      o2[g] = t1 + (int64_t)g * op->dof;
+    }
+    e = pass_mode2(op, G, E2, i2, o2, op->n[2], s);
+    if (e != hipSuccess) return e;
+    return pass_last(op, F3, G, t1, out, add, 1.0, beta, 1, s);
+  }
+  return pass_last(op, F3, G, t0, out, add, 1.0, beta, 1, s);
+}
+
+StencilArgs stencil_args(const mm_op* op, const double* u, bool full) {
+  StencilArgs a{};
+  a.u = u;
+  a.a = op->a;
+  a.n1 = op->n[0];
+  a.n2 = op->n[1];
+  a.n3 = (op->d == 3) ? op->n[2] : 1;
+  for (int mu = 0; mu < 3; ++mu) {
+    const double h = 1.0 / (op->n[mu] + 1);
+    a.ih2[mu] = 1.0 / (h * h);
+    const double b = full ? op->beta[mu] : op->beta[mu] - op->beta_bar[mu];
+    a.cadv[mu] = (mu < op->d) ? b / (2.0 * h) : 0.0;
+  }
+  a.lam_amax = full ? 0.0 : op->lam * op->a_max;
+  a.r0 = op->r[0];
+  a.r1 = op->r[1];
+  a.r2 = op->r[2];
+  a.r3 = op->r[3];
+  a.c0 = 1.0;
+  a.c1 = 1.0;
+  a.flag = op->flag;
+  return a;
+}
+
+mm_status check_op(mm_ctx* ctx, const mm_op* op) {
+  if (!ctx) return MM_EINVAL;
+  if (!op) {
+    set_err(ctx, "null op");
+    return MM_EINVAL;
+  }
+  if (op->ctx != ctx) {
+    set_err(ctx, "op belongs to another context");
+    return MM_EINVAL;
+  }
+  return MM_OK;
+}
+
+}  // namespace
+
+// ======================================================================= C ABI
+extern "C" {
+
+const char* mm_version(void) { return "mumode-gfx950 1.0"; }
+
+mm_status mm_ctx_create(int device, mm_ctx** out) {
+  if (!out) return MM_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return MM_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return MM_EDEVICE;
+  mm_ctx* ctx = new mm_ctx();
+  ctx->device = device;
+  if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete ctx;
+    return MM_EDEVICE;
+  }
+  ctx->reduce_parts = 1024;
+  if (hipMalloc((void**)&ctx->reduce_buf, (ctx->reduce_parts + 1) * sizeof(double)) != hipSuccess) {
+    hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return MM_ENOMEM;
+  }
+  *out = ctx;
+  return MM_OK;
+}
+
+void mm_ctx_destroy(mm_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  if (ctx->reduce_buf) hipFree(ctx->reduce_buf);
+  if (ctx->stream) hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+const char* mm_last_error(const mm_ctx* ctx) {
+  if (!ctx) return "null context";
+  return ctx->last_error.c_str();
+}
+
+void mumode_destroy(mm_op* op) {
+  if (!op) return;
+  if (op->ctx) {
+    hipSetDevice(op->ctx->device);
+    hipStreamSynchronize(op->ctx->stream);
+  }
+  if (op->a) hipFree(op->a);
+  for (size_t i = 0; i < op->fac.size(); ++i)
+    if (op->fac_owned[i] && op->fac[i]) hipFree(op->fac[i]);
+  if (op->f3_stage1) hipFree(op->f3_stage1);
+  if (op->f3_stage2) hipFree(op->f3_stage2);
+  if (op->f3_phi) hipFree(op->f3_phi);
+  for (int i = 0; i < 6; ++i)
+    if (op->buf[i]) hipFree(op->buf[i]);
+  if (op->flag) hipFree(op->flag);
+  delete op;
+}
+
+mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int family, int scheme,
+                       int quad_nodes, int prec, int slices, mm_op** out) {
+  if (!ctx) return MM_EINVAL;
+  if (!prob || !out) {
+    set_err(ctx, "null problem or output pointer");
+    return MM_EINVAL;
+  }
+  *out = nullptr;
+  if (prob->d != 2 && prob->d != 3) {
+    set_err(ctx, "d must be 2 or 3 (got %d)", prob->d);
+    return MM_EINVAL;
+  }
+  for (int mu = 0; mu < prob->d; ++mu)
+    if (prob->n[mu] < 1 || prob->n[mu] > 4096) {
+      set_err(ctx, "n[%d] = %d out of range 1..4096", mu, prob->n[mu]);
+      return MM_EINVAL;
+    }
+  if (!(tau > 0.0) || !std::isfinite(tau)) {
+    set_err(ctx, "tau must be finite and positive");
+    return MM_EINVAL;
+  }
+  if (!prob->a) {
+    set_err(ctx, "null diffusion coefficient");
+    return MM_EINVAL;
+  }
+  if (family != MM_LAWSON && family != MM_ERK) {
+    set_err(ctx, "unknown family %d", family);
+    return MM_EINVAL;
+  }
+  if (family == MM_LAWSON && scheme != MM_LAWSON_EULER && scheme != MM_LAWSON2B) {
+    set_err(ctx, "unknown Lawson scheme %d", scheme);
+    return MM_EINVAL;
+  }
+  if (family == MM_ERK && scheme != MM_ETD2RK && scheme != MM_ERK2P1) {
+    set_err(ctx, "unknown ERK scheme %d", scheme);
+    return MM_EINVAL;
+  }
+  if (family == MM_ERK && (quad_nodes < 1 || quad_nodes > kMaxGroups - 1)) {
+    set_err(ctx, "quad_nodes must be 1..%d", kMaxGroups - 1);
+    return MM_EINVAL;
+  }
+  if (prec < MM_FP64 || prec > MM_BF16X6) {
+    set_err(ctx, "unknown precision %d", prec);
+    return MM_EINVAL;
+  }
+  if (!std::isfinite(prob->lambda) || prob->lambda < 0.0) {
+    set_err(ctx, "lambda must be finite and >= 0");
+    return MM_EINVAL;
+  }
+  (void)slices;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+
+  mm_op* op = new mm_op();
+  op->ctx = ctx;
+  op->d = prob->d;
+  for (int mu = 0; mu < 3; ++mu) {
+    op->n[mu] = (mu < prob->d) ? prob->n[mu] : 1;
+    op->beta[mu] = (mu < prob->d) ? prob->beta[mu] : 0.0;
+    op->beta_bar[mu] = (mu < prob->d) ? prob->beta_bar[mu] : 0.0;
+  }
+  for (int i = 0; i < 4; ++i) op->r[i] = prob->r[i];
+  op->lam = prob->lambda;
+  op->tau = tau;
+  op->family = family;
+  op->scheme = scheme;
+  op->q = (family == MM_ERK) ? quad_nodes : 0;
+  op->prec = prec;
+  op->dof = (int64_t)op->n[0] * op->n[1] * op->n[2];
+  int64_t na = 1;
+  for (int mu = 0; mu < op->d; ++mu) na *= op->n[mu] + 2;
+
+  auto fail = [&](mm_status s) {
+    mumode_destroy(op);
+    return s;
+  };
+  mm_status rc;
+  if ((rc = dev_alloc(op, &op->a, na)) != MM_OK) return fail(rc);
+  if (hipMemcpyAsync(op->a, prob->a, na * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) {
+    set_err(ctx, "copy of the diffusion coefficient failed (device pointer expected)");
+    return fail(MM_EINVAL);
+  }
+  if ((rc = dev_alloc(op, &op->flag, 1)) != MM_OK) return fail(rc);
+  if (hipMemsetAsync(op->flag, 0, sizeof(int), st) != hipSuccess) return fail(MM_EDEVICE);
+
+  // a_max = max over all nodes (eq. (eq:amaxbeta))
+  double amax = 0.0;
+  if (launch_max_reduce(op->a, na, ctx->reduce_buf, ctx->reduce_parts, ctx->reduce_buf + ctx->reduce_parts,
+                        st) != hipSuccess ||
+      hipMemcpyAsync(&amax, ctx->reduce_buf + ctx->reduce_parts, sizeof(double), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    set_err(ctx, "a_max reduction failed");
+    return fail(MM_EDEVICE);
+  }
+  if (!std::isfinite(amax)) {
+    set_err(ctx, "diffusion coefficient is not finite");
+    return fail(MM_EINVAL);
+  }
+  op->a_max = amax;
+
+  // coefficients c of the factors exp(c tau A_mu): c_0 = 1, c_j = theta_j
+  const int nf = 1 + op->q;
+  double cs[kMaxGroups];
+  cs[0] = 1.0;
+  if (op->q > 0) {
+    gauss_legendre(op->q, op->theta + 1, op->weight + 1);
+    for (int j = 1; j <= op->q; ++j) cs[j] = op->theta[j];
+  }
+  op->theta[0] = 1.0;
+  op->weight[0] = 1.0;
+
+  int nmax = 0;
+  for (int mu = 0; mu < op->d; ++mu) nmax = std::max(nmax, op->n[mu]);
+  double* ws = nullptr;
+  if (hipMalloc((void**)&ws, (size_t)7 * nmax * nmax * sizeof(double)) != hipSuccess) {
+    set_err(ctx, "Pade workspace allocation failed");
+    return fail(MM_ENOMEM);
+  }
+  op->fac.assign(op->d, nullptr);
+  op->fac_owned.assign(op->d, false);
+  for (int mu = 0; mu < op->d; ++mu) {
+    int same = -1;
+    for (int nu = 0; nu < mu; ++nu)
+      if (op->n[nu] == op->n[mu] && op->beta_bar[nu] == op->beta_bar[mu]) same = nu;
+    if (same >= 0) {
+      op->fac[mu] = op->fac[same];
+      op->squarings[mu] = op->squarings[same];
+      continue;
+    }
+    const int n = op->n[mu];
+    if ((rc = dev_alloc(op, &op->fac[mu], (int64_t)nf * n * n)) != MM_OK) {
+      hipFree(ws);
+      return fail(rc);
+    }
+    op->fac_owned[mu] = true;
+    const double h = 1.0 / (n + 1);
+    const double diff = op->lam * op->a_max / (h * h);
+    const double adv = op->beta_bar[mu] / (2.0 * h);
+    for (int j = 0; j < nf; ++j) {
+      const double ct = cs[j] * tau;
+      int sq = 0;
+      rc = pade_expm(ctx, n, ct * (diff - adv), ct * (-2.0 * diff), ct * (diff + adv),
+                     op->fac[mu] + (int64_t)j * n * n, &sq, ws);
+      if (rc != MM_OK) {
+        hipFree(ws);
+        return fail(rc);
+      }
+      if (j == 0) op->squarings[mu] = sq;
+    }
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    hipFree(ws);
+    set_err(ctx, "factor setup failed on the device");
+    return fail(MM_EDEVICE);
+  }
+  hipFree(ws);
+
+  const int la = last_axis(op);
+  const int nl = op->n[la];
+  const int64_t dof = op->dof;
+  if (family == MM_ERK) {
+    const int q = op->q;
+    // stage 1: ETD2RK [E(1) | tau w_j E(theta_j)], ERK2P1 [tau w_j E(theta_j)]
+    const int g1 = (scheme == MM_ETD2RK) ? q + 1 : q;
+    if ((rc = dev_alloc(op, &op->f3_stage1, (int64_t)nl * g1 * nl)) != MM_OK) return fail(rc);
+    if ((rc = dev_alloc(op, &op->f3_stage2, (int64_t)nl * q * nl)) != MM_OK) return fail(rc);
+    if ((rc = dev_alloc(op, &op->f3_phi, (int64_t)nl * q * nl)) != MM_OK) return fail(rc);
+    int col = 0;
+    if (scheme == MM_ETD2RK) {
+      HIPCHK(ctx, launch_place_scaled(op->f3_stage1, g1 * nl, 0, factor(op, la, 0), nl, 1.0, st));
+      col = nl;
+    }
+    for (int j = 1; j <= q; ++j) {
+      HIPCHK(ctx, launch_place_scaled(op->f3_stage1, g1 * nl, col + (j - 1) * nl, factor(op, la, j), nl,
+                                      tau * op->weight[j], st));
+      HIPCHK(ctx, launch_place_scaled(op->f3_stage2, q * nl, (j - 1) * nl, factor(op, la, j), nl,
+                                      0.5 * tau * op->weight[j], st));
+      HIPCHK(ctx, launch_place_scaled(op->f3_phi, q * nl, (j - 1) * nl, factor(op, la, j), nl, op->weight[j], st));
+    }
+    // buffers: 0 g0, 1 T1 ((q+1) dof), 2 T2 ((q+1) dof), 3 U, 4 D, 5 F0 (ERK2P1)
+    const int64_t lens[6] = {dof, (q + 1) * dof, (q + 1) * dof, dof, dof, scheme == MM_ERK2P1 ? dof : 0};
+    for (int i = 0; i < 6; ++i) {
+      op->buf_len[i] = lens[i];
+      if (lens[i] > 0 && (rc = dev_alloc(op, &op->buf[i], lens[i])) != MM_OK) return fail(rc);
+    }
+  } else {
+    // buffers: 0 and 1 hold two stacked grid functions each
+    for (int i = 0; i < 2; ++i) {
+      op->buf_len[i] = 2 * dof;
+      if ((rc = dev_alloc(op, &op->buf[i], 2 * dof)) != MM_OK) return fail(rc);
+    }
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) {
+    set_err(ctx, "setup failed on the device");
+    return fail(MM_EDEVICE);
+  }
+  *out = op;
+  return MM_OK;
+}
+
+mm_status mumode_info(const mm_op* op, double* a_max, int* squarings) {
+  if (!op) return MM_EINVAL;
+  if (a_max) *a_max = op->a_max;
+  if (squarings)
+    for (int mu = 0; mu < op->d; ++mu) squarings[mu] = op->squarings[mu];
+  return MM_OK;
+}
+
+mm_status mumode_get_factor(const mm_op* op, int mu, int j, double* host_out) {
+  if (!op || !host_out || mu < 0 || mu >= op->d || j < 0 || j > op->q) return MM_EINVAL;
+  hipSetDevice(op->ctx->device);
+  const int64_t nn = (int64_t)op->n[mu] * op->n[mu];
+  if (hipMemcpy(host_out, factor(op, mu, j), nn * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return MM_EDEVICE;
+  return MM_OK;
+}
+
+mm_status remainder_eval(mm_ctx* ctx, const mm_op* op, const double* u, double* g, double* F, void* stream) {
+  mm_status rc = check_op(ctx, op);
+  if (rc != MM_OK) return rc;
+  if (!u || !g) {
+    set_err(ctx, "null u or g");
+    return MM_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  StencilArgs a = stencil_args(op, u, false);
+  a.out0 = g;
+  a.flag = nullptr;
+  HIPCHK(ctx, launch_stencil(op->d, a, s));
+  if (F) {
+    StencilArgs b = stencil_args(op, u, true);
+    b.out0 = F;
+    b.flag = nullptr;
+    HIPCHK(ctx, launch_stencil(op->d, b, s));
+  }
+  return MM_OK;
+}
+
+mm_status mumode_expv(mm_ctx* ctx, const mm_op* op, int j, const double* in, double* out, void* stream) {
+  mm_status rc = check_op(ctx, op);
+  if (rc != MM_OK) return rc;
+  if (!in || !out || j < 0 || j > op->q) {
+    set_err(ctx, "bad arguments to mumode_expv");
+    return MM_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  double* t0 = (op->family == MM_ERK) ? op->buf[1] : op->buf[0];
+  double* t1 = (op->family == MM_ERK) ? op->buf[2] : op->buf[1];
+  HIPCHK(ctx, exp_action(op, j, in, out, 1, t0, t1, s));
+  return MM_OK;
+}
+
+mm_status mumode_phi1v(mm_ctx* ctx, const mm_op* op, const double* in, double* out, void* stream) {
+  mm_status rc = check_op(ctx, op);
+  if (rc != MM_OK) return rc;
+  if (op->family != MM_ERK) {
+    set_err(ctx, "mumode_phi1v needs an MM_ERK operator (quadrature factors)");
+    return MM_EINVAL;
+  }
+  if (!in || !out) {
+    set_err(ctx, "null input or output");
+    return MM_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const double* ins[kMaxGroups];
+  int fidx[kMaxGroups];
+  for (int g = 0; g < op->q; ++g) {
+    ins[g] = in;
+    fidx[g] = g + 1;
+  }
+  HIPCHK(ctx, grouped_action(op, op->q, ins, fidx, op->f3_phi, out, nullptr, 0.0, op->buf[1], op->buf[2], s));
+  return MM_OK;
+}
+
+mm_status lawson_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* stream) {
+  mm_status rc = check_op(ctx, op);
+  if (rc != MM_OK) return rc;
+  if (op->family != MM_LAWSON) {
+    set_err(ctx, "lawson_step needs an MM_LAWSON operator");
+    return MM_EINVAL;
+  }
+  if (!u || nsteps < 0) {
+    set_err(ctx, "bad arguments to lawson_step");
+    return MM_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const double tau = op->tau;
+  const int64_t dof = op->dof;
+  double* b0 = op->buf[0];
+  double* b1 = op->buf[1];
+  for (int it = 0; it < nsteps; ++it) {
+    if (op->scheme == MM_LAWSON_EULER) {
+      // u+ = e^{tau A}(u + tau g(u))
+      StencilArgs a = stencil_args(op, u, false);
+      a.base0 = u;
+      a.c0 = tau;
+      a.out0 = b0;
+      HIPCHK(ctx, launch_stencil(op->d, a, s));
+      HIPCHK(ctx, exp_action(op, 0, b0, u, 1, b1, b0, s));
+    } else {
+      // v1 = u + tau g(u), v2 = u + tau/2 g(u); [U, W] = e^{tau A}[v1, v2]; u+ = W + tau/2 g(U)
+      StencilArgs a = stencil_args(op, u, false);
+      a.base0 = u;
+      a.c0 = tau;
+      a.out0 = b0;
+      a.base1 = u;
+      a.c1 = 0.5 * tau;
+      a.out1 = b0 + dof;
+      HIPCHK(ctx, launch_stencil(op->d, a, s));
+      double* res = (op->d == 3) ? b1 : b0;
+      HIPCHK(ctx, exp_action(op, 0, b0, res, 2, b1, b0, s));
+      StencilArgs c = stencil_args(op, res, false);
+      c.base0 = res + dof;
+      c.c0 = 0.5 * tau;
+      c.out0 = u;
+      HIPCHK(ctx, launch_stencil(op->d, c, s));
+    }
+  }
+  return MM_OK;
+}
+
+mm_status erk_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* stream) {
+  mm_status rc = check_op(ctx, op);
+  if (rc != MM_OK) return rc;
+  if (op->family != MM_ERK) {
+    set_err(ctx, "erk_step needs an MM_ERK operator");
+    return MM_EINVAL;
+  }
+  if (!u || nsteps < 0) {
+    set_err(ctx, "bad arguments to erk_step");
+    return MM_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const double tau = op->tau;
+  const int q = op->q;
+  double *g0 = op->buf[0], *T1 = op->buf[1], *T2 = op->buf[2], *U = op->buf[3], *D = op->buf[4],
+         *F0 = op->buf[5];
+  const double* ins[kMaxGroups];
+  int fidx[kMaxGroups];
+  for (int it = 0; it < nsteps; ++it) {
+    StencilArgs a = stencil_args(op, u, false);
+    a.out0 = g0;
+    HIPCHK(ctx, launch_stencil(op->d, a, s));
+    if (op->scheme == MM_ETD2RK) {
+      // U = e^{tau A} u + tau sum_j w_j e^{theta_j tau A} g0
+      ins[0] = u;
+      fidx[0] = 0;
+      for (int j = 1; j <= q; ++j) {
+        ins[j] = g0;
+        fidx[j] = j;
+      }
+      HIPCHK(ctx, grouped_action(op, q + 1, ins, fidx, op->f3_stage1, U, nullptr, 0.0, T1, T2, s));
+    } else {
+      // U = u + tau sum_j w_j e^{theta_j tau A} F(u)
+      StencilArgs f = stencil_args(op, u, true);
+      f.out0 = F0;
+      HIPCHK(ctx, launch_stencil(op->d, f, s));
+      for (int j = 0; j < q; ++j) {
+        ins[j] = F0;
+        fidx[j] = j + 1;
+      }
+      HIPCHK(ctx, grouped_action(op, q, ins, fidx, op->f3_stage1, U, u, 1.0, T1, T2, s));
+    }
+    // D = g(U) - g0;  u+ = U + tau/2 sum_j w_j e^{theta_j tau A} D
+    StencilArgs b = stencil_args(op, U, false);
+    b.sub = g0;
+    b.out0 = D;
+    HIPCHK(ctx, launch_stencil(op->d, b, s));
+    for (int j = 0; j < q; ++j) {
+      ins[j] = D;
+      fidx[j] = j + 1;
+    }
+    HIPCHK(ctx, grouped_action(op, q, ins, fidx, op->f3_stage2, u, U, 1.0, T1, T2, s));
+  }
+  return MM_OK;
+}
+
+mm_status mm_check(mm_ctx* ctx, const mm_op* op, void* stream) {
+  mm_status rc = check_op(ctx, op);
+  if (rc != MM_OK) return rc;
+  int flag = 0;
+  HIPCHK(ctx, hipStreamSynchronize((hipStream_t)stream));
+  HIPCHK(ctx, hipMemcpy(&flag, op->flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) {
+    set_err(ctx, "non-finite values in the solution");
+    return MM_EUNSTABLE;
+  }
+  return MM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Internal declarations shared by the HIP sources of the mu-mode library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mumode.h"
+
+namespace mm {
+
+constexpr int kMaxGroups = 8;   // quadrature nodes + 1
+
+// One batched/grouped GEMM  C[g][b] = alpha * A[g][b] . B[g][b]^T-or-not + beta * Cadd[g][b]
+// with row-major operands: A[m][k] at m*lda + k; C[m][n] at m*ldc + n;
+// B[n][k] at n*ldb + k (b_trans = 0) or at k*ldb + n (b_trans = 1).
+// Group g selects base pointers; the inner batch index b adds b*s{A,B,C}.
+struct GemmArgs {
+  const double* A[kMaxGroups];
+  const double* B[kMaxGroups];
+  double* C[kMaxGroups];
+  const double* Cadd[kMaxGroups];
+  int M, N, K;
+  int lda, ldb, ldc;
+  int inner;
+  int64_t sA, sB, sC;
+  int groups;
+  int b_trans;
+  double alpha, beta;
+  // filled by the launcher
+  int tiles_m, tiles_n, total, per_xcd;
+};
+
+// Stencil launch parameters (remainder g and fused stage updates).
+struct StencilArgs {
+  const double* u;      // input grid function
+  const double* a;      // nodal coefficient, (n+2)^d
+  int n1, n2, n3;       // n3 = 1 for d = 2
+  double ih2[3];        // 1/h_mu^2
+  double cadv[3];       // (beta - beta_bar)/(2 h)
+  double lam_amax;      // lambda * a_max (0 for the unsplit F)
+  double r0, r1, r2, r3;
+  const double* sub;    // nullable: s = g - sub
+  const double* base0;  // nullable
+  double c0;
+  double* out0;         // out0 = base0 + c0 * s
+  const double* base1;  // nullable
+  double c1;
+  double* out1;         // nullable: out1 = base1 + c1 * s
+  int* flag;            // nullable: set to 1 if out0 is not finite
+};
+
+hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s);
+hipError_t launch_stencil(int d, const StencilArgs& a, hipStream_t s);
+hipError_t launch_max_reduce(const double* x, int64_t n, double* partial, int nparts, double* out,
+                             hipStream_t s);
+hipError_t launch_build_tridiag(double* M, int n, double sub, double diag, double sup, hipStream_t s);
+// out = c0*X0 + c1*X1 + c2*X2 + c3*X3 + cI*I (any X may be null); n x n
+hipError_t launch_combo(double* out, int n, double c0, const double* X0, double c1, const double* X1,
+                        double c2, const double* X2, double c3, const double* X3, double cI,
+                        hipStream_t s);
+// out = X + s*Y elementwise over count values
+hipError_t launch_axpy(double* out, const double* X, double s, const double* Y, int64_t count,
+                       hipStream_t st);
+// Solve Q X = P in place (X overwrites P); Q is destroyed. `count` independent systems
+// with stride n*n each, one workgroup per system (Gaussian elimination, partial pivoting).
+hipError_t launch_lu_solve(double* Q, double* P, int n, int count, hipStream_t s);
+// dst[r][c0 + c] = w * src[r][c] for an n x n src into a row-major dst with leading dim ldd
+hipError_t launch_place_scaled(double* dst, int ldd, int col0, const double* src, int n, double w,
+                               hipStream_t s);
+hipError_t launch_fill(double* dst, double v, int64_t count, hipStream_t s);
+
+}  // namespace mm
+
+struct mm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;   // setup stream
+  std::string last_error;
+  double* reduce_buf = nullptr;   // partial maxima
+  int reduce_parts = 0;
+};
+
+struct mm_op {
+  mm_ctx* ctx = nullptr;
+  int d = 3;
+  int n[3] = {1, 1, 1};
+  int64_t dof = 0;
+  double tau = 0, lam = 1, a_max = 0;
+  double beta[3] = {0, 0, 0}, beta_bar[3] = {0, 0, 0}, r[4] = {0, 0, 0, 0};
+  int family = 0, scheme = 0, q = 0, prec = 0;
+  int squarings[3] = {0, 0, 0};
+  double theta[8] = {0}, weight[8] = {0};
+  // device memory owned by the op
+  double* a = nullptr;                 // nodal coefficient copy
+  std::vector<double*> fac;            // fac[mu] = (1 + q) stacked n_mu x n_mu FP64 factors
+  std::vector<bool> fac_owned;
+  double* f3_stage1 = nullptr;         // ERK: [E3(1) | tau w_j E3(theta_j)] or [tau w_j E3]
+  double* f3_stage2 = nullptr;         // ERK: [tau/2 w_j E3(theta_j)]
+  double* f3_phi = nullptr;            // [w_j E3(theta_j)] for mumode_phi1v
+  double* buf[6] = {nullptr};          // scratch
+  int64_t buf_len[6] = {0};
+  int* flag = nullptr;                 // sticky non-finite flag
+  int64_t bytes = 0;                   // device footprint
+};
