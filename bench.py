@@ -1,0 +1,196 @@
+"""Benchmark: Mdof*steps/s of the mu-mode Lawson2b path on the 255^3 workload.
+
+One step = one Lawson2b step over the whole grid: two fused remainder/stage passes and
+one stacked exp action (three mode products on two grid functions). The workload is the
+3D Dirichlet ADR problem with 255^3 interior points (h = 1/256), a = 1 + 0.9 tanh(s),
+beta = (10, 10, 10), r = u^2(1 - u), tau = 1e-3, 100 steps to T = 0.1 (synthetic seeded
+inputs). Every contraction precision is timed; the headline value is the FP64 path
+unless --headline names another mode. Each mixed mode's error is reported against the
+FP64 path after the same steps (the FP64 path matches the CPU oracle to 1e-12 in the
+parity tests).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes fp64,fp32,...]
+
+Prints one JSON line. --gpus N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
+HBM_PEAK = 8.0e12
+WORKLOAD = "3d_n255_l2b"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--modes", default="fp64,fp32,bf16x6,bf16x3")
+    ap.add_argument("--headline", default="fp64")
+    ap.add_argument("--latency-reps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    return ap.parse_args()
+
+
+def time_mode(mm, ctx, p, prec, steps, warmup):
+    import torch
+    op = mm.setup_problem(ctx, p, prec=prec)
+    u0 = torch.from_numpy(p.u0).to("cuda")
+    u = u0.clone()
+    stream = torch.cuda.current_stream()
+    if warmup:
+        mm.lawson_step(op, u, warmup)
+    u.copy_(u0)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t0 = time.perf_counter()
+    mm.lawson_step(op, u, steps, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = {}
+    for kind, name in ((mm.MM_KIND_GEMM_K, "gemm_k"), (mm.MM_KIND_GEMM_N, "gemm_n"),
+                       (mm.MM_KIND_STENCIL, "stencil")):
+        n, ms, wk = ctx.timing_read(kind)
+        kern[name] = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / max(n, 1), "work": wk}
+    ctx.timing(False)
+    status = mm.mm_check(op)
+    out = u.cpu().numpy()
+    return op, out, (t1 - t0), kern, status
+
+
+def latency(mm, ctx, op, p, reps):
+    import torch
+    u0 = torch.from_numpy(p.u0).to("cuda")
+    u = u0.clone()
+    lat = []
+    for _ in range(reps):
+        u.copy_(u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mm.lawson_step(op, u, p.steps)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    lat = np.array(lat) * 1e3
+    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "reps": reps, "steps_per_solve": p.steps}
+
+
+def cpu_baseline(p, steps):
+    """The oracle, untuned, on the host cores: `steps` Lawson2b steps of the workload."""
+    cores = len(os.sched_getaffinity(0))
+    try:
+        from threadpoolctl import threadpool_limits
+        ctxm = threadpool_limits(limits=cores)
+    except Exception:  # pragma: no cover
+        ctxm = None
+    from oracle import schemes as S
+    t0 = time.perf_counter()
+    S.solve(p, steps=steps)
+    dt = time.perf_counter() - t0
+    if ctxm is not None:
+        ctxm.unregister() if hasattr(ctxm, "unregister") else None
+    return {"value": p.dof * steps / dt / 1e6, "unit": "Mdof*steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} Lawson2b steps of the 255^3 workload (numpy FP64, OpenBLAS threads = cores)",
+            "seconds": dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import paper_2303_15861_amd as mm
+    import synth
+
+    p = synth.workload(WORKLOAD)
+    ctx = mm.Context(0)
+    modes = [m for m in args.modes.split(",") if m]
+    if "fp64" not in modes:
+        modes = ["fp64"] + modes
+    res = {}
+    ref = None
+    for prec in modes:
+        print(f"[bench] {prec}: setup + {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
+              flush=True)
+        op, out, dt, kern, status = time_mode(mm, ctx, p, prec, args.steps, args.warmup)
+        entry = {"ms_per_step": 1e3 * dt / args.steps, "value": p.dof * args.steps / dt / 1e6,
+                 "kernels": kern, "status": mm.STATUS.get(status, status)}
+        if prec == "fp64":
+            ref = out
+        else:
+            entry["err_vs_fp64"] = float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
+        if prec == args.headline:
+            entry["latency"] = latency(mm, ctx, op, p, args.latency_reps)
+        op.close()
+        res[prec] = entry
+        print(f"[bench] {prec}: {entry['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    head = res[args.headline]
+    # roofline of the dominant kernel of the headline mode
+    kname = max(("gemm_k", "gemm_n", "stencil"), key=lambda k: head["kernels"][k]["total_ms"])
+    k = head["kernels"][kname]
+    if kname == "stencil":
+        # algorithmic bytes per grid point of the fused remainder passes: read u and a,
+        # write two outputs (first pass) or read u, a, W and write u (second pass): 32 B
+        achieved = 32.0 * k["work"] / (k["total_ms"] * 1e-3)
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    else:
+        dtype_peak = {"fp64": "fp64", "fp32": "fp32"}.get(args.headline, "bf16")
+        if dtype_peak == "bf16":
+            # split-BF16 contractions are bound by HBM: 16 B per grid point per pass
+            flops_per_point = 2.0 * p.n[0]
+            bytes_ = 16.0 * k["work"] / flops_per_point
+            achieved = bytes_ / (k["total_ms"] * 1e-3)
+            roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+        else:
+            achieved = k["work"] / (k["total_ms"] * 1e-3)
+            roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[dtype_peak] / 1e12,
+                    "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = {"gemm_k": "gemm (mode 1)", "gemm_n": "gemm (modes 2, 3)", "stencil": "stencil"}[kname]
+    roof["avg_launch_us"] = k["avg_us"]
+    roof["traffic"] = None
+
+    line = {
+        "metric": "Mdof*steps/s at 256^3 (255^3 interior), FP64 vs MFMA mixed at stated error; p50/p99 solve latency",
+        "value": head["value"],
+        "unit": "Mdof*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}[args.headline],
+        "data": "synthetic",
+        "config": {"workload": "3D Dirichlet ADR 255^3 interior, Lawson2b, tau=1e-3, 100 steps to T=0.1",
+                   "dof": p.dof, "scheme": "lawson2b", "headline_mode": args.headline},
+        "latency": head.get("latency"),
+        "modes": {m: {kk: vv for kk, vv in e.items() if kk != "kernels"} for m, e in res.items()},
+        "kernels": {m: e["kernels"] for m, e in res.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        print(f"[bench] cpu baseline: {args.cpu_steps} oracle steps", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
+    print(json.dumps(line))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

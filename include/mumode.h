@@ -151,6 +151,17 @@ mm_status erk_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* st
  * non-finite value since the op was created (the flag is sticky). */
 mm_status mm_check(mm_ctx* ctx, const mm_op* op, void* stream);
 
+/* Per-kernel timing (diagnostics). While enabled, every kernel launch the context
+ * enqueues is bracketed by two HIP events recorded on the launch's own stream, and the
+ * launch's algorithmic work is recorded with it (mode products: 2*M*N*K flops per
+ * batch, padding excluded; stencil: grid points). kind: MM_KIND_STENCIL, MM_KIND_GEMM_K
+ * (mode-1 kernel, both operands read along k) or MM_KIND_GEMM_N (modes 2..d, the grid
+ * operand read along n). mm_timing_read synchronises the recorded events and returns
+ * the totals since the last enable. */
+enum { MM_KIND_STENCIL = 0, MM_KIND_GEMM_K = 1, MM_KIND_GEMM_N = 2 };
+mm_status mm_timing_enable(mm_ctx* ctx, int enable);
+mm_status mm_timing_read(mm_ctx* ctx, int kind, int64_t* launches, double* total_ms, double* work);
+
 /* ---------------------------------------------------------------------------------
  * Serving: a request loop on its own host thread and HIP stream. Requests that arrive
  * while others run are admitted as slots and device memory allow; admitted requests

@@ -35,7 +35,9 @@ STATUS = {0: "MM_OK", 1: "MM_NOT_READY", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "
 EXPORTS = ("mm_ctx_create", "mm_ctx_destroy", "mm_last_error", "mm_version", "mumode_setup",
            "mumode_destroy", "mumode_info", "mumode_get_factor", "remainder_eval", "mumode_expv",
            "mumode_phi1v", "lawson_step", "erk_step", "mm_check", "mm_server_create",
-           "mm_server_destroy", "solve_submit", "solve_poll", "mm_server_clock")
+           "mm_server_destroy", "solve_submit", "solve_poll", "mm_server_clock", "mm_timing_enable",
+           "mm_timing_read")
+MM_KIND_STENCIL, MM_KIND_GEMM_K, MM_KIND_GEMM_N = 0, 1, 2
 
 
 class MMProblem(Structure):
@@ -87,6 +89,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "solve_submit": (i, [vp, POINTER(MMRequest), POINTER(c_uint64)]),
         "solve_poll": (i, [vp, c_uint64, vp, POINTER(MMStats)]),
         "mm_server_clock": (d, [vp]),
+        "mm_timing_enable": (i, [vp, i]),
+        "mm_timing_read": (i, [vp, i, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -147,6 +151,15 @@ class Context:
     def check(self, st: int, what: str):
         if st != MM_OK:
             raise MumodeError(st, f"{what}: {self.error()}")
+
+    def timing(self, enable: bool):
+        self.check(lib().mm_timing_enable(self._h, int(enable)), "mm_timing_enable")
+
+    def timing_read(self, kind: int):
+        """(launches, total milliseconds, algorithmic work) of one kernel kind."""
+        n, ms, wk = c_int64(), c_double(), c_double()
+        self.check(lib().mm_timing_read(self._h, kind, byref(n), byref(ms), byref(wk)), "mm_timing_read")
+        return n.value, ms.value, wk.value
 
     def close(self):
         if self._h:

@@ -150,6 +150,37 @@ mm_status dev_alloc(mm_op* op, T** p, int64_t count) {
 
 int last_axis(const mm_op* op) { return op->d - 1; }
 
+// Bracket one launch with events on its stream when the context is timing.
+template <typename F>
+hipError_t timed_launch(mm_ctx* ctx, int kind, double work, hipStream_t s, F&& launch) {
+  if (!ctx || !ctx->timing) return launch();
+  if (ctx->timed_used == ctx->timed.size()) {
+    mm_timed t{};
+    if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess)
+      return hipErrorOutOfMemory;
+    ctx->timed.push_back(t);
+  }
+  mm_timed& t = ctx->timed[ctx->timed_used++];
+  t.kind = kind;
+  t.work = work;
+  hipError_t e = hipEventRecord(t.start, s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  return hipEventRecord(t.stop, s);
+}
+
+hipError_t gemm(const mm_op* op, GemmArgs& g, hipStream_t s) {
+  const double work = 2.0 * g.M * (double)g.N * g.K * g.inner * g.groups;
+  return timed_launch(op->ctx, g.b_trans ? MM_KIND_GEMM_N : MM_KIND_GEMM_K, work, s,
+                      [&] { return launch_gemm(op->prec, g, s); });
+}
+
+hipError_t stencil(const mm_op* op, const StencilArgs& a, hipStream_t s) {
+  return timed_launch(op->ctx, MM_KIND_STENCIL, (double)op->dof, s,
+                      [&] { return launch_stencil(op->d, a, s); });
+}
+
 // ---------------------------------------------------------------- mode passes
 // mode 1: C (rows x n1) = A (rows x n1) . E1^T, per group (input, factor, output)
 hipError_t pass_mode1(const mm_op* op, int groups, const double* const* in, const double* const* E,
@@ -170,7 +201,7 @@ hipError_t pass_mode1(const mm_op* op, int groups, const double* const* in, cons
   g.b_trans = 0;
   g.alpha = 1.0;
   g.beta = 0.0;
-  return launch_gemm(op->prec, g, s);
+  return gemm(op, g, s);
 }
 
 // mode 2 of a 3D grid: per x3-slab (n2 x n1), C = E2 . slab, `slabs` slabs per group
@@ -196,7 +227,7 @@ hipError_t pass_mode2(const mm_op* op, int groups, const double* const* E, const
   g.b_trans = 1;
   g.alpha = 1.0;
   g.beta = 0.0;
-  return launch_gemm(op->prec, g, s);
+  return gemm(op, g, s);
 }
 
 // last mode: C (nl x P) = alpha * F (nl x K) . B (K x P) + beta * add, K = kmul * nl,
@@ -223,7 +254,7 @@ hipError_t pass_last(const mm_op* op, const double* F, int kmul, const double* i
   g.b_trans = 1;
   g.alpha = alpha;
   g.beta = beta;
-  return launch_gemm(op->prec, g, s);
+  return gemm(op, g, s);
 }
 
 const double* factor(const mm_op* op, int mu, int j) {
@@ -348,6 +379,10 @@ void mm_ctx_destroy(mm_ctx* ctx) {
   hipSetDevice(ctx->device);
   if (ctx->stream) hipStreamSynchronize(ctx->stream);
   if (ctx->reduce_buf) hipFree(ctx->reduce_buf);
+  for (auto& t : ctx->timed) {
+    hipEventDestroy(t.start);
+    hipEventDestroy(t.stop);
+  }
   if (ctx->stream) hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -604,12 +639,12 @@ mm_status remainder_eval(mm_ctx* ctx, const mm_op* op, const double* u, double* 
   StencilArgs a = stencil_args(op, u, false);
   a.out0 = g;
   a.flag = nullptr;
-  HIPCHK(ctx, launch_stencil(op->d, a, s));
+  HIPCHK(ctx, stencil(op, a, s));
   if (F) {
     StencilArgs b = stencil_args(op, u, true);
     b.out0 = F;
     b.flag = nullptr;
-    HIPCHK(ctx, launch_stencil(op->d, b, s));
+    HIPCHK(ctx, stencil(op, b, s));
   }
   return MM_OK;
 }
@@ -673,7 +708,7 @@ mm_status lawson_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void*
       a.base0 = u;
       a.c0 = tau;
       a.out0 = b0;
-      HIPCHK(ctx, launch_stencil(op->d, a, s));
+      HIPCHK(ctx, stencil(op, a, s));
       HIPCHK(ctx, exp_action(op, 0, b0, u, 1, b1, b0, s));
     } else {
       // v1 = u + tau g(u), v2 = u + tau/2 g(u); [U, W] = e^{tau A}[v1, v2]; u+ = W + tau/2 g(U)
@@ -684,14 +719,14 @@ mm_status lawson_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void*
       a.base1 = u;
       a.c1 = 0.5 * tau;
       a.out1 = b0 + dof;
-      HIPCHK(ctx, launch_stencil(op->d, a, s));
+      HIPCHK(ctx, stencil(op, a, s));
       double* res = (op->d == 3) ? b1 : b0;
       HIPCHK(ctx, exp_action(op, 0, b0, res, 2, b1, b0, s));
       StencilArgs c = stencil_args(op, res, false);
       c.base0 = res + dof;
       c.c0 = 0.5 * tau;
       c.out0 = u;
-      HIPCHK(ctx, launch_stencil(op->d, c, s));
+      HIPCHK(ctx, stencil(op, c, s));
     }
   }
   return MM_OK;
@@ -718,7 +753,7 @@ mm_status erk_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* st
   for (int it = 0; it < nsteps; ++it) {
     StencilArgs a = stencil_args(op, u, false);
     a.out0 = g0;
-    HIPCHK(ctx, launch_stencil(op->d, a, s));
+    HIPCHK(ctx, stencil(op, a, s));
     if (op->scheme == MM_ETD2RK) {
       // U = e^{tau A} u + tau sum_j w_j e^{theta_j tau A} g0
       ins[0] = u;
@@ -732,7 +767,7 @@ mm_status erk_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* st
       // U = u + tau sum_j w_j e^{theta_j tau A} F(u)
       StencilArgs f = stencil_args(op, u, true);
       f.out0 = F0;
-      HIPCHK(ctx, launch_stencil(op->d, f, s));
+      HIPCHK(ctx, stencil(op, f, s));
       for (int j = 0; j < q; ++j) {
         ins[j] = F0;
         fidx[j] = j + 1;
@@ -743,13 +778,40 @@ mm_status erk_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* st
     StencilArgs b = stencil_args(op, U, false);
     b.sub = g0;
     b.out0 = D;
-    HIPCHK(ctx, launch_stencil(op->d, b, s));
+    HIPCHK(ctx, stencil(op, b, s));
     for (int j = 0; j < q; ++j) {
       ins[j] = D;
       fidx[j] = j + 1;
     }
     HIPCHK(ctx, grouped_action(op, q, ins, fidx, op->f3_stage2, u, U, 1.0, T1, T2, s));
   }
+  return MM_OK;
+}
+
+mm_status mm_timing_enable(mm_ctx* ctx, int enable) {
+  if (!ctx) return MM_EINVAL;
+  ctx->timing = enable != 0;
+  ctx->timed_used = 0;
+  return MM_OK;
+}
+
+mm_status mm_timing_read(mm_ctx* ctx, int kind, int64_t* launches, double* total_ms, double* work) {
+  if (!ctx) return MM_EINVAL;
+  int64_t cnt = 0;
+  double ms = 0.0, wk = 0.0;
+  for (size_t i = 0; i < ctx->timed_used; ++i) {
+    mm_timed& t = ctx->timed[i];
+    if (t.kind != kind) continue;
+    HIPCHK(ctx, hipEventSynchronize(t.stop));
+    float e = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&e, t.start, t.stop));
+    ++cnt;
+    ms += e;
+    wk += t.work;
+  }
+  if (launches) *launches = cnt;
+  if (total_ms) *total_ms = ms;
+  if (work) *work = wk;
   return MM_OK;
 }
 

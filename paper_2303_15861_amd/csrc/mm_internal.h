@@ -74,12 +74,21 @@ hipError_t launch_fill(double* dst, double v, int64_t count, hipStream_t s);
 
 }  // namespace mm
 
+struct mm_timed {
+  int kind;
+  double work;
+  hipEvent_t start, stop;
+};
+
 struct mm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;   // setup stream
   std::string last_error;
   double* reduce_buf = nullptr;   // partial maxima
   int reduce_parts = 0;
+  bool timing = false;            // per-kernel event timing
+  std::vector<mm_timed> timed;
+  size_t timed_used = 0;
 };
 
 struct mm_op {
