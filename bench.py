@@ -133,7 +133,7 @@ def main():
             ref = out
         else:
             entry["err_vs_fp64"] = float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
-        if prec == args.headline:
+        if prec == args.headline and args.latency_reps > 0:
             entry["latency"] = latency(mm, ctx, op, p, args.latency_reps)
         op.close()
         res[prec] = entry

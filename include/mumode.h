@@ -116,6 +116,9 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
 /* Release the op. Work enqueued with it must have completed (synchronise first). */
 void mumode_destroy(mm_op* op);
 
+/* Wait until all work on the context's device has completed (hipDeviceSynchronize). */
+mm_status mm_synchronize(mm_ctx* ctx);
+
 /* The extracted maximum a_max and the scaling exponent s used for factor c = 1 along
  * axis mu (diagnostics). */
 mm_status mumode_info(const mm_op* op, double* a_max, int* squarings);

@@ -36,7 +36,7 @@ EXPORTS = ("mm_ctx_create", "mm_ctx_destroy", "mm_last_error", "mm_version", "mu
            "mumode_destroy", "mumode_info", "mumode_get_factor", "remainder_eval", "mumode_expv",
            "mumode_phi1v", "lawson_step", "erk_step", "mm_check", "mm_server_create",
            "mm_server_destroy", "solve_submit", "solve_poll", "mm_server_clock", "mm_timing_enable",
-           "mm_timing_read")
+           "mm_timing_read", "mm_synchronize")
 MM_KIND_STENCIL, MM_KIND_GEMM_K, MM_KIND_GEMM_N = 0, 1, 2
 
 
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "solve_poll": (i, [vp, c_uint64, vp, POINTER(MMStats)]),
         "mm_server_clock": (d, [vp]),
         "mm_timing_enable": (i, [vp, i]),
+        "mm_synchronize": (i, [vp]),
         "mm_timing_read": (i, [vp, i, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
     }
     for name, (res, args) in sig.items():
@@ -206,7 +207,8 @@ class Operator:
 
     def close(self):
         if self._h:
-            _torch().cuda.synchronize(self.ctx.device)
+            # through the library, so that this is safe from a finaliser
+            lib().mm_synchronize(self.ctx.handle)
             lib().mumode_destroy(self._h)
             self._h = c_void_p()
 

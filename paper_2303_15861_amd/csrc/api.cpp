@@ -182,34 +182,67 @@ hipError_t stencil(const mm_op* op, const StencilArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- mode passes
+// Operand formats of one mode pass: the grid operand is read as float (in_f32) or
+// double, C is written as float (out_f32) or double. FP64 ops always use double.
+struct PassIO {
+  bool in_f32 = false, out_f32 = false;
+};
+
+// the factor operand of axis mu, coefficient index j, in the op's precision
+const void* factor_op(const mm_op* op, int mu, int j) {
+  if (op->prec == MM_FP64) return op->fac[mu] + (int64_t)j * op->n[mu] * op->n[mu];
+  const int n = op->n[mu];
+  const int64_t per = (int64_t)n * fac_ld(n) * factor_slices(op->prec);
+  const int64_t esz = (op->prec == MM_FP32) ? 4 : 2;
+  return (const char*)op->fac_lp[mu] + j * per * esz;
+}
+
+// the stacked last-axis factor of an ERK stage in the op's precision
+const void* stacked(const mm_op* op, int which) {
+  if (op->prec == MM_FP64) return which == 1 ? op->f3_stage1 : which == 2 ? op->f3_stage2 : op->f3_phi;
+  return which == 1 ? op->f3_stage1_lp : which == 2 ? op->f3_stage2_lp : op->f3_phi_lp;
+}
+
+int64_t factor_slice_stride(const mm_op* op, int rows, int k) {
+  return (int64_t)rows * fac_ld(k) * (op->prec == MM_FP32 ? 0 : 1);
+}
+
+int factor_ld(const mm_op* op, int k) { return op->prec == MM_FP64 ? k : fac_ld(k); }
+
 // mode 1: C (rows x n1) = A (rows x n1) . E1^T, per group (input, factor, output)
-hipError_t pass_mode1(const mm_op* op, int groups, const double* const* in, const double* const* E,
-                      double* const* out, int rows, hipStream_t s) {
+hipError_t pass_mode1(const mm_op* op, int groups, const void* const* in, const int* fidx,
+                      void* const* out, int rows, PassIO io, hipStream_t s) {
+  const int n1 = op->n[0];
   GemmArgs g{};
   for (int i = 0; i < groups; ++i) {
     g.A[i] = in[i];
-    g.B[i] = E[i];
+    g.B[i] = factor_op(op, 0, fidx[i]);
     g.C[i] = out[i];
     g.Cadd[i] = nullptr;
   }
   g.M = rows;
-  g.N = op->n[0];
-  g.K = op->n[0];
-  g.lda = g.ldb = g.ldc = op->n[0];
+  g.N = n1;
+  g.K = n1;
+  g.lda = n1;
+  g.ldb = factor_ld(op, n1);
+  g.ldc = n1;
   g.inner = 1;
   g.groups = groups;
   g.b_trans = 0;
   g.alpha = 1.0;
   g.beta = 0.0;
+  g.in_f32 = io.in_f32;
+  g.out_f32 = io.out_f32;
+  g.fac_slice = factor_slice_stride(op, n1, n1);
   return gemm(op, g, s);
 }
 
 // mode 2 of a 3D grid: per x3-slab (n2 x n1), C = E2 . slab, `slabs` slabs per group
-hipError_t pass_mode2(const mm_op* op, int groups, const double* const* E, const double* const* in,
-                      double* const* out, int slabs, hipStream_t s) {
+hipError_t pass_mode2(const mm_op* op, int groups, const int* fidx, const void* const* in, void* const* out,
+                      int slabs, PassIO io, hipStream_t s) {
   GemmArgs g{};
   for (int i = 0; i < groups; ++i) {
-    g.A[i] = E[i];
+    g.A[i] = factor_op(op, 1, fidx[i]);
     g.B[i] = in[i];
     g.C[i] = out[i];
     g.Cadd[i] = nullptr;
@@ -217,7 +250,7 @@ hipError_t pass_mode2(const mm_op* op, int groups, const double* const* E, const
   g.M = op->n[1];
   g.N = op->n[0];
   g.K = op->n[1];
-  g.lda = op->n[1];
+  g.lda = factor_ld(op, op->n[1]);
   g.ldb = op->n[0];
   g.ldc = op->n[0];
   g.inner = slabs;
@@ -227,13 +260,17 @@ hipError_t pass_mode2(const mm_op* op, int groups, const double* const* E, const
   g.b_trans = 1;
   g.alpha = 1.0;
   g.beta = 0.0;
+  g.in_f32 = io.in_f32;
+  g.out_f32 = io.out_f32;
+  g.fac_slice = factor_slice_stride(op, op->n[1], op->n[1]);
   return gemm(op, g, s);
 }
 
 // last mode: C (nl x P) = alpha * F (nl x K) . B (K x P) + beta * add, K = kmul * nl,
-// P = dof / nl; `inner` stacked vectors of stride dof (same factor).
-hipError_t pass_last(const mm_op* op, const double* F, int kmul, const double* in, double* out,
-                     const double* add, double alpha, double beta, int inner, hipStream_t s) {
+// P = dof / nl; `inner` stacked vectors of stride dof (same factor). F is the factor
+// operand in the op's precision (row stride factor_ld(K)).
+hipError_t pass_last(const mm_op* op, const void* F, int kmul, const void* in, void* out, const double* add,
+                     double alpha, double beta, int inner, PassIO io, hipStream_t s) {
   const int nl = op->n[last_axis(op)];
   const int P = (int)(op->dof / nl);
   GemmArgs g{};
@@ -244,7 +281,7 @@ hipError_t pass_last(const mm_op* op, const double* F, int kmul, const double* i
   g.M = nl;
   g.N = P;
   g.K = kmul * nl;
-  g.lda = kmul * nl;
+  g.lda = factor_ld(op, kmul * nl);
   g.ldb = P;
   g.ldc = P;
   g.inner = inner;
@@ -254,6 +291,9 @@ hipError_t pass_last(const mm_op* op, const double* F, int kmul, const double* i
   g.b_trans = 1;
   g.alpha = alpha;
   g.beta = beta;
+  g.in_f32 = io.in_f32;
+  g.out_f32 = io.out_f32;
+  g.fac_slice = factor_slice_stride(op, nl, kmul * nl);
   return gemm(op, g, s);
 }
 
@@ -261,51 +301,61 @@ const double* factor(const mm_op* op, int mu, int j) {
   return op->fac[mu] + (int64_t)j * op->n[mu] * op->n[mu];
 }
 
-// out = exp(c_j tau A) in for `nvec` stacked vectors (stride dof): in -> t0 [-> t1] -> out
-hipError_t exp_action(const mm_op* op, int j, const double* in, double* out, int nvec, double* t0,
+// out = exp(c_j tau A) in for `nvec` stacked vectors (stride dof): in -> t0 [-> t1] -> out.
+// in_f32: the input is float (mixed modes only); out is always double. In the mixed
+// modes the intermediates t0, t1 hold floats.
+hipError_t exp_action(const mm_op* op, int j, const void* in, bool in_f32, double* out, int nvec, double* t0,
                       double* t1, hipStream_t s) {
-  const double* E1 = factor(op, 0, j);
-  double* o1 = (op->d == 3) ? t0 : t0;
-  hipError_t e = pass_mode1(op, 1, &in, &E1, &o1, (int)(op->dof / op->n[0]) * nvec, s);
-  if (e != hipSuccess) return e;
+  const bool mixed = op->prec != MM_FP64;
+  PassIO first{in_f32, mixed}, mid{mixed, mixed}, last_io{mixed, false};
+  const int fj[1] = {j};
+  const void* i1[1] = {in};
+  void* o1[1] = {t0};
+  const int la = last_axis(op);
+  const void* Fl = (op->prec == MM_FP64) ? (const void*)factor(op, la, j) : factor_op(op, la, j);
   if (op->d == 3) {
-    const double* E2 = factor(op, 1, j);
-    const double* i2 = t0;
-    e = pass_mode2(op, 1, &E2, &i2, &t1, op->n[2] * nvec, s);
+    hipError_t e = pass_mode1(op, 1, i1, fj, o1, (int)(op->dof / op->n[0]) * nvec, first, s);
     if (e != hipSuccess) return e;
-    return pass_last(op, factor(op, 2, j), 1, t1, out, nullptr, 1.0, 0.0, nvec, s);
+    const void* i2[1] = {t0};
+    void* o2[1] = {t1};
+    e = pass_mode2(op, 1, fj, i2, o2, op->n[2] * nvec, mid, s);
+    if (e != hipSuccess) return e;
+    return pass_last(op, Fl, 1, t1, out, nullptr, 1.0, 0.0, nvec, last_io, s);
   }
-  return pass_last(op, factor(op, 1, j), 1, t0, out, nullptr, 1.0, 0.0, nvec, s);
+  hipError_t e = pass_mode1(op, 1, i1, fj, o1, (int)(op->dof / op->n[0]) * nvec, first, s);
+  if (e != hipSuccess) return e;
+  PassIO l2{mixed, false};
+  return pass_last(op, Fl, 1, t0, out, nullptr, 1.0, 0.0, nvec, l2, s);
 }
 
 // out = stacked-last-factor contraction over G groups: group g applies modes 1..d-1 with
-// factor index fidx[g] to input ins[g]; the last mode sums the groups with the
-// stacked factor F3 (nl x G*nl) and adds beta*add.
-hipError_t grouped_action(const mm_op* op, int G, const double* const* ins, const int* fidx,
-                          const double* F3, double* out, const double* add, double beta, double* t0,
-                          double* t1, hipStream_t s) {
-  const double* E1[kMaxGroups];
-  double* o1[kMaxGroups];
+// factor index fidx[g] to the FP64 input ins[g]; the last mode sums the groups with the
+// stacked factor F3 (nl x G*nl, in the op's precision) and adds beta*add. t0 and t1
+// hold G grid functions each (floats in the mixed modes).
+hipError_t grouped_action(const mm_op* op, int G, const double* const* ins, const int* fidx, const void* F3,
+                          double* out, const double* add, double beta, double* t0, double* t1, hipStream_t s) {
+  const bool mixed = op->prec != MM_FP64;
+  const int64_t esz = mixed ? 4 : 8;
+  const void* in1[kMaxGroups];
+  void* o1[kMaxGroups];
   for (int g = 0; g < G; ++g) {
-    E1[g] = factor(op, 0, fidx[g]);
-    o1[g] = t0 + (int64_t)g * op->dof;
+    in1[g] = ins[g];
+    o1[g] = (char*)t0 + g * op->dof * esz;
   }
-  hipError_t e = pass_mode1(op, G, ins, E1, o1, (int)(op->dof / op->n[0]), s);
+  hipError_t e = pass_mode1(op, G, in1, fidx, o1, (int)(op->dof / op->n[0]), PassIO{false, mixed}, s);
   if (e != hipSuccess) return e;
   if (op->d == 3) {
-    const double* E2[kMaxGroups];
-    const double* i2[kMaxGroups];
-    double* o2[kMaxGroups];
+    const void* i2[kMaxGroups];
+    void* o2[kMaxGroups];
     for (int g = 0; g < G; ++g) {
-      E2[g] = factor(op, 1, fidx[g]);
-      i2[g] = t0 + (int64_t)g * op->dof;
-      o2[g] = t1 + (int64_t)g * op->dof;
+      i2[g] = (const char*)t0 + g * op->dof * esz;
+      o2[g] = (char*)t1 + g * op->dof * esz;
     }
-    e = pass_mode2(op, G, E2, i2, o2, op->n[2], s);
+    e = pass_mode2(op, G, fidx, i2, o2, op->n[2], PassIO{mixed, mixed}, s);
     if (e != hipSuccess) return e;
-    return pass_last(op, F3, G, t1, out, add, 1.0, beta, 1, s);
+    return pass_last(op, F3, G, t1, out, add, 1.0, beta, 1, PassIO{mixed, false}, s);
   }
-  return pass_last(op, F3, G, t0, out, add, 1.0, beta, 1, s);
+  return pass_last(op, F3, G, t0, out, add, 1.0, beta, 1, PassIO{mixed, false}, s);
 }
 
 StencilArgs stencil_args(const mm_op* op, const double* u, bool full) {
@@ -404,6 +454,11 @@ void mumode_destroy(mm_op* op) {
   if (op->f3_stage1) hipFree(op->f3_stage1);
   if (op->f3_stage2) hipFree(op->f3_stage2);
   if (op->f3_phi) hipFree(op->f3_phi);
+  for (size_t i = 0; i < op->fac_lp.size(); ++i)
+    if (op->fac_owned[i] && op->fac_lp[i]) hipFree(op->fac_lp[i]);
+  if (op->f3_stage1_lp) hipFree(op->f3_stage1_lp);
+  if (op->f3_stage2_lp) hipFree(op->f3_stage2_lp);
+  if (op->f3_phi_lp) hipFree(op->f3_phi_lp);
   for (int i = 0; i < 6; ++i)
     if (op->buf[i]) hipFree(op->buf[i]);
   if (op->flag) hipFree(op->flag);
@@ -567,6 +622,26 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     return fail(MM_EDEVICE);
   }
   hipFree(ws);
+  // mixed modes: FP32 or BF16-slice copies with zero-padded rows
+  const int nsl = factor_slices(prec);
+  const int64_t esz = (prec == MM_FP32) ? 4 : 2;
+  op->fac_lp.assign(op->d, nullptr);
+  if (prec != MM_FP64) {
+    for (int mu = 0; mu < op->d; ++mu) {
+      if (!op->fac_owned[mu]) {
+        for (int nu = 0; nu < mu; ++nu)
+          if (op->fac[nu] == op->fac[mu]) op->fac_lp[mu] = op->fac_lp[nu];
+        continue;
+      }
+      const int n = op->n[mu];
+      const int64_t per = (int64_t)n * fac_ld(n) * nsl;
+      char* dst = nullptr;
+      if ((rc = dev_alloc(op, &dst, nf * per * esz)) != MM_OK) return fail(rc);
+      op->fac_lp[mu] = dst;
+      for (int j = 0; j < nf; ++j)
+        HIPCHK(ctx, launch_convert_factor(prec, dst + j * per * esz, op->fac[mu] + (int64_t)j * n * n, n, n, n, st));
+    }
+  }
 
   const int la = last_axis(op);
   const int nl = op->n[la];
@@ -589,6 +664,19 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
       HIPCHK(ctx, launch_place_scaled(op->f3_stage2, q * nl, (j - 1) * nl, factor(op, la, j), nl,
                                       0.5 * tau * op->weight[j], st));
       HIPCHK(ctx, launch_place_scaled(op->f3_phi, q * nl, (j - 1) * nl, factor(op, la, j), nl, op->weight[j], st));
+    }
+    if (prec != MM_FP64) {
+      const int64_t s1 = (int64_t)nl * fac_ld(g1 * nl) * nsl * esz, s2 = (int64_t)nl * fac_ld(q * nl) * nsl * esz;
+      char *d1 = nullptr, *d2 = nullptr, *d3 = nullptr;
+      if ((rc = dev_alloc(op, &d1, s1)) != MM_OK) return fail(rc);
+      op->f3_stage1_lp = d1;
+      if ((rc = dev_alloc(op, &d2, s2)) != MM_OK) return fail(rc);
+      op->f3_stage2_lp = d2;
+      if ((rc = dev_alloc(op, &d3, s2)) != MM_OK) return fail(rc);
+      op->f3_phi_lp = d3;
+      HIPCHK(ctx, launch_convert_factor(prec, d1, op->f3_stage1, nl, g1 * nl, g1 * nl, st));
+      HIPCHK(ctx, launch_convert_factor(prec, d2, op->f3_stage2, nl, q * nl, q * nl, st));
+      HIPCHK(ctx, launch_convert_factor(prec, d3, op->f3_phi, nl, q * nl, q * nl, st));
     }
     // buffers: 0 g0, 1 T1 ((q+1) dof), 2 T2 ((q+1) dof), 3 U, 4 D, 5 F0 (ERK2P1)
     const int64_t lens[6] = {dof, (q + 1) * dof, (q + 1) * dof, dof, dof, scheme == MM_ERK2P1 ? dof : 0};
@@ -659,7 +747,7 @@ mm_status mumode_expv(mm_ctx* ctx, const mm_op* op, int j, const double* in, dou
   hipStream_t s = (hipStream_t)stream;
   double* t0 = (op->family == MM_ERK) ? op->buf[1] : op->buf[0];
   double* t1 = (op->family == MM_ERK) ? op->buf[2] : op->buf[1];
-  HIPCHK(ctx, exp_action(op, j, in, out, 1, t0, t1, s));
+  HIPCHK(ctx, exp_action(op, j, in, false, out, 1, t0, t1, s));
   return MM_OK;
 }
 
@@ -681,7 +769,7 @@ mm_status mumode_phi1v(mm_ctx* ctx, const mm_op* op, const double* in, double* o
     ins[g] = in;
     fidx[g] = g + 1;
   }
-  HIPCHK(ctx, grouped_action(op, op->q, ins, fidx, op->f3_phi, out, nullptr, 0.0, op->buf[1], op->buf[2], s));
+  HIPCHK(ctx, grouped_action(op, op->q, ins, fidx, stacked(op, 3), out, nullptr, 0.0, op->buf[1], op->buf[2], s));
   return MM_OK;
 }
 
@@ -701,27 +789,36 @@ mm_status lawson_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void*
   const int64_t dof = op->dof;
   double* b0 = op->buf[0];
   double* b1 = op->buf[1];
+  const bool mixed = op->prec != MM_FP64;
   for (int it = 0; it < nsteps; ++it) {
     if (op->scheme == MM_LAWSON_EULER) {
       // u+ = e^{tau A}(u + tau g(u))
       StencilArgs a = stencil_args(op, u, false);
       a.base0 = u;
       a.c0 = tau;
-      a.out0 = b0;
+      if (mixed)
+        a.out0f = (float*)b0;
+      else
+        a.out0 = b0;
       HIPCHK(ctx, stencil(op, a, s));
-      HIPCHK(ctx, exp_action(op, 0, b0, u, 1, b1, b0, s));
+      HIPCHK(ctx, exp_action(op, 0, b0, mixed, u, 1, b1, b0, s));
     } else {
       // v1 = u + tau g(u), v2 = u + tau/2 g(u); [U, W] = e^{tau A}[v1, v2]; u+ = W + tau/2 g(U)
       StencilArgs a = stencil_args(op, u, false);
       a.base0 = u;
       a.c0 = tau;
-      a.out0 = b0;
       a.base1 = u;
       a.c1 = 0.5 * tau;
-      a.out1 = b0 + dof;
+      if (mixed) {
+        a.out0f = (float*)b0;
+        a.out1f = (float*)b0 + dof;
+      } else {
+        a.out0 = b0;
+        a.out1 = b0 + dof;
+      }
       HIPCHK(ctx, stencil(op, a, s));
       double* res = (op->d == 3) ? b1 : b0;
-      HIPCHK(ctx, exp_action(op, 0, b0, res, 2, b1, b0, s));
+      HIPCHK(ctx, exp_action(op, 0, b0, mixed, res, 2, b1, b0, s));
       StencilArgs c = stencil_args(op, res, false);
       c.base0 = res + dof;
       c.c0 = 0.5 * tau;
@@ -762,7 +859,7 @@ mm_status erk_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* st
         ins[j] = g0;
         fidx[j] = j;
       }
-      HIPCHK(ctx, grouped_action(op, q + 1, ins, fidx, op->f3_stage1, U, nullptr, 0.0, T1, T2, s));
+      HIPCHK(ctx, grouped_action(op, q + 1, ins, fidx, stacked(op, 1), U, nullptr, 0.0, T1, T2, s));
     } else {
       // U = u + tau sum_j w_j e^{theta_j tau A} F(u)
       StencilArgs f = stencil_args(op, u, true);
@@ -772,7 +869,7 @@ mm_status erk_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* st
         ins[j] = F0;
         fidx[j] = j + 1;
       }
-      HIPCHK(ctx, grouped_action(op, q, ins, fidx, op->f3_stage1, U, u, 1.0, T1, T2, s));
+      HIPCHK(ctx, grouped_action(op, q, ins, fidx, stacked(op, 1), U, u, 1.0, T1, T2, s));
     }
     // D = g(U) - g0;  u+ = U + tau/2 sum_j w_j e^{theta_j tau A} D
     StencilArgs b = stencil_args(op, U, false);
@@ -783,8 +880,15 @@ mm_status erk_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* st
       ins[j] = D;
       fidx[j] = j + 1;
     }
-    HIPCHK(ctx, grouped_action(op, q, ins, fidx, op->f3_stage2, u, U, 1.0, T1, T2, s));
+    HIPCHK(ctx, grouped_action(op, q, ins, fidx, stacked(op, 2), u, U, 1.0, T1, T2, s));
   }
+  return MM_OK;
+}
+
+mm_status mm_synchronize(mm_ctx* ctx) {
+  if (!ctx) return MM_EINVAL;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipDeviceSynchronize());
   return MM_OK;
 }
 

@@ -13,19 +13,21 @@
 // operand are dispatched to the same XCD (workgroups are dealt round-robin over the
 // eight XCDs, each with its own L2).
 //
-// Precisions (operands are FP64 in memory in every mode; conversion happens while
-// staging into LDS):
-//   FP64   v_mfma_f64_16x16x4 with FP64 accumulation.
-//   FP32   operands rounded to FP32, v_mfma_f32_16x16x4, each 16-long K-chunk summed
-//          in FP32 and added into FP64 accumulators.
-//   BF16xS operands split into S BF16 slices (x = s0 + s1 [+ s2], each the nearest-even
-//          BF16 of the remaining residual); all slice products s_i s_j with i + j < S on
-//          v_mfma_f32_16x16x32_bf16, FP32 accumulation per 32-long K-chunk, chunk sums
-//          added into FP32 accumulators.
+// Precisions:
+//   FP64   v_mfma_f64_16x16x4 with FP64 accumulation; all operands FP64.
+//   FP32   factor pre-rounded to FP32 at setup, grid operand rounded to FP32 (nearest
+//          even) while staging, v_mfma_f32_16x16x4 with FP32 accumulation.
+//   BF16xS factor pre-split at setup, grid operand split while staging into S BF16
+//          slices (x = s0 + s1 [+ s2], each the nearest-even BF16 of the remaining
+//          residual); all slice products s_i s_j with i + j < S on
+//          v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
+// In the mixed modes the grid operand may be FP32 or FP64 in memory and C may be
+// written as FP32 (intermediate passes) or FP64 (last pass of an action).
 #include "mm_internal.h"
 
 namespace mm {
 
+typedef double d2 __attribute__((ext_vector_type(2)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -51,60 +53,26 @@ __device__ __forceinline__ void decode_tile(const GemmArgs& p, int P, int& g, in
   n0 = tn * NT;
 }
 
+template <typename TOut>
+__device__ __forceinline__ void store_out(TOut* C, const double* Cadd, int idx, double v, double beta) {
+  if (Cadd) v += beta * Cadd[idx];
+  C[idx] = (TOut)v;
+}
+
 // ------------------------------------------------------------------------------------
-// FP64 and FP32: v_mfma_*_16x16x4. K-chunk of 16; within a chunk the four lane groups
-// g = lane/16 take k = 4g + s at MFMA step s, so A and B use one consistent permutation.
+// FP64: v_mfma_f64_16x16x4. K-chunk of 16; within a chunk the four lane groups
+// g = lane/16 take k = 4g + s at MFMA step s, so A and B use one consistent
+// permutation. Rows of A (and of B' when it is read along k) sit in LDS as [row][k]
+// and a lane reads two k values of a fragment row with one 16-byte access; the grid
+// operand of modes 2/3 stays in its [k][n] order in LDS (pitch 132 doubles: a wave's
+// four k rows of sixteen n hit every bank exactly twice) and is read one value at a
+// time. Global loads are branch-free: out-of-range rows of A or B' are clamped into
+// the matrix (they only feed outputs that are masked at the store) and only the last
+// K-chunk zeroes k >= K.
 // ------------------------------------------------------------------------------------
 constexpr int KC4 = 16;
-constexpr int P4 = KC4 + 1;  // LDS row pitch (elements), odd to spread banks
-
-template <typename T, int BT>
-struct Stage4 {
-  // global -> registers for one 128 x 16 tile of A (rows m0.., k0..) and B'
-  __device__ __forceinline__ static void loadA(double (&ra)[8], const double* __restrict__ A, int lda,
-                                               int m0, int M, int k0, int K, int tid) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = i * THREADS + tid;
-      const int row = e >> 4, kk = e & 15;
-      const int m = m0 + row, k = k0 + kk;
-      ra[i] = (m < M && k < K) ? A[m * lda + k] : 0.0;
-    }
-  }
-  __device__ __forceinline__ static void loadB(double (&rb)[8], const double* __restrict__ B, int ldb,
-                                               int n0, int N, int k0, int K, int tid) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = i * THREADS + tid;
-      if (BT) {
-        const int kk = e >> 7, nn = e & 127;
-        const int n = n0 + nn, k = k0 + kk;
-        rb[i] = (n < N && k < K) ? B[k * ldb + n] : 0.0;
-      } else {
-        const int row = e >> 4, kk = e & 15;
-        const int n = n0 + row, k = k0 + kk;
-        rb[i] = (n < N && k < K) ? B[n * ldb + k] : 0.0;
-      }
-    }
-  }
-  __device__ __forceinline__ static void storeA(T* s, const double (&ra)[8], int tid) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = i * THREADS + tid;
-      s[(e >> 4) * P4 + (e & 15)] = (T)ra[i];
-    }
-  }
-  __device__ __forceinline__ static void storeB(T* s, const double (&rb)[8], int tid) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = i * THREADS + tid;
-      if (BT)
-        s[(e & 127) * P4 + (e >> 7)] = (T)rb[i];
-      else
-        s[(e >> 4) * P4 + (e & 15)] = (T)rb[i];
-    }
-  }
-};
+constexpr int P64 = KC4 + 2;   // [row][k] pitch in doubles (144 B: 16-byte aligned rows)
+constexpr int PKN = NT + 4;    // [k][n] pitch in doubles (8*PKN = 32 mod 64 banks)
 
 template <int BT>
 __global__ __launch_bounds__(THREADS, 2) void gemm_f64(GemmArgs p) {
@@ -113,18 +81,18 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_f64(GemmArgs p) {
   if (P >= p.total) return;
   int g, b, m0, n0;
   decode_tile(p, P, g, b, m0, n0);
-  const double* __restrict__ A = p.A[g] + b * p.sA;
-  const double* __restrict__ B = p.B[g] + b * p.sB;
-  double* __restrict__ C = p.C[g] + b * p.sC;
+  const double* __restrict__ A = (const double*)p.A[g] + b * p.sA;
+  const double* __restrict__ B = (const double*)p.B[g] + b * p.sB;
+  double* __restrict__ C = (double*)p.C[g] + b * p.sC;
   const double* __restrict__ Cadd = p.Cadd[g] ? p.Cadd[g] + b * p.sC : nullptr;
 
-  __shared__ double As[2][MT * P4];
-  __shared__ double Bs[2][NT * P4];
-  using S = Stage4<double, BT>;
+  constexpr int BSZ = BT ? KC4 * PKN : NT * P64;
+  __shared__ __attribute__((aligned(16))) double As[2][MT * P64];
+  __shared__ __attribute__((aligned(16))) double Bs[2][BSZ];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int lg = lane >> 4, lr = lane & 15;
-  const int M = p.M, N = p.N, K = p.K;
+  const int M = p.M, N = p.N, K = p.K, lda = p.lda, ldb = p.ldb;
 
   d4 acc[4][4];
 #pragma unroll
@@ -132,39 +100,69 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_f64(GemmArgs p) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
+  // element e = i*256 + tid of a tile: A and B' read along k: row = e/16 = 16i + tid/16,
+  // k = tid%16;  B' read along n: k = e/128 = 2i + tid/128, n = tid%128
+  const int r16 = tid >> 4, k16 = tid & 15;
+  const int nB = min(n0 + (tid & 127), N - 1), kB = tid >> 7;
   double ra[8], rb[8];
-  S::loadA(ra, A, p.lda, m0, M, 0, K, tid);
-  S::loadB(rb, B, p.ldb, n0, N, 0, K, tid);
-  S::storeA(As[0], ra, tid);
-  S::storeB(Bs[0], rb, tid);
+  // loads are unconditional (clamped indices, unsigned 32-bit offsets from the uniform
+  // base) so that the eight loads of a chunk stay in flight through the MFMA phase;
+  // k >= K (last chunk only) is zeroed when the registers are written to LDS
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const unsigned arow = (unsigned)min(m0 + 16 * i + r16, M - 1);
+      const int kb = BT ? 2 * i + kB : k16;
+      const unsigned brow = (unsigned)(BT ? nB : min(n0 + 16 * i + r16, N - 1));
+      const unsigned ka = (unsigned)min(k0 + k16, K - 1), kbb = (unsigned)min(k0 + kb, K - 1);
+      ra[i] = A[arow * (unsigned)lda + ka];
+      rb[i] = BT ? B[kbb * (unsigned)ldb + brow] : B[brow * (unsigned)ldb + kbb];
+    }
+  };
+  auto store = [&](double* as, double* bs, int k0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = i * THREADS + tid;
+      const int kb = BT ? 2 * i + kB : k16;
+      as[(e >> 4) * P64 + (e & 15)] = (k0 + k16 < K) ? ra[i] : 0.0;
+      const double y = (k0 + kb < K) ? rb[i] : 0.0;
+      if (BT)
+        bs[(e >> 7) * PKN + (e & 127)] = y;
+      else
+        bs[(e >> 4) * P64 + (e & 15)] = y;
+    }
+  };
+  load(0);
+  store(As[0], Bs[0], 0);
   __syncthreads();
   const int nch = (K + KC4 - 1) / KC4;
   for (int c = 0; c < nch; ++c) {
     const int cur = c & 1;
-    if (c + 1 < nch) {
-      S::loadA(ra, A, p.lda, m0, M, (c + 1) * KC4, K, tid);
-      S::loadB(rb, B, p.ldb, n0, N, (c + 1) * KC4, K, tid);
-    }
+    if (c + 1 < nch) load((c + 1) * KC4);
     const double* as = As[cur];
     const double* bs = Bs[cur];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int kk = 4 * lg + s;
-      double av[4], bv[4];
+    for (int h = 0; h < 2; ++h) {   // k = 4g + 2h + {0, 1}
+      d2 af[4], bf[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = as[(wm + 16 * i + lr) * P4 + kk];
+      for (int i = 0; i < 4; ++i) {
+        af[i] = *reinterpret_cast<const d2*>(as + (wm + 16 * i + lr) * P64 + 4 * lg + 2 * h);
+        if (BT) {
+          const double* q = bs + (4 * lg + 2 * h) * PKN + wn + 16 * i + lr;
+          bf[i] = d2{q[0], q[PKN]};
+        } else {
+          bf[i] = *reinterpret_cast<const d2*>(bs + (wn + 16 * i + lr) * P64 + 4 * lg + 2 * h);
+        }
+      }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = bs[(wn + 16 * j + lr) * P4 + kk];
+      for (int s = 0; s < 2; ++s)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
     }
-    if (c + 1 < nch) {
-      S::storeA(As[cur ^ 1], ra, tid);
-      S::storeB(Bs[cur ^ 1], rb, tid);
-    }
+    if (c + 1 < nch) store(As[cur ^ 1], Bs[cur ^ 1], (c + 1) * KC4);
     __syncthreads();
   }
   // f64 16x16 layout: lane l, element t holds row 4t + l/16, column l%16
@@ -177,84 +175,117 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_f64(GemmArgs p) {
       for (int t = 0; t < 4; ++t) {
         const int m = m0 + wm + 16 * i + 4 * t + lg;
         const int n = n0 + wn + 16 * j + lr;
-        if (m < M && n < N) {
-          double v = alpha * acc[i][j][t];
-          if (Cadd) v += beta * Cadd[m * p.ldc + n];
-          C[m * p.ldc + n] = v;
-        }
+        if (m < M && n < N) store_out<double>(C, Cadd, m * p.ldc + n, alpha * acc[i][j][t], beta);
       }
 }
 
-template <int BT>
-__global__ __launch_bounds__(THREADS, 1) void gemm_f32(GemmArgs p) {
+// ------------------------------------------------------------------------------------
+// FP32: same K permutation as FP64; the pre-converted factor arrives as 16-byte vectors
+// of four k values, the grid operand as runs of eight k values per thread.
+// ------------------------------------------------------------------------------------
+constexpr int P32 = KC4 + 4;  // LDS row pitch in floats (80 B: 16-byte aligned rows)
+
+template <int BT, typename TIn, typename TOut>
+__global__ __launch_bounds__(THREADS, 2) void gemm_f32(GemmArgs p) {
   const int L = blockIdx.x;
   const int P = (L & 7) * p.per_xcd + (L >> 3);
   if (P >= p.total) return;
   int g, b, m0, n0;
   decode_tile(p, P, g, b, m0, n0);
-  const double* __restrict__ A = p.A[g] + b * p.sA;
-  const double* __restrict__ B = p.B[g] + b * p.sB;
-  double* __restrict__ C = p.C[g] + b * p.sC;
+  // factor: A (BT) or B' (!BT), float rows of stride ld = fac_ld(K)
+  const float* __restrict__ F = BT ? (const float*)p.A[g] + b * p.sA : (const float*)p.B[g] + b * p.sB;
+  const TIn* __restrict__ V = BT ? (const TIn*)p.B[g] + b * p.sB : (const TIn*)p.A[g] + b * p.sA;
+  TOut* __restrict__ C = (TOut*)p.C[g] + b * p.sC;
   const double* __restrict__ Cadd = p.Cadd[g] ? p.Cadd[g] + b * p.sC : nullptr;
+  const int M = p.M, N = p.N, K = p.K;
+  const int ldf = BT ? p.lda : p.ldb;           // factor row stride (padded)
+  const int ldv = BT ? p.ldb : p.lda;           // grid operand stride
+  const int fr0 = BT ? m0 : n0, frows = BT ? M : N;   // factor rows of this tile
+  const int vr0 = BT ? n0 : m0, vrows = BT ? N : M;   // grid rows (n for BT, m otherwise)
 
-  __shared__ float As[2][MT * P4];
-  __shared__ float Bs[2][NT * P4];
-  using S = Stage4<float, BT>;
+  __shared__ __attribute__((aligned(16))) float Fs[2][128 * P32];
+  __shared__ __attribute__((aligned(16))) float Vs[2][128 * P32];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int lg = lane >> 4, lr = lane & 15;
-  const int M = p.M, N = p.N, K = p.K;
 
-  d4 acc[4][4];
+  f4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  double ra[8], rb[8];
-  S::loadA(ra, A, p.lda, m0, M, 0, K, tid);
-  S::loadB(rb, B, p.ldb, n0, N, 0, K, tid);
-  S::storeA(As[0], ra, tid);
-  S::storeB(Bs[0], rb, tid);
+  f4 rf[2];
+  TIn rv[8];
+  // factor: 128 rows x 16 k = 512 float4, two per thread (rows clamped into range)
+  int foff[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = h * THREADS + tid;
+    foff[h] = min(fr0 + (e >> 2), frows - 1) * ldf + (e & 3) * 4;
+  }
+  // grid: BT: lanes take consecutive n, a run of eight k per thread;
+  //       !BT: lanes take consecutive k (coalesced rows), eight rows per thread
+  int voff[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (BT)
+      voff[j] = ((tid >> 7) * 8 + j) * ldv + min(vr0 + (tid & 127), vrows - 1);
+    else
+      voff[j] = min(vr0 + (tid >> 4) + 16 * j, vrows - 1) * ldv + (tid & 15);
+  }
+  auto vk_of = [&](int j) { return BT ? (tid >> 7) * 8 + j : (tid & 15); };
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) rf[h] = *reinterpret_cast<const f4*>(F + foff[h] + k0);
+    // unconditional loads (k clamped); conversion and the k >= K zeroing happen at the
+    // LDS store so that the loads stay in flight through the MFMA phase
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int kk = vk_of(j);
+      const int kc = min(k0 + kk, K - 1) - kk;
+      rv[j] = V[(unsigned)(voff[j] + kc * (BT ? ldv : 1))];
+    }
+  };
+  auto cv = [&](int j, int k0) -> float { return (k0 + vk_of(j) < K) ? (float)rv[j] : 0.f; };
+  auto store = [&](float* fs, float* vs, int k0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = h * THREADS + tid;
+      *reinterpret_cast<f4*>(fs + (e >> 2) * P32 + (e & 3) * 4) = rf[h];
+    }
+    if (BT) {
+      const int vrow = tid & 127, vk = (tid >> 7) * 8;
+      *reinterpret_cast<f4*>(vs + vrow * P32 + vk) = f4{cv(0, k0), cv(1, k0), cv(2, k0), cv(3, k0)};
+      *reinterpret_cast<f4*>(vs + vrow * P32 + vk + 4) = f4{cv(4, k0), cv(5, k0), cv(6, k0), cv(7, k0)};
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) vs[((tid >> 4) + 16 * j) * P32 + (tid & 15)] = cv(j, k0);
+    }
+  };
+  load(0);
+  store(Fs[0], Vs[0], 0);
   __syncthreads();
   const int nch = (K + KC4 - 1) / KC4;
   for (int c = 0; c < nch; ++c) {
     const int cur = c & 1;
-    if (c + 1 < nch) {
-      S::loadA(ra, A, p.lda, m0, M, (c + 1) * KC4, K, tid);
-      S::loadB(rb, B, p.ldb, n0, N, (c + 1) * KC4, K, tid);
+    if (c + 1 < nch) load((c + 1) * KC4);
+    const float* as = BT ? Fs[cur] : Vs[cur];
+    const float* bs = BT ? Vs[cur] : Fs[cur];
+    f4 af[4], bf[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      af[i] = *reinterpret_cast<const f4*>(as + (wm + 16 * i + lr) * P32 + 4 * lg);
+      bf[i] = *reinterpret_cast<const f4*>(bs + (wn + 16 * i + lr) * P32 + 4 * lg);
     }
-    const float* as = As[cur];
-    const float* bs = Bs[cur];
-    f4 part[4][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) part[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int kk = 4 * lg + s;
-      float av[4], bv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = as[(wm + 16 * i + lr) * P4 + kk];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = bs[(wn + 16 * j + lr) * P4 + kk];
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], part[i][j], 0, 0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc[i][j][t] += (double)part[i][j][t];
-    if (c + 1 < nch) {
-      S::storeA(As[cur ^ 1], ra, tid);
-      S::storeB(Bs[cur ^ 1], rb, tid);
-    }
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
+    if (c + 1 < nch) store(Fs[cur ^ 1], Vs[cur ^ 1], (c + 1) * KC4);
     __syncthreads();
   }
   // f32 16x16 layout: lane l, element t holds row 4(l/16) + t, column l%16
@@ -267,51 +298,52 @@ __global__ __launch_bounds__(THREADS, 1) void gemm_f32(GemmArgs p) {
       for (int t = 0; t < 4; ++t) {
         const int m = m0 + wm + 16 * i + 4 * lg + t;
         const int n = n0 + wn + 16 * j + lr;
-        if (m < M && n < N) {
-          double v = alpha * acc[i][j][t];
-          if (Cadd) v += beta * Cadd[m * p.ldc + n];
-          C[m * p.ldc + n] = v;
-        }
+        if (m < M && n < N) store_out<TOut>(C, Cadd, m * p.ldc + n, alpha * (double)acc[i][j][t], beta);
       }
 }
 
 // ------------------------------------------------------------------------------------
-// Split BF16: K-chunk of 32 (one v_mfma_f32_16x16x32_bf16 per tile and product). LDS
-// holds S slices of each operand, rows of 32 k (+8 pad) so that lane group g reads its
+// Split BF16: K-chunk of 32 (one v_mfma_f32_16x16x32_bf16 per tile and slice product).
+// LDS holds S slices of each operand in rows of 32 k (+8 pad); lane group g reads its
 // eight consecutive k (8g .. 8g+7) as one 16-byte access.
 // ------------------------------------------------------------------------------------
 constexpr int KCB = 32;
 constexpr int PB = 40;
 
 template <int S>
-__device__ __forceinline__ void split_bf16(double x, __bf16 (&out)[S]) {
-  double rem = x;
+__device__ __forceinline__ void split_bf16(float x, __bf16 (&out)[S]) {
+  float rem = x;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const __bf16 h = (__bf16)(float)rem;
+    const __bf16 h = (__bf16)rem;
     out[s] = h;
-    rem -= (double)(float)h;
+    rem -= (float)h;   // exact: rem and h agree in their leading bits
   }
 }
 
-template <int BT, int S>
+template <int BT, int S, typename TIn, typename TOut>
 __global__ __launch_bounds__(THREADS, 2) void gemm_bf16(GemmArgs p) {
   const int L = blockIdx.x;
   const int P = (L & 7) * p.per_xcd + (L >> 3);
   if (P >= p.total) return;
   int g, b, m0, n0;
   decode_tile(p, P, g, b, m0, n0);
-  const double* __restrict__ A = p.A[g] + b * p.sA;
-  const double* __restrict__ B = p.B[g] + b * p.sB;
-  double* __restrict__ C = p.C[g] + b * p.sC;
+  const __bf16* __restrict__ F = BT ? (const __bf16*)p.A[g] + b * p.sA : (const __bf16*)p.B[g] + b * p.sB;
+  const TIn* __restrict__ V = BT ? (const TIn*)p.B[g] + b * p.sB : (const TIn*)p.A[g] + b * p.sA;
+  TOut* __restrict__ C = (TOut*)p.C[g] + b * p.sC;
   const double* __restrict__ Cadd = p.Cadd[g] ? p.Cadd[g] + b * p.sC : nullptr;
+  const int M = p.M, N = p.N, K = p.K;
+  const int ldf = BT ? p.lda : p.ldb;
+  const int ldv = BT ? p.ldb : p.lda;
+  const int fr0 = BT ? m0 : n0, frows = BT ? M : N;
+  const int vr0 = BT ? n0 : m0, vrows = BT ? N : M;
+  const int64_t fsl = p.fac_slice;
 
-  __shared__ __attribute__((aligned(16))) __bf16 As[S][MT * PB];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[S][NT * PB];
+  __shared__ __attribute__((aligned(16))) __bf16 Fs[S][128 * PB];
+  __shared__ __attribute__((aligned(16))) __bf16 Vs[S][128 * PB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int lg = lane >> 4, lr = lane & 15;
-  const int M = p.M, N = p.N, K = p.K;
 
   f4 acc[4][4];
 #pragma unroll
@@ -319,69 +351,69 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_bf16(GemmArgs p) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  // each thread stages two runs of 8 consecutive k for A and for B'
-  double ra[2][8], rb[2][8];
+  bf8 rf[S][2];
+  TIn rv[16];
+  int foff[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = h * THREADS + tid;
+    foff[h] = min(fr0 + (e >> 2), frows - 1) * ldf + (e & 3) * 8;
+  }
+  // grid: BT: lanes take consecutive n, a run of sixteen k per thread;
+  //       !BT: lanes take consecutive k (coalesced rows), sixteen rows per thread
+  int voff[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    if (BT)
+      voff[j] = ((tid >> 7) * 16 + j) * ldv + min(vr0 + (tid & 127), vrows - 1);
+    else
+      voff[j] = min(vr0 + (tid >> 5) + 8 * j, vrows - 1) * ldv + (tid & 31);
+  }
   auto load = [&](int k0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int e = h * THREADS + tid;
-      {  // A: row = e/4, k run = 8*(e%4)
-        const int row = e >> 2, k8 = (e & 3) * 8;
-        const int m = m0 + row;
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int k = k0 + k8 + j;
-          ra[h][j] = (m < M && k < K) ? A[m * p.lda + k] : 0.0;
-        }
-      }
-      if (BT) {  // B'[n][k] = B[k*ldb + n]: lanes take consecutive n
-        const int nn = e & 127, k8 = (e >> 7) * 8;
-        const int n = n0 + nn;
+      for (int s = 0; s < S; ++s) rf[s][h] = *reinterpret_cast<const bf8*>(F + s * fsl + foff[h] + k0);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int k = k0 + k8 + j;
-          rb[h][j] = (n < N && k < K) ? B[k * p.ldb + n] : 0.0;
-        }
-      } else {
-        const int row = e >> 2, k8 = (e & 3) * 8;
-        const int n = n0 + row;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int k = k0 + k8 + j;
-          rb[h][j] = (n < N && k < K) ? B[n * p.ldb + k] : 0.0;
-        }
-      }
+    for (int j = 0; j < 16; ++j) {
+      const int kk = BT ? (tid >> 7) * 16 + j : (tid & 31);
+      const int kc = min(k0 + kk, K - 1) - kk;
+      rv[j] = V[(unsigned)(voff[j] + kc * (BT ? ldv : 1))];
     }
   };
-  auto store = [&]() {
+  auto cv = [&](int j, int k0) -> float {
+    const int kk = BT ? (tid >> 7) * 16 + j : (tid & 31);
+    return (k0 + kk < K) ? (float)rv[j] : 0.f;
+  };
+  auto store = [&](int k0) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int e = h * THREADS + tid;
-      bf8 va[S], vb[S];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        __bf16 sa[S], sb[S];
-        split_bf16<S>(ra[h][j], sa);
-        split_bf16<S>(rb[h][j], sb);
+      for (int s = 0; s < S; ++s) *reinterpret_cast<bf8*>(&Fs[s][(e >> 2) * PB + (e & 3) * 8]) = rf[s][h];
+    }
+    if (BT) {
+      const int vrow = tid & 127, vk = (tid >> 7) * 16;
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-          va[s][j] = sa[s];
-          vb[s][j] = sb[s];
+      for (int half = 0; half < 2; ++half) {
+        bf8 v[S];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          __bf16 sl[S];
+          split_bf16<S>(cv(8 * half + j, k0), sl);
+#pragma unroll
+          for (int s = 0; s < S; ++s) v[s][j] = sl[s];
         }
-      }
-      const int rowA = e >> 2, kA = (e & 3) * 8;
-      int rowB, kB;
-      if (BT) {
-        rowB = e & 127;
-        kB = (e >> 7) * 8;
-      } else {
-        rowB = e >> 2;
-        kB = (e & 3) * 8;
-      }
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        *reinterpret_cast<bf8*>(&As[s][rowA * PB + kA]) = va[s];
-        *reinterpret_cast<bf8*>(&Bs[s][rowB * PB + kB]) = vb[s];
+        for (int s = 0; s < S; ++s) *reinterpret_cast<bf8*>(&Vs[s][vrow * PB + vk + 8 * half]) = v[s];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        __bf16 sl[S];
+        split_bf16<S>(cv(j, k0), sl);
+#pragma unroll
+        for (int s = 0; s < S; ++s) Vs[s][((tid >> 5) + 8 * j) * PB + (tid & 31)] = sl[s];
       }
     }
   };
@@ -389,29 +421,32 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_bf16(GemmArgs p) {
   const int nch = (K + KCB - 1) / KCB;
   load(0);
   for (int c = 0; c < nch; ++c) {
-    store();
+    store(c * KCB);
     __syncthreads();
     if (c + 1 < nch) load((c + 1) * KCB);
-    bf8 av[S][4], bv[S][4];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
+    for (int sa = 0; sa < S; ++sa) {
+      bf8 af[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        av[s][i] = *reinterpret_cast<const bf8*>(&As[s][(wm + 16 * i + lr) * PB + 8 * lg]);
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        bv[s][j] = *reinterpret_cast<const bf8*>(&Bs[s][(wn + 16 * j + lr) * PB + 8 * lg]);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-#pragma unroll
-        for (int sa = 0; sa < S; ++sa)
-#pragma unroll
-          for (int sb = 0; sb + sa < S; ++sb)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[sa][i], bv[sb][j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < 4; ++i) {
+        const __bf16* base = BT ? &Fs[sa][0] : &Vs[sa][0];
+        af[i] = *reinterpret_cast<const bf8*>(base + (wm + 16 * i + lr) * PB + 8 * lg);
       }
+#pragma unroll
+      for (int sb = 0; sa + sb < S; ++sb) {
+        bf8 bfr[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const __bf16* base = BT ? &Vs[sb][0] : &Fs[sb][0];
+          bfr[j] = *reinterpret_cast<const bf8*>(base + (wn + 16 * j + lr) * PB + 8 * lg);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      }
+    }
     __syncthreads();
   }
   const double alpha = p.alpha, beta = p.beta;
@@ -423,12 +458,70 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_bf16(GemmArgs p) {
       for (int t = 0; t < 4; ++t) {
         const int m = m0 + wm + 16 * i + 4 * lg + t;
         const int n = n0 + wn + 16 * j + lr;
-        if (m < M && n < N) {
-          double v = alpha * (double)acc[i][j][t];
-          if (Cadd) v += beta * Cadd[m * p.ldc + n];
-          C[m * p.ldc + n] = v;
-        }
+        if (m < M && n < N) store_out<TOut>(C, Cadd, m * p.ldc + n, alpha * (double)acc[i][j][t], beta);
       }
+}
+
+// ------------------------------------------------------------------------------------
+// factor pre-conversion for the mixed modes
+// ------------------------------------------------------------------------------------
+int factor_slices(int prec) { return prec == MM_BF16X3 ? 2 : prec == MM_BF16X6 ? 3 : 1; }
+
+__global__ void convert_factor_f32(float* dst, const double* src, int rows, int k, int lds, int ldd) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)rows * ldd) return;
+  const int r = (int)(e / ldd), c = (int)(e % ldd);
+  dst[e] = (c < k) ? (float)src[(int64_t)r * lds + c] : 0.f;
+}
+
+template <int S>
+__global__ void convert_factor_bf16(__bf16* dst, const double* src, int rows, int k, int lds, int ldd) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t cnt = (int64_t)rows * ldd;
+  if (e >= cnt) return;
+  const int r = (int)(e / ldd), c = (int)(e % ldd);
+  double rem = (c < k) ? src[(int64_t)r * lds + c] : 0.0;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const __bf16 h = (__bf16)(float)rem;
+    dst[s * cnt + e] = h;
+    rem -= (double)(float)h;
+  }
+}
+
+hipError_t launch_convert_factor(int prec, void* dst, const double* src, int rows, int k, int lds,
+                                 hipStream_t s) {
+  const int ldd = fac_ld(k);
+  const int64_t cnt = (int64_t)rows * ldd;
+  const unsigned blocks = (unsigned)((cnt + 255) / 256);
+  switch (prec) {
+    case MM_FP32: convert_factor_f32<<<blocks, 256, 0, s>>>((float*)dst, src, rows, k, lds, ldd); break;
+    case MM_BF16X3: convert_factor_bf16<2><<<blocks, 256, 0, s>>>((__bf16*)dst, src, rows, k, lds, ldd); break;
+    case MM_BF16X6: convert_factor_bf16<3><<<blocks, 256, 0, s>>>((__bf16*)dst, src, rows, k, lds, ldd); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+template <int BT>
+hipError_t launch_mixed(int prec, GemmArgs& g, dim3 grid, dim3 block, hipStream_t s) {
+  const int io = (g.in_f32 ? 1 : 0) | (g.out_f32 ? 2 : 0);
+#define MM_LAUNCH_IO(KERNEL, ...)                                                     \
+  switch (io) {                                                                     \
+    case 0: KERNEL<__VA_ARGS__, double, double><<<grid, block, 0, s>>>(g); break;   \
+    case 1: KERNEL<__VA_ARGS__, float, double><<<grid, block, 0, s>>>(g); break;    \
+    case 2: KERNEL<__VA_ARGS__, double, float><<<grid, block, 0, s>>>(g); break;    \
+    default: KERNEL<__VA_ARGS__, float, float><<<grid, block, 0, s>>>(g); break;    \
+  }
+  switch (prec) {
+    case MM_FP32: MM_LAUNCH_IO(gemm_f32, BT) break;
+    case MM_BF16X3: MM_LAUNCH_IO(gemm_bf16, BT, 2) break;
+    case MM_BF16X6: MM_LAUNCH_IO(gemm_bf16, BT, 3) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef MM_LAUNCH_IO
+  return hipGetLastError();
 }
 
 hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s) {
@@ -439,6 +532,11 @@ hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s) {
   if ((int64_t)g.M * g.lda >= lim || (int64_t)g.M * g.ldc >= lim ||
       (int64_t)(g.b_trans ? g.K : g.N) * g.ldb >= lim)
     return hipErrorInvalidValue;
+  if (prec != MM_FP64) {
+    // the pre-converted factor must have its padded row stride
+    const int ldf = g.b_trans ? g.lda : g.ldb;
+    if (ldf < fac_ld(g.K) || ldf % kFacPad != 0) return hipErrorInvalidValue;
+  }
   g.tiles_m = (g.M + MT - 1) / MT;
   g.tiles_n = (g.N + NT - 1) / NT;
   const int64_t total = (int64_t)g.tiles_m * g.tiles_n * g.inner * g.groups;
@@ -446,27 +544,13 @@ hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s) {
   g.total = (int)total;
   g.per_xcd = (g.total + 7) / 8;
   const dim3 grid(8 * g.per_xcd), block(THREADS);
-  switch (prec) {
-    case MM_FP64:
-      if (g.b_trans) gemm_f64<1><<<grid, block, 0, s>>>(g);
-      else gemm_f64<0><<<grid, block, 0, s>>>(g);
-      break;
-    case MM_FP32:
-      if (g.b_trans) gemm_f32<1><<<grid, block, 0, s>>>(g);
-      else gemm_f32<0><<<grid, block, 0, s>>>(g);
-      break;
-    case MM_BF16X3:
-      if (g.b_trans) gemm_bf16<1, 2><<<grid, block, 0, s>>>(g);
-      else gemm_bf16<0, 2><<<grid, block, 0, s>>>(g);
-      break;
-    case MM_BF16X6:
-      if (g.b_trans) gemm_bf16<1, 3><<<grid, block, 0, s>>>(g);
-      else gemm_bf16<0, 3><<<grid, block, 0, s>>>(g);
-      break;
-    default:
-      return hipErrorInvalidValue;
+  if (prec == MM_FP64) {
+    if (g.in_f32 || g.out_f32) return hipErrorInvalidValue;
+    if (g.b_trans) gemm_f64<1><<<grid, block, 0, s>>>(g);
+    else gemm_f64<0><<<grid, block, 0, s>>>(g);
+    return hipGetLastError();
   }
-  return hipGetLastError();
+  return g.b_trans ? launch_mixed<1>(prec, g, grid, block, s) : launch_mixed<0>(prec, g, grid, block, s);
 }
 
 }  // namespace mm

@@ -13,14 +13,18 @@ namespace mm {
 
 constexpr int kMaxGroups = 8;   // quadrature nodes + 1
 
-// One batched/grouped GEMM  C[g][b] = alpha * A[g][b] . B[g][b]^T-or-not + beta * Cadd[g][b]
+// One batched/grouped GEMM  C[g][b] = alpha * A[g][b] . B'[g][b] + beta * Cadd[g][b]
 // with row-major operands: A[m][k] at m*lda + k; C[m][n] at m*ldc + n;
-// B[n][k] at n*ldb + k (b_trans = 0) or at k*ldb + n (b_trans = 1).
+// B'[n][k] at n*ldb + k (b_trans = 0) or at k*ldb + n (b_trans = 1).
 // Group g selects base pointers; the inner batch index b adds b*s{A,B,C}.
+// FP64 mode: every operand is double. Mixed modes: the factor operand (B' when
+// b_trans = 0, A when b_trans = 1) is pre-converted at setup -- FP32, or S BF16 slices
+// `fac_slice` elements apart -- with its rows zero-padded to a multiple of 32 in k;
+// the grid operand is float (in_f32) or double, C is float (out_f32) or double.
 struct GemmArgs {
-  const double* A[kMaxGroups];
-  const double* B[kMaxGroups];
-  double* C[kMaxGroups];
+  const void* A[kMaxGroups];
+  const void* B[kMaxGroups];
+  void* C[kMaxGroups];
   const double* Cadd[kMaxGroups];
   int M, N, K;
   int lda, ldb, ldc;
@@ -29,9 +33,14 @@ struct GemmArgs {
   int groups;
   int b_trans;
   double alpha, beta;
+  int in_f32, out_f32;
+  int64_t fac_slice;
   // filled by the launcher
   int tiles_m, tiles_n, total, per_xcd;
 };
+
+constexpr int kFacPad = 32;   // k padding of pre-converted factors
+inline int fac_ld(int k) { return (k + kFacPad - 1) / kFacPad * kFacPad; }
 
 // Stencil launch parameters (remainder g and fused stage updates).
 struct StencilArgs {
@@ -46,9 +55,11 @@ struct StencilArgs {
   const double* base0;  // nullable
   double c0;
   double* out0;         // out0 = base0 + c0 * s
+  float* out0f;         // if set, out0 is written here as float instead
   const double* base1;  // nullable
   double c1;
   double* out1;         // nullable: out1 = base1 + c1 * s
+  float* out1f;         // if set, out1 is written here as float instead
   int* flag;            // nullable: set to 1 if out0 is not finite
 };
 
@@ -71,6 +82,12 @@ hipError_t launch_lu_solve(double* Q, double* P, int n, int count, hipStream_t s
 hipError_t launch_place_scaled(double* dst, int ldd, int col0, const double* src, int n, double w,
                                hipStream_t s);
 hipError_t launch_fill(double* dst, double v, int64_t count, hipStream_t s);
+// Pre-convert an FP64 factor (rows x k, leading dim lds) for the mixed modes into
+// dst (rows x fac_ld(k), zero-padded): prec MM_FP32 -> float, MM_BF16X3/X6 -> S BF16
+// slices, slice s at dst + s*rows*fac_ld(k) (elements).
+hipError_t launch_convert_factor(int prec, void* dst, const double* src, int rows, int k, int lds,
+                                 hipStream_t s);
+int factor_slices(int prec);
 
 }  // namespace mm
 
@@ -108,6 +125,11 @@ struct mm_op {
   double* f3_stage1 = nullptr;         // ERK: [E3(1) | tau w_j E3(theta_j)] or [tau w_j E3]
   double* f3_stage2 = nullptr;         // ERK: [tau/2 w_j E3(theta_j)]
   double* f3_phi = nullptr;            // [w_j E3(theta_j)] for mumode_phi1v
+  // mixed modes: pre-converted copies (see GemmArgs), same stacking
+  std::vector<void*> fac_lp;
+  void* f3_stage1_lp = nullptr;
+  void* f3_stage2_lp = nullptr;
+  void* f3_phi_lp = nullptr;
   double* buf[6] = {nullptr};          // scratch
   int64_t buf_len[6] = {0};
   int* flag = nullptr;                 // sticky non-finite flag

@@ -7,57 +7,90 @@
 // lam_amax = 0 and the full velocity the same kernel yields F(u) (Appendix, u' = F(u)).
 // The stage updates of the schemes are fused as out0 = base0 + c0 (g - sub) and
 // out1 = base1 + c1 (g - sub), so each remainder evaluation is one pass over HBM.
-// Threads run along x1 (coalesced); neighbours along x2/x3 come from L2.
 #include <cfloat>
 
 #include "mm_internal.h"
 
 namespace mm {
 
+// Each thread owns one x1 column of a YT (x2) x ZT (x3) patch of grid points and keeps
+// the patch with a one-point halo in registers, so the x2/x3 neighbours of u and a are
+// loaded once per patch instead of once per point; x1 neighbours come from the same
+// cache lines as the neighbouring lanes' centres. A wave covers 64 consecutive x1, so
+// every access is a coalesced row segment. No LDS and no barriers.
+constexpr int SX = 64, SY = 4, YT = 2, ZT = 4;
+
 template <int D>
-__global__ __launch_bounds__(256) void stencil_kernel(StencilArgs p) {
-  const int i1 = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int i2 = blockIdx.y * 4 + (threadIdx.x >> 6);
-  const int i3 = blockIdx.z;
+__global__ __launch_bounds__(SX * SY) void stencil_kernel(StencilArgs p) {
+  constexpr int ZP = (D == 3) ? ZT : 1;   // points per thread along x3
+  const int tx = threadIdx.x & (SX - 1), ty = threadIdx.x / SX;
+  const int i1 = blockIdx.x * SX + tx;
+  const int y0 = (blockIdx.y * SY + ty) * YT;
+  const int z0 = (D == 3) ? blockIdx.z * ZT : 0;
   const int n1 = p.n1, n2 = p.n2, n3 = p.n3;
-  if (i1 >= n1 || i2 >= n2 || i3 >= n3) return;
-  const int s2 = n1, s3 = n1 * n2;                      // strides of u
-  const int t2 = n1 + 2, t3 = (n1 + 2) * (n2 + 2);      // strides of a
-  const int idx = i1 + s2 * i2 + s3 * i3;
-  const int ia = (i1 + 1) + t2 * (i2 + 1) + (D == 3 ? t3 * (i3 + 1) : 0);
+  if (i1 >= n1) return;
+  const int s2 = n1, s3 = n1 * n2;                    // strides of u
+  const int t2 = n1 + 2, t3 = (n1 + 2) * (n2 + 2);    // strides of a (padded)
   const double* __restrict__ u = p.u;
   const double* __restrict__ a = p.a;
-  const double uc = u[idx];
-  const double ac = a[ia];
+  // patch with halo: uu[y][z] holds u at (i1, y0 - 1 + y, z0 - 1 + z); corners unused
+  double uu[YT + 2][ZP + 2], aa[YT + 2][ZP + 2];
+#pragma unroll
+  for (int y = 0; y < YT + 2; ++y)
+#pragma unroll
+    for (int z = 0; z < ZP + 2; ++z) {
+      const int i2 = y0 - 1 + y;
+      const int i3 = (D == 3) ? z0 - 1 + z : 0;
+      const bool need = (D == 3) ? !((y == 0 || y == YT + 1) && (z == 0 || z == ZP + 1)) : (z == 1);
+      const bool uin = need && i2 >= 0 && i2 < n2 && i3 >= 0 && i3 < n3;
+      const bool ain = need && i2 >= -1 && i2 <= n2 && (D == 2 || (i3 >= -1 && i3 <= n3));
+      uu[y][z] = uin ? u[i1 + s2 * i2 + s3 * i3] : 0.0;
+      aa[y][z] = ain ? a[(i1 + 1) + t2 * (i2 + 1) + (D == 3 ? t3 * (i3 + 1) : 0)] : 0.0;
+    }
   const double la = p.lam_amax;
-
-  // axis 1
-  const double um1 = (i1 > 0) ? u[idx - 1] : 0.0;
-  const double up1 = (i1 + 1 < n1) ? u[idx + 1] : 0.0;
-  double g = ((0.5 * (ac + a[ia + 1]) - la) * (up1 - uc) - (0.5 * (ac + a[ia - 1]) - la) * (uc - um1)) * p.ih2[0] +
-             p.cadv[0] * (up1 - um1);
-  // axis 2
-  const double um2 = (i2 > 0) ? u[idx - s2] : 0.0;
-  const double up2 = (i2 + 1 < n2) ? u[idx + s2] : 0.0;
-  g += ((0.5 * (ac + a[ia + t2]) - la) * (up2 - uc) - (0.5 * (ac + a[ia - t2]) - la) * (uc - um2)) * p.ih2[1] +
-       p.cadv[1] * (up2 - um2);
-  if (D == 3) {
-    const double um3 = (i3 > 0) ? u[idx - s3] : 0.0;
-    const double up3 = (i3 + 1 < n3) ? u[idx + s3] : 0.0;
-    g += ((0.5 * (ac + a[ia + t3]) - la) * (up3 - uc) - (0.5 * (ac + a[ia - t3]) - la) * (uc - um3)) * p.ih2[2] +
-         p.cadv[2] * (up3 - um3);
-  }
-  g += p.r0 + uc * (p.r1 + uc * (p.r2 + uc * p.r3));
-  if (p.sub) g -= p.sub[idx];
-  const double o0 = (p.base0 ? p.base0[idx] : 0.0) + p.c0 * g;
-  p.out0[idx] = o0;
-  if (p.out1) p.out1[idx] = (p.base1 ? p.base1[idx] : 0.0) + p.c1 * g;
-  if (p.flag && !(fabs(o0) <= DBL_MAX)) p.flag[0] = 1;
+#pragma unroll
+  for (int y = 1; y <= YT; ++y)
+#pragma unroll
+    for (int z = 1; z <= ZP; ++z) {
+      const int i2 = y0 - 1 + y;
+      const int i3 = (D == 3) ? z0 - 1 + z : 0;
+      if (i2 >= n2 || i3 >= n3) continue;
+      const int idx = i1 + s2 * i2 + s3 * i3;
+      const int ia = (i1 + 1) + t2 * (i2 + 1) + (D == 3 ? t3 * (i3 + 1) : 0);
+      const double uc = uu[y][z], ac = aa[y][z];
+      const double uxm = (i1 > 0) ? u[idx - 1] : 0.0;
+      const double uxp = (i1 + 1 < n1) ? u[idx + 1] : 0.0;
+      const double axm = a[ia - 1], axp = a[ia + 1];
+      double g = ((0.5 * (ac + axp) - la) * (uxp - uc) - (0.5 * (ac + axm) - la) * (uc - uxm)) * p.ih2[0] +
+                 p.cadv[0] * (uxp - uxm);
+      g += ((0.5 * (ac + aa[y + 1][z]) - la) * (uu[y + 1][z] - uc) -
+            (0.5 * (ac + aa[y - 1][z]) - la) * (uc - uu[y - 1][z])) * p.ih2[1] +
+           p.cadv[1] * (uu[y + 1][z] - uu[y - 1][z]);
+      if (D == 3)
+        g += ((0.5 * (ac + aa[y][z + 1]) - la) * (uu[y][z + 1] - uc) -
+              (0.5 * (ac + aa[y][z - 1]) - la) * (uc - uu[y][z - 1])) * p.ih2[2] +
+             p.cadv[2] * (uu[y][z + 1] - uu[y][z - 1]);
+      g += p.r0 + uc * (p.r1 + uc * (p.r2 + uc * p.r3));
+      if (p.sub) g -= p.sub[idx];
+      const double o0 = (p.base0 ? p.base0[idx] : 0.0) + p.c0 * g;
+      if (p.out0f)
+        p.out0f[idx] = (float)o0;
+      else
+        p.out0[idx] = o0;
+      if (p.out1 || p.out1f) {
+        const double o1 = (p.base1 ? p.base1[idx] : 0.0) + p.c1 * g;
+        if (p.out1f)
+          p.out1f[idx] = (float)o1;
+        else
+          p.out1[idx] = o1;
+      }
+      if (p.flag && !(fabs(o0) <= DBL_MAX)) p.flag[0] = 1;
+    }
 }
 
 hipError_t launch_stencil(int d, const StencilArgs& a, hipStream_t s) {
-  const dim3 block(256);
-  const dim3 grid((a.n1 + 63) / 64, (a.n2 + 3) / 4, d == 3 ? a.n3 : 1);
+  const dim3 block(SX * SY);
+  const dim3 grid((a.n1 + SX - 1) / SX, (a.n2 + SY * YT - 1) / (SY * YT), d == 3 ? (a.n3 + ZT - 1) / ZT : 1);
   if (d == 3)
     stencil_kernel<3><<<grid, block, 0, s>>>(a);
   else

@@ -106,9 +106,10 @@ def test_exp_action(mm, ctx, n):
     op = mm.setup_problem(ctx, p)
     out = dev(np.zeros(p.shape))
     mm.mumode_expv(op, dev(V), out)
-    ref = oracle_op(p).expv(1.0, V)
-    assert relerr(host(out), ref) <= FP64_TOL
+    got = host(out)
     op.close()
+    ref = oracle_op(p).expv(1.0, V)
+    assert relerr(got, ref) <= FP64_TOL
 
 
 def test_exp_action_in_place_and_nonsymmetric_factor(mm, ctx):
@@ -162,10 +163,12 @@ def test_steps_match_oracle(mm, ctx, scheme, n, steps, tau):
     op = mm.setup_problem(ctx, p)
     u = dev(p.u0)
     mm.step(op, u, p.steps)
-    assert mm.mm_check(op) == mm.MM_OK
-    ref = S.solve(p)
-    assert relerr(host(u), ref) <= FP64_TOL
+    status = mm.mm_check(op)
+    got = host(u)
     op.close()
+    assert status == mm.MM_OK
+    ref = S.solve(p)
+    assert relerr(got, ref) <= FP64_TOL
 
 
 def test_steps_compose(mm, ctx):
@@ -189,10 +192,12 @@ def test_full_size_one_step(mm, ctx, name):
     op = mm.setup_problem(ctx, p)
     u = dev(p.u0)
     mm.step(op, u, 1)
-    assert mm.mm_check(op) == mm.MM_OK
-    ref = S.solve(p, steps=1)
-    assert relerr(host(u), ref) <= FP64_TOL
+    status = mm.mm_check(op)
+    got = host(u)
     op.close()
+    assert status == mm.MM_OK
+    ref = S.solve(p, steps=1)
+    assert relerr(got, ref) <= FP64_TOL
 
 
 # ------------------------------------------------------------------ errors and flags
