@@ -28,6 +28,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
+DESCRIPTION = {
+    "3d_n255_l2b": "3D Dirichlet ADR 255^3 interior, Lawson2b, tau=1e-3, 100 steps to T=0.1",
+    "3d_n127_l2b": "3D Dirichlet ADR 127^3 interior, Lawson2b, tau=5e-4, 200 steps to T=0.1",
+    "3d_n127_etd2rk": "3D Dirichlet ADR 127^3 interior, ETD2RK with 4-node phi1, tau=5e-4, 200 steps",
+    "3d_n383_etd2rk": "3D Dirichlet ADR 383^3 interior, anisotropic a in (0.01, 2), ETD2RK with 6-node "
+                      "phi1, tau=2e-3, 50 steps",
+    "2d_n63_le": "2D Dirichlet ADR 63^2 interior, Lawson-Euler, tau=1e-3, 100 steps",
+}
 HBM_PEAK = 8.0e12
 WORKLOAD = "3d_n255_l2b"
 
@@ -35,6 +43,7 @@ WORKLOAD = "3d_n255_l2b"
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default=WORKLOAD, help="one of synth.WORKLOADS")
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--modes", default="fp64,fp32,bf16x6,bf16x3")
@@ -42,6 +51,10 @@ def parse():
     ap.add_argument("--latency-reps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--serve", default="fp64,bf16x3",
+                    help="precisions for the served-stream run ('' to skip)")
+    ap.add_argument("--serve-count", type=int, default=512)
+    ap.add_argument("--serve-active", type=int, default=16)
     return ap.parse_args()
 
 
@@ -52,12 +65,12 @@ def time_mode(mm, ctx, p, prec, steps, warmup):
     u = u0.clone()
     stream = torch.cuda.current_stream()
     if warmup:
-        mm.lawson_step(op, u, warmup)
+        mm.step(op, u, warmup)
     u.copy_(u0)
     torch.cuda.synchronize()
     ctx.timing(True)
     t0 = time.perf_counter()
-    mm.lawson_step(op, u, steps, stream)
+    mm.step(op, u, steps, stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kern = {}
@@ -80,12 +93,57 @@ def latency(mm, ctx, op, p, reps):
         u.copy_(u0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        mm.lawson_step(op, u, p.steps)
+        mm.step(op, u, p.steps)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
     lat = np.array(lat) * 1e3
     return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "reps": reps, "steps_per_solve": p.steps}
+
+
+def serve_stream(mm, prec, count, max_active):
+    """The served stream: `count` seeded Lawson2b solves (50% 2D N in {64..512}^2, 50% 3D
+    N in {32..192}^3, beta ~ U[0,20]^d, f = u(1-u) or u^2(1-u), 20-200 steps to T = 0.1)
+    submitted at Poisson arrival times (200/s). Latency = completion - submission on the
+    server clock."""
+    import synth
+    reqs = synth.request_stream(count=count, seed=1)
+    probs = [r.problem() for r in reqs]          # generated before the clock starts
+    srv = mm.Server(0, max_active=max_active)
+    ids = []
+    t0 = time.perf_counter()
+    for r, p in zip(reqs, probs):
+        delay = r.arrival_s - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        st, rid = mm.solve_submit(srv, p, prec=prec)
+        ids.append((rid, p))
+    lat, done, statuses, work = [], [], {}, 0.0
+    t_first = None
+    pending = list(ids)
+    while pending:
+        rest = []
+        for rid, p in pending:
+            st, u, info = mm.solve_poll(srv, rid, p.shape)
+            if st == mm.MM_NOT_READY:
+                rest.append((rid, p))
+                continue
+            statuses[mm.STATUS.get(st, st)] = statuses.get(mm.STATUS.get(st, st), 0) + 1
+            if info:
+                lat.append(info["t_done"] - info["t_submit"])
+                done.append(info["t_done"])
+                t_first = info["t_submit"] if t_first is None else min(t_first, info["t_submit"])
+                work += p.dof * p.steps
+        pending = rest
+        if pending:
+            time.sleep(0.002)
+    srv.close()
+    lat = np.array(lat) * 1e3
+    span = max(done) - t_first
+    return {"requests": count, "max_active": max_active, "status": statuses,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "makespan_s": span,
+            "throughput_mdof_steps_per_s": work / span / 1e6}
 
 
 def cpu_baseline(p, steps):
@@ -103,7 +161,7 @@ def cpu_baseline(p, steps):
     if ctxm is not None:
         ctxm.unregister() if hasattr(ctxm, "unregister") else None
     return {"value": p.dof * steps / dt / 1e6, "unit": "Mdof*steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{steps} Lawson2b steps of the 255^3 workload (numpy FP64, OpenBLAS threads = cores)",
+            "sample": f"{steps} {p.scheme} steps of the {p.name} workload (numpy FP64, OpenBLAS threads = cores)",
             "seconds": dt}
 
 
@@ -116,7 +174,7 @@ def main():
     import paper_2303_15861_amd as mm
     import synth
 
-    p = synth.workload(WORKLOAD)
+    p = synth.workload(args.workload)
     ctx = mm.Context(0)
     modes = [m for m in args.modes.split(",") if m]
     if "fp64" not in modes:
@@ -178,13 +236,21 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}[args.headline],
         "data": "synthetic",
-        "config": {"workload": "3D Dirichlet ADR 255^3 interior, Lawson2b, tau=1e-3, 100 steps to T=0.1",
-                   "dof": p.dof, "scheme": "lawson2b", "headline_mode": args.headline},
+        "config": {"workload": DESCRIPTION.get(args.workload, args.workload),
+                   "dof": p.dof, "scheme": p.scheme, "headline_mode": args.headline},
         "latency": head.get("latency"),
         "modes": {m: {kk: vv for kk, vv in e.items() if kk != "kernels"} for m, e in res.items()},
         "kernels": {m: e["kernels"] for m, e in res.items()},
         "roofline": roof,
     }
+    serving = {}
+    for prec in [m for m in args.serve.split(",") if m]:
+        print(f"[bench] served stream: {args.serve_count} requests, {prec}", file=sys.stderr, flush=True)
+        serving[prec] = serve_stream(mm, prec, args.serve_count, args.serve_active)
+        print(f"[bench] served stream {prec}: p50 {serving[prec]['p50_ms']:.1f} ms "
+              f"p99 {serving[prec]['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    if serving:
+        line["serving"] = serving
     if not args.no_cpu:
         print(f"[bench] cpu baseline: {args.cpu_steps} oracle steps", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)

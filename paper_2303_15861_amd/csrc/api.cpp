@@ -80,6 +80,45 @@ hipError_t gemm_sq(int n, const double* X, const double* Y, double* Z, hipStream
   return launch_gemm(MM_FP64, g, s);
 }
 
+// Q^{-1} P by the Newton-Schulz iteration X <- X (2I - Q X) from X0 = Q^T/(|Q|_1 |Q|_inf)
+// (quadratic convergence once |I - Q X| < 1; Pan and Schreiber, SIAM J. Sci. Stat.
+// Comput. 12(5), 1991), all products on the FP64 MFMA GEMM. The Pade denominator of
+// a matrix with |A|_1 <= theta_13 is well conditioned, so a handful of iterations
+// reach the rounding floor. On success the result overwrites P; Q is never written.
+// X, R, Y are n x n scratch. Returns MM_NOT_READY, with P untouched, if the residual
+// does not fall below 1e-10 within 60 iterations (the caller then uses Gaussian
+// elimination).
+mm_status newton_schulz_solve(mm_ctx* ctx, int n, const double* Q, double* P, double* X, double* R,
+                              double* Y) {
+  hipStream_t st = ctx->stream;
+  double* scal = ctx->reduce_buf;   // two doubles of device scratch
+  double h[2];
+  HIPCHK(ctx, launch_norms(Q, n, scal, st));
+  HIPCHK(ctx, hipMemcpyAsync(h, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  if (!(h[0] > 0.0) || !(h[1] > 0.0) || !std::isfinite(h[0] * h[1])) return MM_NOT_READY;
+  HIPCHK(ctx, launch_scaled_transpose(X, Q, n, 1.0 / (h[0] * h[1]), st));
+  int extra = -1;
+  for (int it = 0; it < 60; ++it) {
+    HIPCHK(ctx, gemm_sq(n, Q, X, R, st));                 // R = Q X
+    HIPCHK(ctx, launch_resid(R, n, scal, st));
+    double res = 0.0;
+    HIPCHK(ctx, hipMemcpyAsync(&res, scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    if (!std::isfinite(res)) return MM_NOT_READY;
+    if (extra < 0 && res < 1e-10) extra = 1;              // one more step reaches the floor
+    else if (extra == 0) break;
+    else if (extra > 0) --extra;
+    HIPCHK(ctx, launch_combo(R, n, -1.0, R, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, 2.0, st));  // 2I - QX
+    HIPCHK(ctx, gemm_sq(n, X, R, Y, st));                 // X (2I - QX)
+    std::swap(X, Y);
+    if (it == 59) return MM_NOT_READY;
+  }
+  HIPCHK(ctx, gemm_sq(n, X, P, Y, st));                   // Q^{-1} P
+  HIPCHK(ctx, hipMemcpyAsync(P, Y, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  return MM_OK;
+}
+
 // exp(T) for the n x n tridiagonal Toeplitz T = tridiag(sub, diag, sup) by the [13/13]
 // Pade approximant with scaling and squaring (Higham, SIAM J. Matrix Anal. Appl. 26(4),
 // 2005): s = max(0, ceil(log2(||T||_1 / theta_13))), X = r_13(T/2^s), then s squarings.
@@ -121,7 +160,12 @@ mm_status pade_expm(mm_ctx* ctx, int n, double sub, double diag, double sup, dou
   // (V - U) X = (V + U): P in A2, Q in A4
   HIPCHK(ctx, launch_combo(A2, n, 1.0, V, 1.0, U, 0.0, nullptr, 0.0, nullptr, 0.0, st));
   HIPCHK(ctx, launch_combo(A4, n, 1.0, V, -1.0, U, 0.0, nullptr, 0.0, nullptr, 0.0, st));
-  HIPCHK(ctx, launch_lu_solve(A4, A2, n, 1, st));
+  mm_status rs = newton_schulz_solve(ctx, n, A4, A2, A6, T1, U);
+  if (rs == MM_NOT_READY) {   // not converged: Gaussian elimination (Q and P are intact)
+    HIPCHK(ctx, launch_lu_solve(A4, A2, n, 1, st));
+  } else if (rs != MM_OK) {
+    return rs;
+  }
   double* X = A2;
   double* Y = A6;
   for (int i = 0; i < s; ++i) {
@@ -135,10 +179,13 @@ mm_status pade_expm(mm_ctx* ctx, int n, double sub, double diag, double sup, dou
   return MM_OK;
 }
 
+// Device memory of ops comes from the stream-ordered pool on the context's stream, so
+// that creating and releasing ops does not synchronise the device (plain hipFree may),
+// which keeps admission in the request server from stalling on running requests.
 template <typename T>
 mm_status dev_alloc(mm_op* op, T** p, int64_t count) {
   const size_t bytes = (size_t)count * sizeof(T);
-  hipError_t e = hipMalloc((void**)p, bytes);
+  hipError_t e = hipMallocAsync((void**)p, bytes, op->ctx->stream);
   if (e != hipSuccess) {
     set_err(op->ctx, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
     *p = nullptr;
@@ -149,6 +196,10 @@ mm_status dev_alloc(mm_op* op, T** p, int64_t count) {
 }
 
 int last_axis(const mm_op* op) { return op->d - 1; }
+
+void dev_free(mm_op* op, void* p) {
+  if (p) hipFreeAsync(p, op->ctx->stream);
+}
 
 // Bracket one launch with events on its stream when the context is timing.
 template <typename F>
@@ -414,6 +465,12 @@ mm_status mm_ctx_create(int device, mm_ctx** out) {
     delete ctx;
     return MM_EDEVICE;
   }
+  // keep freed pool memory for reuse instead of returning it to the driver
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+    uint64_t keep = UINT64_MAX;
+    hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
   ctx->reduce_parts = 1024;
   if (hipMalloc((void**)&ctx->reduce_buf, (ctx->reduce_parts + 1) * sizeof(double)) != hipSuccess) {
     hipStreamDestroy(ctx->stream);
@@ -444,24 +501,24 @@ const char* mm_last_error(const mm_ctx* ctx) {
 
 void mumode_destroy(mm_op* op) {
   if (!op) return;
-  if (op->ctx) {
-    hipSetDevice(op->ctx->device);
-    hipStreamSynchronize(op->ctx->stream);
+  if (!op->ctx) {
+    delete op;
+    return;
   }
-  if (op->a) hipFree(op->a);
+  hipSetDevice(op->ctx->device);
+  dev_free(op, op->a);
   for (size_t i = 0; i < op->fac.size(); ++i)
-    if (op->fac_owned[i] && op->fac[i]) hipFree(op->fac[i]);
-  if (op->f3_stage1) hipFree(op->f3_stage1);
-  if (op->f3_stage2) hipFree(op->f3_stage2);
-  if (op->f3_phi) hipFree(op->f3_phi);
+    if (op->fac_owned[i]) dev_free(op, op->fac[i]);
+  dev_free(op, op->f3_stage1);
+  dev_free(op, op->f3_stage2);
+  dev_free(op, op->f3_phi);
   for (size_t i = 0; i < op->fac_lp.size(); ++i)
-    if (op->fac_owned[i] && op->fac_lp[i]) hipFree(op->fac_lp[i]);
-  if (op->f3_stage1_lp) hipFree(op->f3_stage1_lp);
-  if (op->f3_stage2_lp) hipFree(op->f3_stage2_lp);
-  if (op->f3_phi_lp) hipFree(op->f3_phi_lp);
-  for (int i = 0; i < 6; ++i)
-    if (op->buf[i]) hipFree(op->buf[i]);
-  if (op->flag) hipFree(op->flag);
+    if (op->fac_owned[i]) dev_free(op, op->fac_lp[i]);
+  dev_free(op, op->f3_stage1_lp);
+  dev_free(op, op->f3_stage2_lp);
+  dev_free(op, op->f3_phi_lp);
+  for (int i = 0; i < 6; ++i) dev_free(op, op->buf[i]);
+  dev_free(op, op->flag);
   delete op;
 }
 
@@ -580,7 +637,7 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
   int nmax = 0;
   for (int mu = 0; mu < op->d; ++mu) nmax = std::max(nmax, op->n[mu]);
   double* ws = nullptr;
-  if (hipMalloc((void**)&ws, (size_t)7 * nmax * nmax * sizeof(double)) != hipSuccess) {
+  if (hipMallocAsync((void**)&ws, (size_t)7 * nmax * nmax * sizeof(double), st) != hipSuccess) {
     set_err(ctx, "Pade workspace allocation failed");
     return fail(MM_ENOMEM);
   }
@@ -597,7 +654,7 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     }
     const int n = op->n[mu];
     if ((rc = dev_alloc(op, &op->fac[mu], (int64_t)nf * n * n)) != MM_OK) {
-      hipFree(ws);
+      hipFreeAsync(ws, st);
       return fail(rc);
     }
     op->fac_owned[mu] = true;
@@ -610,18 +667,17 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
       rc = pade_expm(ctx, n, ct * (diff - adv), ct * (-2.0 * diff), ct * (diff + adv),
                      op->fac[mu] + (int64_t)j * n * n, &sq, ws);
       if (rc != MM_OK) {
-        hipFree(ws);
+        hipFreeAsync(ws, st);
         return fail(rc);
       }
       if (j == 0) op->squarings[mu] = sq;
     }
   }
+  hipFreeAsync(ws, st);
   if (hipStreamSynchronize(st) != hipSuccess) {
-    hipFree(ws);
     set_err(ctx, "factor setup failed on the device");
     return fail(MM_EDEVICE);
   }
-  hipFree(ws);
   // mixed modes: FP32 or BF16-slice copies with zero-padded rows
   const int nsl = factor_slices(prec);
   const int64_t esz = (prec == MM_FP32) ? 4 : 2;

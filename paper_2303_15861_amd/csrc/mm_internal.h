@@ -82,6 +82,10 @@ hipError_t launch_lu_solve(double* Q, double* P, int n, int count, hipStream_t s
 hipError_t launch_place_scaled(double* dst, int ldd, int col0, const double* src, int n, double w,
                                hipStream_t s);
 hipError_t launch_fill(double* dst, double v, int64_t count, hipStream_t s);
+// out[0] = ||Q||_1, out[1] = ||Q||_inf (device); X = alpha Q^T; out[0] = max |R - I|
+hipError_t launch_norms(const double* Q, int n, double* out, hipStream_t s);
+hipError_t launch_scaled_transpose(double* X, const double* Q, int n, double alpha, hipStream_t s);
+hipError_t launch_resid(const double* R, int n, double* out, hipStream_t s);
 // Pre-convert an FP64 factor (rows x k, leading dim lds) for the mixed modes into
 // dst (rows x fac_ld(k), zero-padded): prec MM_FP32 -> float, MM_BF16X3/X6 -> S BF16
 // slices, slice s at dst + s*rows*fac_ld(k) (elements).

@@ -1,17 +1,19 @@
 // Continuous-batching request loop over the mu-mode Lawson2b path.
 //
-// A server owns one mm_ctx, a small pool of HIP streams (default priority) and one
-// host thread. solve_submit copies a request into the pending queue. The loop
-//   1. admits pending requests in arrival order while fewer than max_active are
-//      running and the HBM budget covers the request's footprint (operator, factors,
-//      scratch, state); admission runs mumode_setup and uploads u0;
-//   2. enqueues a few Lawson2b steps for every running request, each request on the
-//      stream of its slot, so kernels of different requests overlap on the device;
-//   3. retires requests whose last step has completed (event query, no blocking):
-//      checks the non-finite flag, copies the solution out, releases device memory.
-// Each request runs the same kernels on the same shapes whether it is alone or in a
-// mix, so its result does not depend on the other requests.
-#include <atomic>
+// A server owns a few admission threads and one step thread, each with its own mm_ctx,
+// and a pool of HIP streams (default priority):
+//   admission threads: take submitted requests in arrival order while fewer than
+//     max_active are admitted and the HBM budget covers the request's footprint; uploads
+//     a and u0 and runs mumode_setup (operator, Pade factors) on its own stream, with
+//     stream-ordered allocations, then hands the request to the step thread;
+//   step thread: enqueues all steps of each handed-over request on the least loaded
+//     stream, so kernels of different requests run side by side on the device, and
+//     retires requests whose completion event has fired (non-finite flag, copy-out,
+//     release of device memory and budget).
+// Setup of new requests therefore overlaps the steps of running ones. Each request runs
+// the same kernels on the same shapes whatever else is admitted, so its result does not
+// depend on the mix.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -26,18 +28,17 @@
 namespace {
 
 constexpr int kStreams = 4;
-constexpr int kStepsPerRound = 4;
+constexpr int kAdmitThreads = 4;
 
 struct Job {
   uint64_t id = 0;
   mm_request req{};
   std::vector<double> a, u0;
   int64_t est_bytes = 0;
+  double work = 0;   // flop estimate for stream balancing
   double t_submit = 0, t_admit = 0, t_done = 0;
-  // running state
   mm_op* op = nullptr;
   double* u = nullptr;
-  int done_steps = 0;
   int slot = 0;
   hipEvent_t ev = nullptr;
   int64_t bytes = 0;
@@ -57,8 +58,17 @@ int64_t footprint(const mm_request& r) {
     fac += (int64_t)r.n[mu] * r.n[mu];
     nmax = std::max<int64_t>(nmax, r.n[mu]);
   }
-  // a, u, 4 scratch grid functions, factors, Pade workspace (7 n^2)
-  return 8 * (na + 5 * dof + fac + 7 * nmax * nmax) + 4096;
+  // a, u, 4 scratch grid functions, factors (+ mixed copies), Pade workspace (7 n^2)
+  return 8 * (na + 5 * dof + 2 * fac + 7 * nmax * nmax) + 4096;
+}
+
+double work_estimate(const mm_request& r) {
+  double dof = 1, nsum = 0;
+  for (int mu = 0; mu < r.d; ++mu) {
+    dof *= r.n[mu];
+    nsum += r.n[mu];
+  }
+  return r.steps * dof * (4.0 * nsum + 200.0);
 }
 
 }  // namespace
@@ -67,28 +77,34 @@ struct mm_server {
   int device = 0;
   int max_active = 8;
   int64_t budget = 0;
-  mm_ctx* ctx = nullptr;
+  mm_ctx* ctx = nullptr;                    // step thread
+  mm_ctx* actx[kAdmitThreads] = {};         // admission threads
   hipStream_t streams[kStreams] = {};
-  std::thread thr;
+  double stream_load[kStreams] = {};
+  std::thread admit_thr[kAdmitThreads], step_thr;
   std::mutex mu;
-  std::condition_variable cv;
+  std::condition_variable cv_admit, cv_step;
   bool stop = false;
   uint64_t next_id = 1;
-  std::deque<std::unique_ptr<Job>> pending;
+  std::deque<std::unique_ptr<Job>> pending;   // submitted
+  std::deque<std::unique_ptr<Job>> ready;     // set up, not yet enqueued
+  int64_t used = 0;                           // bytes held by admitted requests
+  int admitted = 0;                           // in setup, ready or running
   std::map<uint64_t, Result> results;
-  std::map<uint64_t, int> state;   // 0 pending, 1 running
+  std::map<uint64_t, int> state;              // 0 pending, 1 admitted
   std::chrono::steady_clock::time_point t0;
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
 
+  // record the outcome; called without the lock held
   void finish(Job& j, int status) {
     Result r;
     r.status = status;
     if (status == MM_OK) {
-      // the request's completion event has fired; a blocking copy on the null stream
-      // does not wait for the (non-blocking) slot streams, which may hold other work
+      // the completion event has fired; a blocking copy on the null stream does not
+      // wait for the (non-blocking) slot streams, which may hold other requests' work
       r.u.resize(j.u0.size());
       if (hipMemcpy(r.u.data(), j.u, r.u.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
         r.status = MM_EDEVICE;
@@ -98,7 +114,7 @@ struct mm_server {
     r.stats.t_admit = j.t_admit;
     r.stats.t_done = j.t_done;
     r.stats.bytes = j.bytes;
-    r.stats.steps = j.done_steps;
+    r.stats.steps = (r.status == MM_OK) ? j.req.steps : 0;
     r.stats.status = r.status;
     release(j);
     std::lock_guard<std::mutex> lk(mu);
@@ -107,21 +123,35 @@ struct mm_server {
   }
 
   void release(Job& j) {
-    if (j.op) mumode_destroy(j.op);
+    if (j.op) {
+      hipStream_t fs = j.op->ctx->stream;
+      mumode_destroy(j.op);   // stream-ordered frees on the op's context stream
+      if (j.u) hipFreeAsync(j.u, fs);
+    } else if (j.u) {
+      hipFreeAsync(j.u, ctx->stream);
+    }
     j.op = nullptr;
-    if (j.u) hipFree(j.u);
     j.u = nullptr;
     if (j.ev) hipEventDestroy(j.ev);
     j.ev = nullptr;
   }
 
-  int admit(Job& j, int slot) {
+  // admission thread: upload and set up one request on the thread's own stream
+  int admit(Job& j, mm_ctx* actx) {
     const mm_request& r = j.req;
+    hipStream_t cs = actx->stream;
     double* da = nullptr;
     const size_t abytes = j.a.size() * sizeof(double);
-    if (hipMalloc((void**)&da, abytes) != hipSuccess) return MM_ENOMEM;
-    if (hipMemcpy(da, j.a.data(), abytes, hipMemcpyHostToDevice) != hipSuccess) {
-      hipFree(da);
+    const size_t ubytes = j.u0.size() * sizeof(double);
+    if (hipMallocAsync((void**)&da, abytes, cs) != hipSuccess) return MM_ENOMEM;
+    if (hipMallocAsync((void**)&j.u, ubytes, cs) != hipSuccess) {
+      j.u = nullptr;
+      hipFreeAsync(da, cs);
+      return MM_ENOMEM;
+    }
+    if (hipMemcpyAsync(da, j.a.data(), abytes, hipMemcpyHostToDevice, cs) != hipSuccess ||
+        hipMemcpyAsync(j.u, j.u0.data(), ubytes, hipMemcpyHostToDevice, cs) != hipSuccess) {
+      hipFreeAsync(da, cs);
       return MM_EDEVICE;
     }
     mm_problem p{};
@@ -134,103 +164,129 @@ struct mm_server {
     for (int i = 0; i < 4; ++i) p.r[i] = r.r[i];
     p.lambda = r.lambda;
     p.a = da;
-    int st = mumode_setup(ctx, &p, r.tau, MM_LAWSON, MM_LAWSON2B, 0, r.prec, 0, &j.op);
-    hipFree(da);
-    if (st != MM_OK) return st;
-    const size_t ubytes = j.u0.size() * sizeof(double);
-    if (hipMalloc((void**)&j.u, ubytes) != hipSuccess) return MM_ENOMEM;
-    if (hipMemcpyAsync(j.u, j.u0.data(), ubytes, hipMemcpyHostToDevice, streams[slot]) != hipSuccess)
-      return MM_EDEVICE;
+    // mumode_setup ends with a synchronisation of actx's stream: a, u and the op are
+    // ready for any stream afterwards
+    const int st = mumode_setup(actx, &p, r.tau, MM_LAWSON, MM_LAWSON2B, 0, r.prec, 0, &j.op);
+    hipFreeAsync(da, cs);
+    if (st != MM_OK) {
+      j.op = nullptr;
+      return st;
+    }
     if (hipEventCreateWithFlags(&j.ev, hipEventDisableTiming) != hipSuccess) return MM_EDEVICE;
-    j.slot = slot;
+    j.op->ctx = ctx;   // from here on the step thread owns the op
     j.bytes = j.op->bytes + (int64_t)ubytes;
     j.t_admit = now();
     return MM_OK;
   }
 
-  void loop() {
+  void admission_loop(mm_ctx* actx) {
     hipSetDevice(device);
-    std::vector<std::unique_ptr<Job>> active;
-    int64_t used = 0;
-    int rr = 0;
     while (true) {
-      std::deque<std::unique_ptr<Job>> admit_now;
+      std::unique_ptr<Job> j;
       {
         std::unique_lock<std::mutex> lk(mu);
-        if (active.empty() && pending.empty()) cv.wait(lk, [&] { return stop || !pending.empty(); });
-        if (stop && pending.empty() && active.empty()) break;
-        // admission in arrival order: stop at the first request that does not fit
-        while (!pending.empty() && (int)active.size() + (int)admit_now.size() < max_active &&
-               used + pending.front()->est_bytes <= budget) {
-          used += pending.front()->est_bytes;
-          state[pending.front()->id] = 1;
-          admit_now.push_back(std::move(pending.front()));
-          pending.pop_front();
+        cv_admit.wait(lk, [&] {
+          if (pending.empty()) return stop;
+          return admitted < max_active && used + pending.front()->est_bytes <= budget;
+        });
+        if (pending.empty()) return;   // stop requested and nothing left to admit
+        j = std::move(pending.front());
+        pending.pop_front();
+        used += j->est_bytes;
+        ++admitted;
+        state[j->id] = 1;
+      }
+      const int st = admit(*j, actx);
+      if (st != MM_OK && j->u) {   // free u on this thread's stream (no op took it over)
+        if (!j->op) {
+          hipFreeAsync(j->u, actx->stream);
+          j->u = nullptr;
         }
       }
-      for (auto& jp : admit_now) {
-        const int slot = rr++ % kStreams;
-        const int st = admit(*jp, slot);
+      if (st != MM_OK) {
+        finish(*j, st);
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          used -= j->est_bytes;
+          --admitted;
+        }
+        cv_step.notify_all();
+        continue;
+      }
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        used += j->bytes - j->est_bytes;
+        ready.push_back(std::move(j));
+      }
+      cv_step.notify_all();
+    }
+  }
+
+  void retire(Job& j, int status) {
+    const int64_t b = j.bytes;
+    finish(j, status);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      used -= b;
+      --admitted;
+    }
+    cv_admit.notify_all();
+  }
+
+  void step_loop() {
+    hipSetDevice(device);
+    std::vector<std::unique_ptr<Job>> active;
+    while (true) {
+      std::deque<std::unique_ptr<Job>> fresh;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        if (active.empty()) {
+          cv_step.wait(lk, [&] { return !ready.empty() || (stop && pending.empty() && admitted == 0); });
+          if (ready.empty() && stop && pending.empty() && admitted == 0) return;
+        }
+        fresh.swap(ready);
+      }
+      for (auto& jp : fresh) {
+        Job& j = *jp;
+        const int s = (int)(std::min_element(stream_load, stream_load + kStreams) - stream_load);
+        j.slot = s;
+        int st = lawson_step(ctx, j.op, j.u, j.req.steps, streams[s]);
+        if (st == MM_OK && hipEventRecord(j.ev, streams[s]) != hipSuccess) st = MM_EDEVICE;
         if (st != MM_OK) {
-          used -= jp->est_bytes;
-          finish(*jp, st);
+          hipStreamSynchronize(streams[s]);
+          retire(j, st);
           continue;
         }
-        used += jp->bytes - jp->est_bytes;
-        jp->est_bytes = jp->bytes;
+        stream_load[s] += j.work;
         active.push_back(std::move(jp));
       }
-      // one round: a few steps for every running request
-      for (auto& jp : active) {
-        Job& j = *jp;
-        if (j.done_steps >= j.req.steps) continue;
-        const int k = std::min(kStepsPerRound, j.req.steps - j.done_steps);
-        if (lawson_step(ctx, j.op, j.u, k, streams[j.slot]) != MM_OK) {
-          j.done_steps = -1;
-          continue;
-        }
-        j.done_steps += k;
-        if (j.done_steps >= j.req.steps) hipEventRecord(j.ev, streams[j.slot]);
-      }
-      // retire finished requests without blocking on the others
+      bool progressed = !fresh.empty();
       for (size_t i = 0; i < active.size();) {
         Job& j = *active[i];
-        bool fin = false;
-        int status = MM_OK;
-        if (j.done_steps < 0) {
-          fin = true;
-          status = MM_EDEVICE;
-        } else if (j.done_steps >= j.req.steps) {
-          const hipError_t q = hipEventQuery(j.ev);
-          if (q == hipSuccess) {
-            fin = true;
-            int flag = 0;
-            if (hipMemcpy(&flag, j.op->flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
-              status = MM_EDEVICE;
-            else if (flag)
-              status = MM_EUNSTABLE;
-          } else if (q != hipErrorNotReady) {
-            fin = true;
-            status = MM_EDEVICE;
-          }
-        }
-        if (fin) {
-          used -= j.bytes;
-          finish(j, status);
-          active.erase(active.begin() + i);
-        } else {
+        const hipError_t q = hipEventQuery(j.ev);
+        if (q == hipErrorNotReady) {
           ++i;
+          continue;
         }
+        int status = MM_OK;
+        if (q != hipSuccess) {
+          status = MM_EDEVICE;
+        } else {
+          int flag = 0;
+          if (hipMemcpy(&flag, j.op->flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+            status = MM_EDEVICE;
+          else if (flag)
+            status = MM_EUNSTABLE;
+        }
+        stream_load[j.slot] -= j.work;
+        retire(j, status);
+        active.erase(active.begin() + i);
+        progressed = true;
       }
-      // nothing left to enqueue: wait for the device instead of spinning
-      bool all_enqueued = !active.empty();
-      for (auto& jp : active) all_enqueued = all_enqueued && jp->done_steps >= jp->req.steps;
-      if (all_enqueued) {
+      if (!progressed && !active.empty()) {
+        // nothing finished: wait for new work or poll the events again shortly
         std::unique_lock<std::mutex> lk(mu);
-        bool can_admit = !pending.empty() && (int)active.size() < max_active &&
-                         used + pending.front()->est_bytes <= budget;
-        lk.unlock();
-        if (!can_admit) hipEventSynchronize(active.front()->ev);
+        cv_step.wait_for(lk, std::chrono::microseconds(200), [&] { return !ready.empty(); });
       }
     }
   }
@@ -245,13 +301,17 @@ mm_status mm_server_create(int device, int max_active, int64_t hbm_budget, mm_se
   s->device = device;
   s->max_active = max_active;
   mm_status st = mm_ctx_create(device, &s->ctx);
+  for (int i = 0; i < kAdmitThreads && st == MM_OK; ++i) st = mm_ctx_create(device, &s->actx[i]);
   if (st != MM_OK) {
+    for (int i = 0; i < kAdmitThreads; ++i) mm_ctx_destroy(s->actx[i]);
+    mm_ctx_destroy(s->ctx);
     delete s;
     return st;
   }
   if (hbm_budget <= 0) {
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      for (int i = 0; i < kAdmitThreads; ++i) mm_ctx_destroy(s->actx[i]);
       mm_ctx_destroy(s->ctx);
       delete s;
       return MM_EDEVICE;
@@ -261,12 +321,17 @@ mm_status mm_server_create(int device, int max_active, int64_t hbm_budget, mm_se
   s->budget = hbm_budget;
   for (int i = 0; i < kStreams; ++i)
     if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
+      for (int k = 0; k < kAdmitThreads; ++k) mm_ctx_destroy(s->actx[k]);
       mm_ctx_destroy(s->ctx);
       delete s;
       return MM_EDEVICE;
     }
   s->t0 = std::chrono::steady_clock::now();
-  s->thr = std::thread([s] { s->loop(); });
+  for (int i = 0; i < kAdmitThreads; ++i) {
+    mm_ctx* a = s->actx[i];
+    s->admit_thr[i] = std::thread([s, a] { s->admission_loop(a); });
+  }
+  s->step_thr = std::thread([s] { s->step_loop(); });
   *out = s;
   return MM_OK;
 }
@@ -277,10 +342,16 @@ void mm_server_destroy(mm_server* s) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
   }
-  s->cv.notify_all();
-  if (s->thr.joinable()) s->thr.join();
+  s->cv_admit.notify_all();
+  s->cv_step.notify_all();
+  for (int i = 0; i < kAdmitThreads; ++i)
+    if (s->admit_thr[i].joinable()) s->admit_thr[i].join();
+  s->cv_step.notify_all();
+  if (s->step_thr.joinable()) s->step_thr.join();
+  hipSetDevice(s->device);
   for (int i = 0; i < kStreams; ++i)
     if (s->streams[i]) hipStreamDestroy(s->streams[i]);
+  for (int i = 0; i < kAdmitThreads; ++i) mm_ctx_destroy(s->actx[i]);
   mm_ctx_destroy(s->ctx);
   delete s;
 }
@@ -306,16 +377,18 @@ mm_status solve_submit(mm_server* s, const mm_request* r, uint64_t* id) {
   j->req.a = nullptr;
   j->req.u0 = nullptr;
   j->est_bytes = footprint(j->req);
+  j->work = work_estimate(j->req);
   if (j->est_bytes > s->budget) return MM_ENOMEM;
   j->t_submit = s->now();
   {
     std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return MM_EBUSY;
     j->id = s->next_id++;
     *id = j->id;
     s->state[j->id] = 0;
     s->pending.push_back(std::move(j));
   }
-  s->cv.notify_all();
+  s->cv_admit.notify_all();
   return MM_OK;
 }
 

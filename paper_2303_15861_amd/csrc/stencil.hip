@@ -271,6 +271,76 @@ __global__ __launch_bounds__(1024) void lu_solve_kernel(double* Qall, double* Pa
   }
 }
 
+// out[0] = max column sum of |Q| (1-norm), out[1] = max row sum (inf-norm); one block
+__global__ __launch_bounds__(1024) void norms_kernel(const double* Q, int n, double* out) {
+  __shared__ double s1[1024], si[1024];
+  double c1 = 0.0, ci = 0.0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double col = 0.0, row = 0.0;
+    for (int i = 0; i < n; ++i) {
+      col += fabs(Q[(int64_t)i * n + j]);
+      row += fabs(Q[(int64_t)j * n + i]);
+    }
+    c1 = fmax(c1, col);
+    ci = fmax(ci, row);
+  }
+  s1[threadIdx.x] = c1;
+  si[threadIdx.x] = ci;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + w]);
+      si[threadIdx.x] = fmax(si[threadIdx.x], si[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = s1[0];
+    out[1] = si[0];
+  }
+}
+
+hipError_t launch_norms(const double* Q, int n, double* out, hipStream_t s) {
+  norms_kernel<<<1, 1024, 0, s>>>(Q, n, out);
+  return hipGetLastError();
+}
+
+__global__ void scaled_transpose(double* X, const double* Q, int n, double alpha) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int r = (int)(e / n), c = (int)(e % n);
+  X[e] = alpha * Q[(int64_t)c * n + r];
+}
+
+hipError_t launch_scaled_transpose(double* X, const double* Q, int n, double alpha, hipStream_t s) {
+  const int64_t cnt = (int64_t)n * n;
+  scaled_transpose<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(X, Q, n, alpha);
+  return hipGetLastError();
+}
+
+// out[0] = max |R - I|; one block
+__global__ __launch_bounds__(1024) void resid_kernel(const double* R, int n, double* out) {
+  __shared__ double sm[1024];
+  double m = 0.0;
+  const int64_t cnt = (int64_t)n * n;
+  for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const int r = (int)(e / n), c = (int)(e % n);
+    m = fmax(m, fabs(R[e] - (r == c ? 1.0 : 0.0)));
+  }
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+hipError_t launch_resid(const double* R, int n, double* out, hipStream_t s) {
+  resid_kernel<<<1, 1024, 0, s>>>(R, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_lu_solve(double* Q, double* P, int n, int count, hipStream_t s) {
   lu_solve_kernel<<<count, 1024, 0, s>>>(Q, P, n);
   return hipGetLastError();

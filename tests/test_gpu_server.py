@@ -1,0 +1,125 @@
+"""Request server (solve_submit / solve_poll): continuous batching of Lawson2b solves.
+
+Checks: a request's result is bit-for-bit the same alone and among other requests
+(each request runs the same kernels on the same shapes whatever else is admitted),
+it matches the FP64 oracle, admission respects the HBM budget, a request larger than
+the budget is refused, a non-finite request fails alone, and unknown ids are reported.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import schemes as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_15861_amd as m
+    return m
+
+
+def wait(mm, srv, rid, shape, timeout=120.0):
+    t0 = time.time()
+    while True:
+        st, u, info = mm.solve_poll(srv, rid, shape)
+        if st != mm.MM_NOT_READY:
+            return st, u, info
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"request {rid} not done after {timeout} s")
+        time.sleep(0.001)
+
+
+def relerr(got, ref):
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+def test_alone_equals_mix_and_oracle(mm):
+    target = synth.smooth_problem((24, 20, 16), 11, tau=2e-3, steps=20, scheme="l2b", beta=(3, -2, 1))
+    others = [synth.smooth_problem((31, 31, 31), 21, tau=1e-3, steps=30),
+              synth.smooth_problem((63, 63), 22, tau=1e-3, steps=40, beta=(5, 1)),
+              synth.smooth_problem((40, 33, 28), 23, tau=1e-3, steps=25),
+              synth.smooth_problem((127, 127), 24, tau=5e-4, steps=50, beta=(0, 9)),
+              synth.smooth_problem((24, 20, 16), 25, tau=2e-3, steps=20),
+              synth.smooth_problem((63, 63, 63), 26, tau=1e-3, steps=10)]
+    srv = mm.Server(0, max_active=8)
+    try:
+        st, rid = mm.solve_submit(srv, target)
+        assert st == mm.MM_OK
+        st, u_alone, info = wait(mm, srv, rid, target.shape)
+        assert st == mm.MM_OK and info["steps"] == target.steps
+        ids = []
+        for p in others[:3]:
+            ids.append((p, mm.solve_submit(srv, p)[1]))
+        st, rid2 = mm.solve_submit(srv, target)
+        for p in others[3:]:
+            ids.append((p, mm.solve_submit(srv, p)[1]))
+        st, u_mix, _ = wait(mm, srv, rid2, target.shape)
+        assert st == mm.MM_OK
+        results = [(p, wait(mm, srv, i, p.shape)) for p, i in ids]
+    finally:
+        srv.close()
+    assert np.array_equal(u_alone, u_mix)
+    assert relerr(u_alone, S.solve(target)) <= 1e-12
+    for p, (st, u, _) in results:
+        assert st == mm.MM_OK
+        assert relerr(u, S.solve(p)) <= 1e-12
+
+
+def test_admission_respects_hbm_budget(mm):
+    probs = [synth.smooth_problem((20, 20, 20), 30 + i, tau=1e-3, steps=15) for i in range(4)]
+    # room for one 20^3 request at a time (footprint about 0.45 MB)
+    srv = mm.Server(0, max_active=8, hbm_budget=700_000)
+    try:
+        ids = [mm.solve_submit(srv, p)[1] for p in probs]
+        out = [wait(mm, srv, i, p.shape) for p, i in zip(probs, ids)]
+        big = synth.smooth_problem((63, 63, 63), 1, tau=1e-3, steps=2)
+        st_big, _ = mm.solve_submit(srv, big)
+    finally:
+        srv.close()
+    assert st_big == mm.MM_ENOMEM
+    spans = sorted((info["t_admit"], info["t_done"]) for st, u, info in out)
+    for (a0, d0), (a1, d1) in zip(spans, spans[1:]):
+        assert a1 >= d0 - 1e-6, spans   # never two admitted at once
+    for (st, u, info), p in zip(out, probs):
+        assert st == mm.MM_OK
+        assert 0 < info["bytes"] <= 700_000
+        assert relerr(u, S.solve(p)) <= 1e-12
+
+
+def test_nonfinite_request_fails_alone(mm):
+    good = synth.smooth_problem((30, 29, 28), 40, tau=1e-3, steps=12)
+    bad = synth.smooth_problem((30, 29, 28), 41, tau=1e-3, steps=12)
+    bad.u0 = bad.u0.copy()
+    bad.u0[5, 6, 7] = np.nan
+    srv = mm.Server(0, max_active=4)
+    try:
+        ib = mm.solve_submit(srv, bad)[1]
+        ig = mm.solve_submit(srv, good)[1]
+        sb, ub, _ = wait(mm, srv, ib, bad.shape)
+        sg, ug, _ = wait(mm, srv, ig, good.shape)
+        assert mm.solve_poll(srv, 987654, good.shape)[0] == mm.MM_ENOTFOUND
+    finally:
+        srv.close()
+    assert sb == mm.MM_EUNSTABLE and ub is None
+    assert sg == mm.MM_OK
+    assert relerr(ug, S.solve(good)) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_precision_requests(mm, prec):
+    p = synth.smooth_problem((40, 36, 32), 50, tau=1e-3, steps=10)
+    srv = mm.Server(0, max_active=4)
+    try:
+        rid = mm.solve_submit(srv, p, prec=prec)[1]
+        st, u, _ = wait(mm, srv, rid, p.shape)
+    finally:
+        srv.close()
+    assert st == mm.MM_OK
+    assert relerr(u, S.solve(p)) <= (1e-4 if prec == "fp32" else 1e-3)
