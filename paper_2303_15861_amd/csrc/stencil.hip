@@ -20,13 +20,28 @@ namespace mm {
 // every access is a coalesced row segment. No LDS and no barriers.
 constexpr int SX = 64, SY = 4, YT = 2, ZT = 4;
 
+// Block order: workgroups are dealt round-robin over the eight XCDs (id % 8), each with
+// its own L2. XCD k takes a contiguous band of x2-blocks and walks it x1-fastest, then
+// x2, then x3, so the x2 and x3 halos a block reads were (or are about to be) fetched
+// into the same L2 by its neighbours.
+struct StencilGrid {
+  int nxb, nyb, nzb, ybx;
+};
+
 template <int D>
-__global__ __launch_bounds__(SX * SY) void stencil_kernel(StencilArgs p) {
+__global__ __launch_bounds__(SX * SY) void stencil_kernel(StencilArgs p, StencilGrid sg) {
   constexpr int ZP = (D == 3) ? ZT : 1;   // points per thread along x3
+  const int L = blockIdx.x;
+  const int xcd = L & 7, j = L >> 3;
+  const int bx = j % sg.nxb;
+  const int r = j / sg.nxb;
+  const int by = xcd * sg.ybx + r % sg.ybx;
+  const int bz = r / sg.ybx;
+  if (by >= sg.nyb || bz >= sg.nzb) return;
   const int tx = threadIdx.x & (SX - 1), ty = threadIdx.x / SX;
-  const int i1 = blockIdx.x * SX + tx;
-  const int y0 = (blockIdx.y * SY + ty) * YT;
-  const int z0 = (D == 3) ? blockIdx.z * ZT : 0;
+  const int i1 = bx * SX + tx;
+  const int y0 = (by * SY + ty) * YT;
+  const int z0 = (D == 3) ? bz * ZT : 0;
   const int n1 = p.n1, n2 = p.n2, n3 = p.n3;
   if (i1 >= n1) return;
   const int s2 = n1, s3 = n1 * n2;                    // strides of u
@@ -89,12 +104,17 @@ __global__ __launch_bounds__(SX * SY) void stencil_kernel(StencilArgs p) {
 }
 
 hipError_t launch_stencil(int d, const StencilArgs& a, hipStream_t s) {
-  const dim3 block(SX * SY);
-  const dim3 grid((a.n1 + SX - 1) / SX, (a.n2 + SY * YT - 1) / (SY * YT), d == 3 ? (a.n3 + ZT - 1) / ZT : 1);
+  StencilGrid sg;
+  sg.nxb = (a.n1 + SX - 1) / SX;
+  sg.nyb = (a.n2 + SY * YT - 1) / (SY * YT);
+  sg.nzb = (d == 3) ? (a.n3 + ZT - 1) / ZT : 1;
+  sg.ybx = (sg.nyb + 7) / 8;
+  const int64_t blocks = 8LL * sg.nxb * sg.ybx * sg.nzb;
+  if (blocks >= (1LL << 31)) return hipErrorInvalidValue;
   if (d == 3)
-    stencil_kernel<3><<<grid, block, 0, s>>>(a);
+    stencil_kernel<3><<<dim3((unsigned)blocks), dim3(SX * SY), 0, s>>>(a, sg);
   else
-    stencil_kernel<2><<<grid, block, 0, s>>>(a);
+    stencil_kernel<2><<<dim3((unsigned)blocks), dim3(SX * SY), 0, s>>>(a, sg);
   return hipGetLastError();
 }
 
