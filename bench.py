@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--modes", default="fp64,fp32,bf16x6,bf16x3")
     ap.add_argument("--headline", default="fp64")
     ap.add_argument("--latency-reps", type=int, default=20)
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="replay step loops from recorded HIP graphs of this many steps (0: direct launches)")
+    ap.add_argument("--tile", type=int, default=0, help="force the mode-product workgroup tile (64 or 128)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--serve", default="fp64,bf16x3",
@@ -82,29 +85,37 @@ def measured_traffic():
     return float(m_bytes.group(1)) if sha == m_sha.group(1) else None
 
 
-def time_mode(mm, ctx, p, prec, steps, warmup):
+def time_mode(mm, ctx, p, prec, steps, warmup, graph_steps=0):
+    """Timed region: `steps` steps on a resident state, no per-kernel events. A second,
+    untimed pass of the same steps brackets every kernel with HIP events on its stream
+    for the per-kernel table and the roofline. With graph replay the warmup runs at
+    least one graph's worth of steps, so that the graph is recorded before timing."""
     import torch
     op = mm.setup_problem(ctx, p, prec=prec)
     u0 = torch.from_numpy(p.u0).to("cuda")
     u = u0.clone()
     stream = torch.cuda.current_stream()
+    warmup = max(warmup, graph_steps)
     if warmup:
-        mm.step(op, u, warmup)
+        mm.step(op, u, warmup, stream)
     u.copy_(u0)
     torch.cuda.synchronize()
-    ctx.timing(True)
     t0 = time.perf_counter()
     mm.step(op, u, steps, stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    status = mm.mm_check(op)
+    out = u.cpu().numpy()
+    u.copy_(u0)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    mm.step(op, u, steps, stream)
     kern = {}
     for kind, name in ((mm.MM_KIND_GEMM_K, "gemm_k"), (mm.MM_KIND_GEMM_N, "gemm_n"),
                        (mm.MM_KIND_STENCIL, "stencil")):
         n, ms, wk = ctx.timing_read(kind)
         kern[name] = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / max(n, 1), "work": wk}
     ctx.timing(False)
-    status = mm.mm_check(op)
-    out = u.cpu().numpy()
     return op, out, (t1 - t0), kern, status
 
 
@@ -210,6 +221,8 @@ def main():
               flush=True)
         del src, dst
     ctx = mm.Context(0)
+    ctx.set_graph_steps(args.graph_steps)
+    ctx.set_gemm_tile(args.tile)
     modes = [m for m in args.modes.split(",") if m]
     if "fp64" not in modes:
         modes = ["fp64"] + modes
@@ -218,7 +231,7 @@ def main():
     for prec in modes:
         print(f"[bench] {prec}: setup + {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
               flush=True)
-        op, out, dt, kern, status = time_mode(mm, ctx, p, prec, args.steps, args.warmup)
+        op, out, dt, kern, status = time_mode(mm, ctx, p, prec, args.steps, args.warmup, args.graph_steps)
         entry = {"ms_per_step": 1e3 * dt / args.steps, "value": p.dof * args.steps / dt / 1e6,
                  "kernels": kern, "status": mm.STATUS.get(status, status)}
         if prec == "fp64":
@@ -272,7 +285,8 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}[args.headline],
         "data": "synthetic",
         "config": {"workload": DESCRIPTION.get(args.workload, args.workload),
-                   "dof": p.dof, "scheme": p.scheme, "headline_mode": args.headline},
+                   "dof": p.dof, "scheme": p.scheme, "headline_mode": args.headline,
+                   "graph_steps": args.graph_steps, "tile": args.tile or "auto"},
         "latency": head.get("latency"),
         "modes": {m: {kk: vv for kk, vv in e.items() if kk != "kernels"} for m, e in res.items()},
         "kernels": {m: e["kernels"] for m, e in res.items()},

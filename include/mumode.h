@@ -165,6 +165,22 @@ enum { MM_KIND_STENCIL = 0, MM_KIND_GEMM_K = 1, MM_KIND_GEMM_N = 2 };
 mm_status mm_timing_enable(mm_ctx* ctx, int enable);
 mm_status mm_timing_read(mm_ctx* ctx, int kind, int64_t* launches, double* total_ms, double* work);
 
+/* Workgroup tile of the mode-product kernels launched through this context (tuning and
+ * tests). tile = 0 (default): 128 x 128 tiles, or 64 x 64 when a launch has fewer
+ * 128-tiles than the chip holds at once; 64 or 128 force that size. Both give results
+ * that agree to rounding (the sum over k runs in the same order in both). Other values:
+ * MM_EINVAL. Takes effect for launches enqueued after the call. */
+mm_status mm_set_gemm_tile(mm_ctx* ctx, int tile);
+
+/* Step replay through HIP graphs (launch-bound small problems). steps = 0 (default):
+ * lawson_step / erk_step launch their kernels one by one. steps = G > 0: a call with
+ * nsteps >= G records G steps on that state buffer into a graph once (kept by the op and
+ * recorded again when the buffer or G changes) and replays it nsteps / G times on the
+ * call's stream, then launches the remaining steps directly. Kernels, their order and
+ * therefore the results are the same as without graphs. Ignored while per-kernel timing
+ * is enabled. steps outside [0, 4096]: MM_EINVAL. */
+mm_status mm_set_graph_steps(mm_ctx* ctx, int steps);
+
 /* ---------------------------------------------------------------------------------
  * Serving: a request loop on its own host thread and HIP stream. Requests that arrive
  * while others run are admitted as slots and device memory allow; admitted requests

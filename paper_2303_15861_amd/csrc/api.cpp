@@ -223,6 +223,7 @@ hipError_t timed_launch(mm_ctx* ctx, int kind, double work, hipStream_t s, F&& l
 
 hipError_t gemm(const mm_op* op, GemmArgs& g, hipStream_t s) {
   const double work = 2.0 * g.M * (double)g.N * g.K * g.inner * g.groups;
+  g.tile = op->ctx ? op->ctx->gemm_tile : 0;
   return timed_launch(op->ctx, g.b_trans ? MM_KIND_GEMM_N : MM_KIND_GEMM_K, work, s,
                       [&] { return launch_gemm(op->prec, g, s); });
 }
@@ -491,6 +492,7 @@ void mm_ctx_destroy(mm_ctx* ctx) {
     hipEventDestroy(t.stop);
   }
   if (ctx->stream) hipStreamDestroy(ctx->stream);
+  if (ctx->capture) hipStreamDestroy(ctx->capture);
   delete ctx;
 }
 
@@ -519,6 +521,7 @@ void mumode_destroy(mm_op* op) {
   dev_free(op, op->f3_phi_lp);
   for (int i = 0; i < 6; ++i) dev_free(op, op->buf[i]);
   dev_free(op, op->flag);
+  if (op->gexec) hipGraphExecDestroy(op->gexec);
   delete op;
 }
 
@@ -829,18 +832,12 @@ mm_status mumode_phi1v(mm_ctx* ctx, const mm_op* op, const double* in, double* o
   return MM_OK;
 }
 
-mm_status lawson_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* stream) {
-  mm_status rc = check_op(ctx, op);
-  if (rc != MM_OK) return rc;
-  if (op->family != MM_LAWSON) {
-    set_err(ctx, "lawson_step needs an MM_LAWSON operator");
-    return MM_EINVAL;
-  }
-  if (!u || nsteps < 0) {
-    set_err(ctx, "bad arguments to lawson_step");
-    return MM_EINVAL;
-  }
-  hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+
+// Enqueue nsteps Lawson steps on s (arguments already validated).
+mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hipStream_t s) {
   const double tau = op->tau;
   const int64_t dof = op->dof;
   double* b0 = op->buf[0];
@@ -885,18 +882,8 @@ mm_status lawson_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void*
   return MM_OK;
 }
 
-mm_status erk_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* stream) {
-  mm_status rc = check_op(ctx, op);
-  if (rc != MM_OK) return rc;
-  if (op->family != MM_ERK) {
-    set_err(ctx, "erk_step needs an MM_ERK operator");
-    return MM_EINVAL;
-  }
-  if (!u || nsteps < 0) {
-    set_err(ctx, "bad arguments to erk_step");
-    return MM_EINVAL;
-  }
-  hipStream_t s = (hipStream_t)stream;
+// Enqueue nsteps ERK steps on s (arguments already validated).
+mm_status enqueue_erk(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hipStream_t s) {
   const double tau = op->tau;
   const int q = op->q;
   double *g0 = op->buf[0], *T1 = op->buf[1], *T2 = op->buf[2], *U = op->buf[3], *D = op->buf[4],
@@ -941,6 +928,90 @@ mm_status erk_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* st
   return MM_OK;
 }
 
+mm_status enqueue_steps(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hipStream_t s) {
+  return op->family == MM_LAWSON ? enqueue_lawson(ctx, op, u, nsteps, s) : enqueue_erk(ctx, op, u, nsteps, s);
+}
+
+// Record `gs` steps on state u into the op's graph (capture runs nothing).
+mm_status record_graph(mm_ctx* ctx, const mm_op* op, double* u, int gs) {
+  if (!ctx->capture) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+  if (op->gexec) {
+    HIPCHK(ctx, hipGraphExecDestroy(op->gexec));
+    op->gexec = nullptr;
+  }
+  HIPCHK(ctx, hipStreamBeginCapture(ctx->capture, hipStreamCaptureModeThreadLocal));
+  mm_status rc = enqueue_steps(ctx, op, u, gs, ctx->capture);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->capture, &graph);
+  if (rc != MM_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return rc;
+  }
+  HIPCHK(ctx, e);
+  const hipError_t ei = hipGraphInstantiate(&op->gexec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  HIPCHK(ctx, ei);
+  op->gu = u;
+  op->gsteps = gs;
+  return MM_OK;
+}
+
+// Steps through recorded graphs when the context asks for them (and is not timing
+// individual kernels), else by direct launches.
+mm_status run_steps(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hipStream_t s) {
+  const int gs = ctx->graph_steps;
+  if (gs <= 0 || ctx->timing || nsteps < gs) return enqueue_steps(ctx, op, u, nsteps, s);
+  if (!op->gexec || op->gu != u || op->gsteps != gs) {
+    mm_status rc = record_graph(ctx, op, u, gs);
+    if (rc != MM_OK) return rc;
+  }
+  const int reps = nsteps / gs;
+  for (int i = 0; i < reps; ++i) HIPCHK(ctx, hipGraphLaunch(op->gexec, s));
+  return enqueue_steps(ctx, op, u, nsteps - reps * gs, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+mm_status lawson_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* stream) {
+  mm_status rc = check_op(ctx, op);
+  if (rc != MM_OK) return rc;
+  if (op->family != MM_LAWSON) {
+    set_err(ctx, "lawson_step needs an MM_LAWSON operator");
+    return MM_EINVAL;
+  }
+  if (!u || nsteps < 0) {
+    set_err(ctx, "bad arguments to lawson_step");
+    return MM_EINVAL;
+  }
+  return run_steps(ctx, op, u, nsteps, (hipStream_t)stream);
+}
+
+mm_status erk_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* stream) {
+  mm_status rc = check_op(ctx, op);
+  if (rc != MM_OK) return rc;
+  if (op->family != MM_ERK) {
+    set_err(ctx, "erk_step needs an MM_ERK operator");
+    return MM_EINVAL;
+  }
+  if (!u || nsteps < 0) {
+    set_err(ctx, "bad arguments to erk_step");
+    return MM_EINVAL;
+  }
+  return run_steps(ctx, op, u, nsteps, (hipStream_t)stream);
+}
+
+mm_status mm_set_graph_steps(mm_ctx* ctx, int steps) {
+  if (!ctx) return MM_EINVAL;
+  if (steps < 0 || steps > 4096) {
+    set_err(ctx, "graph steps must be in [0, 4096]");
+    return MM_EINVAL;
+  }
+  ctx->graph_steps = steps;
+  return MM_OK;
+}
+
 mm_status mm_synchronize(mm_ctx* ctx) {
   if (!ctx) return MM_EINVAL;
   HIPCHK(ctx, hipSetDevice(ctx->device));
@@ -952,6 +1023,16 @@ mm_status mm_timing_enable(mm_ctx* ctx, int enable) {
   if (!ctx) return MM_EINVAL;
   ctx->timing = enable != 0;
   ctx->timed_used = 0;
+  return MM_OK;
+}
+
+mm_status mm_set_gemm_tile(mm_ctx* ctx, int tile) {
+  if (!ctx) return MM_EINVAL;
+  if (tile != 0 && tile != 64 && tile != 128) {
+    set_err(ctx, "gemm tile must be 0, 64 or 128");
+    return MM_EINVAL;
+  }
+  ctx->gemm_tile = tile;
   return MM_OK;
 }
 

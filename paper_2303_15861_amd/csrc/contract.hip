@@ -7,8 +7,9 @@
 //   mode 2:                A = E2,  B'[n][k] = V_slab[k][n] (slab = one x3 plane), C = n2 x n1
 //   mode 3 (2D: mode 2):   A = E3,  B'[n][k] = V[k][n] with V viewed n3 x (n1 n2)
 // so A is always read along k (row-major) and B' either along k (factor, mode 1) or
-// along n (grid operand, modes 2/3, "b_trans"). Workgroup tile 128 x 128, four waves of
-// 64 x 64, K staged through LDS in chunks; ragged edges are zero-filled on load and
+// along n (grid operand, modes 2/3, "b_trans"). Square workgroup tiles of T = 128 or 64
+// (four waves of T/2 x T/2; the launcher takes 64 when 128-tiles would not fill the
+// chip once), K staged through LDS in chunks; ragged edges are zero-filled on load and
 // masked on store. The linear workgroup id is remapped so that tiles sharing the large
 // operand are dispatched to the same XCD (workgroups are dealt round-robin over the
 // eight XCDs, each with its own L2).
@@ -32,8 +33,9 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int MT = 128, NT = 128, THREADS = 256;
+constexpr int THREADS = 256;
 
+template <int T>
 __device__ __forceinline__ void decode_tile(const GemmArgs& p, int P, int& g, int& b, int& m0,
                                             int& n0) {
   const int tiles = p.tiles_m * p.tiles_n;
@@ -49,8 +51,8 @@ __device__ __forceinline__ void decode_tile(const GemmArgs& p, int P, int& g, in
     tn = t % p.tiles_n;
     tm = t / p.tiles_n;
   }
-  m0 = tm * MT;
-  n0 = tn * NT;
+  m0 = tm * T;
+  n0 = tn * T;
 }
 
 template <typename TOut>
@@ -72,47 +74,54 @@ __device__ __forceinline__ void store_out(TOut* C, const double* Cadd, int idx, 
 // ------------------------------------------------------------------------------------
 constexpr int KC4 = 16;
 constexpr int P64 = KC4 + 2;   // [row][k] pitch in doubles (144 B: 16-byte aligned rows)
-constexpr int PKN = NT + 4;    // [k][n] pitch in doubles (8*PKN = 32 mod 64 banks)
+// [k][n] pitch T + 4 doubles: 8 * pitch = 32 mod 64 banks for both tile sizes
 
-template <int BT>
-__global__ __launch_bounds__(THREADS, 2) void gemm_f64(GemmArgs p) {
+template <int T>
+constexpr int occupancy() { return T == 128 ? 2 : 4; }
+
+template <int BT, int T>
+__global__ __launch_bounds__(THREADS, occupancy<T>()) void gemm_f64(GemmArgs p) {
+  constexpr int FI = T / 32;          // 16 x 16 fragments per wave and dimension
+  constexpr int NL = T / 16;          // tile elements per thread and operand per chunk
+  constexpr int PKN = T + 4;
+  constexpr int KR = THREADS / T;     // k rows of the [k][n] tile covered by one pass
   const int L = blockIdx.x;
   const int P = (L & 7) * p.per_xcd + (L >> 3);
   if (P >= p.total) return;
   int g, b, m0, n0;
-  decode_tile(p, P, g, b, m0, n0);
+  decode_tile<T>(p, P, g, b, m0, n0);
   const double* __restrict__ A = (const double*)p.A[g] + b * p.sA;
   const double* __restrict__ B = (const double*)p.B[g] + b * p.sB;
   double* __restrict__ C = (double*)p.C[g] + b * p.sC;
   const double* __restrict__ Cadd = p.Cadd[g] ? p.Cadd[g] + b * p.sC : nullptr;
 
-  constexpr int BSZ = BT ? KC4 * PKN : NT * P64;
-  __shared__ __attribute__((aligned(16))) double As[2][MT * P64];
+  constexpr int BSZ = BT ? KC4 * PKN : T * P64;
+  __shared__ __attribute__((aligned(16))) double As[2][T * P64];
   __shared__ __attribute__((aligned(16))) double Bs[2][BSZ];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = (wave >> 1) * (T / 2), wn = (wave & 1) * (T / 2);
   const int lg = lane >> 4, lr = lane & 15;
   const int M = p.M, N = p.N, K = p.K, lda = p.lda, ldb = p.ldb;
 
-  d4 acc[4][4];
+  d4 acc[FI][FI];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FI; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
   // element e = i*256 + tid of a tile: A and B' read along k: row = e/16 = 16i + tid/16,
-  // k = tid%16;  B' read along n: k = e/128 = 2i + tid/128, n = tid%128
+  // k = tid%16;  B' read along n: k = e/T = KR*i + tid/T, n = tid%T
   const int r16 = tid >> 4, k16 = tid & 15;
-  const int nB = min(n0 + (tid & 127), N - 1), kB = tid >> 7;
-  double ra[8], rb[8];
+  const int nB = min(n0 + (tid % T), N - 1), kB = tid / T;
+  double ra[NL], rb[NL];
   // loads are unconditional (clamped indices, unsigned 32-bit offsets from the uniform
-  // base) so that the eight loads of a chunk stay in flight through the MFMA phase;
+  // base) so that the loads of a chunk stay in flight through the MFMA phase;
   // k >= K (last chunk only) is zeroed when the registers are written to LDS
   auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < NL; ++i) {
       const unsigned arow = (unsigned)min(m0 + 16 * i + r16, M - 1);
-      const int kb = BT ? 2 * i + kB : k16;
+      const int kb = BT ? KR * i + kB : k16;
       const unsigned brow = (unsigned)(BT ? nB : min(n0 + 16 * i + r16, N - 1));
       const unsigned ka = (unsigned)min(k0 + k16, K - 1), kbb = (unsigned)min(k0 + kb, K - 1);
       ra[i] = A[arow * (unsigned)lda + ka];
@@ -121,13 +130,13 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_f64(GemmArgs p) {
   };
   auto store = [&](double* as, double* bs, int k0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < NL; ++i) {
       const int e = i * THREADS + tid;
-      const int kb = BT ? 2 * i + kB : k16;
+      const int kb = BT ? KR * i + kB : k16;
       as[(e >> 4) * P64 + (e & 15)] = (k0 + k16 < K) ? ra[i] : 0.0;
       const double y = (k0 + kb < K) ? rb[i] : 0.0;
       if (BT)
-        bs[(e >> 7) * PKN + (e & 127)] = y;
+        bs[(e / T) * PKN + (e % T)] = y;
       else
         bs[(e >> 4) * P64 + (e & 15)] = y;
     }
@@ -143,9 +152,9 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_f64(GemmArgs p) {
     const double* bs = Bs[cur];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {   // k = 4g + 2h + {0, 1}
-      d2 af[4], bf[4];
+      d2 af[FI], bf[FI];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < FI; ++i) {
         af[i] = *reinterpret_cast<const d2*>(as + (wm + 16 * i + lr) * P64 + 4 * lg + 2 * h);
         if (BT) {
           const double* q = bs + (4 * lg + 2 * h) * PKN + wn + 16 * i + lr;
@@ -157,9 +166,9 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_f64(GemmArgs p) {
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FI; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < FI; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
     }
     if (c + 1 < nch) store(As[cur ^ 1], Bs[cur ^ 1], (c + 1) * KC4);
@@ -168,9 +177,9 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_f64(GemmArgs p) {
   // f64 16x16 layout: lane l, element t holds row 4t + l/16, column l%16
   const double alpha = p.alpha, beta = p.beta;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < FI; ++j)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int m = m0 + wm + 16 * i + 4 * t + lg;
@@ -185,13 +194,16 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_f64(GemmArgs p) {
 // ------------------------------------------------------------------------------------
 constexpr int P32 = KC4 + 4;  // LDS row pitch in floats (80 B: 16-byte aligned rows)
 
-template <int BT, typename TIn, typename TOut>
-__global__ __launch_bounds__(THREADS, 2) void gemm_f32(GemmArgs p) {
+template <int BT, int T, typename TIn, typename TOut>
+__global__ __launch_bounds__(THREADS, occupancy<T>()) void gemm_f32(GemmArgs p) {
+  constexpr int FI = T / 32;
+  constexpr int NF = T / 64;          // factor float4 per thread and chunk
+  constexpr int NV = T / 16;          // grid values per thread and chunk
   const int L = blockIdx.x;
   const int P = (L & 7) * p.per_xcd + (L >> 3);
   if (P >= p.total) return;
   int g, b, m0, n0;
-  decode_tile(p, P, g, b, m0, n0);
+  decode_tile<T>(p, P, g, b, m0, n0);
   // factor: A (BT) or B' (!BT), float rows of stride ld = fac_ld(K)
   const float* __restrict__ F = BT ? (const float*)p.A[g] + b * p.sA : (const float*)p.B[g] + b * p.sB;
   const TIn* __restrict__ V = BT ? (const TIn*)p.B[g] + b * p.sB : (const TIn*)p.A[g] + b * p.sA;
@@ -203,45 +215,45 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_f32(GemmArgs p) {
   const int fr0 = BT ? m0 : n0, frows = BT ? M : N;   // factor rows of this tile
   const int vr0 = BT ? n0 : m0, vrows = BT ? N : M;   // grid rows (n for BT, m otherwise)
 
-  __shared__ __attribute__((aligned(16))) float Fs[2][128 * P32];
-  __shared__ __attribute__((aligned(16))) float Vs[2][128 * P32];
+  __shared__ __attribute__((aligned(16))) float Fs[2][T * P32];
+  __shared__ __attribute__((aligned(16))) float Vs[2][T * P32];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = (wave >> 1) * (T / 2), wn = (wave & 1) * (T / 2);
   const int lg = lane >> 4, lr = lane & 15;
 
-  f4 acc[4][4];
+  f4 acc[FI][FI];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < FI; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  f4 rf[2];
-  TIn rv[8];
-  // factor: 128 rows x 16 k = 512 float4, two per thread (rows clamped into range)
-  int foff[2];
+  f4 rf[NF];
+  TIn rv[NV];
+  // factor: T rows x 16 k = 4T float4 (rows clamped into range)
+  int foff[NF];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < NF; ++h) {
     const int e = h * THREADS + tid;
     foff[h] = min(fr0 + (e >> 2), frows - 1) * ldf + (e & 3) * 4;
   }
-  // grid: BT: lanes take consecutive n, a run of eight k per thread;
-  //       !BT: lanes take consecutive k (coalesced rows), eight rows per thread
-  int voff[8];
+  // grid: BT: lanes take consecutive n, a run of NV k per thread;
+  //       !BT: lanes take consecutive k (coalesced rows), NV rows per thread
+  int voff[NV];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
+  for (int j = 0; j < NV; ++j) {
     if (BT)
-      voff[j] = ((tid >> 7) * 8 + j) * ldv + min(vr0 + (tid & 127), vrows - 1);
+      voff[j] = ((tid / T) * NV + j) * ldv + min(vr0 + (tid % T), vrows - 1);
     else
       voff[j] = min(vr0 + (tid >> 4) + 16 * j, vrows - 1) * ldv + (tid & 15);
   }
-  auto vk_of = [&](int j) { return BT ? (tid >> 7) * 8 + j : (tid & 15); };
+  auto vk_of = [&](int j) { return BT ? (tid / T) * NV + j : (tid & 15); };
   auto load = [&](int k0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) rf[h] = *reinterpret_cast<const f4*>(F + foff[h] + k0);
+    for (int h = 0; h < NF; ++h) rf[h] = *reinterpret_cast<const f4*>(F + foff[h] + k0);
     // unconditional loads (k clamped); conversion and the k >= K zeroing happen at the
     // LDS store so that the loads stay in flight through the MFMA phase
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < NV; ++j) {
       const int kk = vk_of(j);
       const int kc = min(k0 + kk, K - 1) - kk;
       rv[j] = V[(unsigned)(voff[j] + kc * (BT ? ldv : 1))];
@@ -250,17 +262,19 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_f32(GemmArgs p) {
   auto cv = [&](int j, int k0) -> float { return (k0 + vk_of(j) < K) ? (float)rv[j] : 0.f; };
   auto store = [&](float* fs, float* vs, int k0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NF; ++h) {
       const int e = h * THREADS + tid;
       *reinterpret_cast<f4*>(fs + (e >> 2) * P32 + (e & 3) * 4) = rf[h];
     }
     if (BT) {
-      const int vrow = tid & 127, vk = (tid >> 7) * 8;
-      *reinterpret_cast<f4*>(vs + vrow * P32 + vk) = f4{cv(0, k0), cv(1, k0), cv(2, k0), cv(3, k0)};
-      *reinterpret_cast<f4*>(vs + vrow * P32 + vk + 4) = f4{cv(4, k0), cv(5, k0), cv(6, k0), cv(7, k0)};
+      const int vrow = tid % T, vk = (tid / T) * NV;
+#pragma unroll
+      for (int q = 0; q < NV / 4; ++q)
+        *reinterpret_cast<f4*>(vs + vrow * P32 + vk + 4 * q) =
+            f4{cv(4 * q, k0), cv(4 * q + 1, k0), cv(4 * q + 2, k0), cv(4 * q + 3, k0)};
     } else {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) vs[((tid >> 4) + 16 * j) * P32 + (tid & 15)] = cv(j, k0);
+      for (int j = 0; j < NV; ++j) vs[((tid >> 4) + 16 * j) * P32 + (tid & 15)] = cv(j, k0);
     }
   };
   load(0);
@@ -272,18 +286,18 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_f32(GemmArgs p) {
     if (c + 1 < nch) load((c + 1) * KC4);
     const float* as = BT ? Fs[cur] : Vs[cur];
     const float* bs = BT ? Vs[cur] : Fs[cur];
-    f4 af[4], bf[4];
+    f4 af[FI], bf[FI];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < FI; ++i) {
       af[i] = *reinterpret_cast<const f4*>(as + (wm + 16 * i + lr) * P32 + 4 * lg);
       bf[i] = *reinterpret_cast<const f4*>(bs + (wn + 16 * i + lr) * P32 + 4 * lg);
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < FI; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
     if (c + 1 < nch) store(Fs[cur ^ 1], Vs[cur ^ 1], (c + 1) * KC4);
     __syncthreads();
@@ -291,9 +305,9 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_f32(GemmArgs p) {
   // f32 16x16 layout: lane l, element t holds row 4(l/16) + t, column l%16
   const double alpha = p.alpha, beta = p.beta;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < FI; ++j)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int m = m0 + wm + 16 * i + 4 * lg + t;
@@ -321,13 +335,16 @@ __device__ __forceinline__ void split_bf16(float x, __bf16 (&out)[S]) {
   }
 }
 
-template <int BT, int S, typename TIn, typename TOut>
-__global__ __launch_bounds__(THREADS, 2) void gemm_bf16(GemmArgs p) {
+template <int BT, int T, int S, typename TIn, typename TOut>
+__global__ __launch_bounds__(THREADS, occupancy<T>()) void gemm_bf16(GemmArgs p) {
+  constexpr int FI = T / 32;
+  constexpr int NF = T / 64;          // factor bf8 vectors per thread, slice and chunk
+  constexpr int NV = T / 8;           // grid values per thread and chunk
   const int L = blockIdx.x;
   const int P = (L & 7) * p.per_xcd + (L >> 3);
   if (P >= p.total) return;
   int g, b, m0, n0;
-  decode_tile(p, P, g, b, m0, n0);
+  decode_tile<T>(p, P, g, b, m0, n0);
   const __bf16* __restrict__ F = BT ? (const __bf16*)p.A[g] + b * p.sA : (const __bf16*)p.B[g] + b * p.sB;
   const TIn* __restrict__ V = BT ? (const TIn*)p.B[g] + b * p.sB : (const TIn*)p.A[g] + b * p.sA;
   TOut* __restrict__ C = (TOut*)p.C[g] + b * p.sC;
@@ -339,63 +356,61 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_bf16(GemmArgs p) {
   const int vr0 = BT ? n0 : m0, vrows = BT ? N : M;
   const int64_t fsl = p.fac_slice;
 
-  __shared__ __attribute__((aligned(16))) __bf16 Fs[S][128 * PB];
-  __shared__ __attribute__((aligned(16))) __bf16 Vs[S][128 * PB];
+  __shared__ __attribute__((aligned(16))) __bf16 Fs[S][T * PB];
+  __shared__ __attribute__((aligned(16))) __bf16 Vs[S][T * PB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = (wave >> 1) * (T / 2), wn = (wave & 1) * (T / 2);
   const int lg = lane >> 4, lr = lane & 15;
 
-  f4 acc[4][4];
+  f4 acc[FI][FI];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < FI; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  bf8 rf[S][2];
-  TIn rv[16];
-  int foff[2];
+  bf8 rf[S][NF];
+  TIn rv[NV];
+  int foff[NF];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < NF; ++h) {
     const int e = h * THREADS + tid;
     foff[h] = min(fr0 + (e >> 2), frows - 1) * ldf + (e & 3) * 8;
   }
-  // grid: BT: lanes take consecutive n, a run of sixteen k per thread;
-  //       !BT: lanes take consecutive k (coalesced rows), sixteen rows per thread
-  int voff[16];
+  // grid: BT: lanes take consecutive n, a run of NV k per thread;
+  //       !BT: lanes take consecutive k (coalesced rows), NV rows per thread
+  int voff[NV];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
+  for (int j = 0; j < NV; ++j) {
     if (BT)
-      voff[j] = ((tid >> 7) * 16 + j) * ldv + min(vr0 + (tid & 127), vrows - 1);
+      voff[j] = ((tid / T) * NV + j) * ldv + min(vr0 + (tid % T), vrows - 1);
     else
       voff[j] = min(vr0 + (tid >> 5) + 8 * j, vrows - 1) * ldv + (tid & 31);
   }
+  auto vk_of = [&](int j) { return BT ? (tid / T) * NV + j : (tid & 31); };
   auto load = [&](int k0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < NF; ++h)
 #pragma unroll
       for (int s = 0; s < S; ++s) rf[s][h] = *reinterpret_cast<const bf8*>(F + s * fsl + foff[h] + k0);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int kk = BT ? (tid >> 7) * 16 + j : (tid & 31);
+    for (int j = 0; j < NV; ++j) {
+      const int kk = vk_of(j);
       const int kc = min(k0 + kk, K - 1) - kk;
       rv[j] = V[(unsigned)(voff[j] + kc * (BT ? ldv : 1))];
     }
   };
-  auto cv = [&](int j, int k0) -> float {
-    const int kk = BT ? (tid >> 7) * 16 + j : (tid & 31);
-    return (k0 + kk < K) ? (float)rv[j] : 0.f;
-  };
+  auto cv = [&](int j, int k0) -> float { return (k0 + vk_of(j) < K) ? (float)rv[j] : 0.f; };
   auto store = [&](int k0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NF; ++h) {
       const int e = h * THREADS + tid;
 #pragma unroll
       for (int s = 0; s < S; ++s) *reinterpret_cast<bf8*>(&Fs[s][(e >> 2) * PB + (e & 3) * 8]) = rf[s][h];
     }
     if (BT) {
-      const int vrow = tid & 127, vk = (tid >> 7) * 16;
+      const int vrow = tid % T, vk = (tid / T) * NV;
 #pragma unroll
-      for (int half = 0; half < 2; ++half) {
+      for (int half = 0; half < NV / 8; ++half) {
         bf8 v[S];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -409,7 +424,7 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_bf16(GemmArgs p) {
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
+      for (int j = 0; j < NV; ++j) {
         __bf16 sl[S];
         split_bf16<S>(cv(j, k0), sl);
 #pragma unroll
@@ -426,24 +441,24 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_bf16(GemmArgs p) {
     if (c + 1 < nch) load((c + 1) * KCB);
 #pragma unroll
     for (int sa = 0; sa < S; ++sa) {
-      bf8 af[4];
+      bf8 af[FI];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < FI; ++i) {
         const __bf16* base = BT ? &Fs[sa][0] : &Vs[sa][0];
         af[i] = *reinterpret_cast<const bf8*>(base + (wm + 16 * i + lr) * PB + 8 * lg);
       }
 #pragma unroll
       for (int sb = 0; sa + sb < S; ++sb) {
-        bf8 bfr[4];
+        bf8 bfr[FI];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < FI; ++j) {
           const __bf16* base = BT ? &Vs[sb][0] : &Fs[sb][0];
           bfr[j] = *reinterpret_cast<const bf8*>(base + (wn + 16 * j + lr) * PB + 8 * lg);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FI; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < FI; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
       }
     }
@@ -451,9 +466,9 @@ __global__ __launch_bounds__(THREADS, 2) void gemm_bf16(GemmArgs p) {
   }
   const double alpha = p.alpha, beta = p.beta;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < FI; ++j)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int m = m0 + wm + 16 * i + 4 * lg + t;
@@ -504,7 +519,7 @@ hipError_t launch_convert_factor(int prec, void* dst, const double* src, int row
 }
 
 // ------------------------------------------------------------------------------------
-template <int BT>
+template <int BT, int T>
 hipError_t launch_mixed(int prec, GemmArgs& g, dim3 grid, dim3 block, hipStream_t s) {
   const int io = (g.in_f32 ? 1 : 0) | (g.out_f32 ? 2 : 0);
 #define MM_LAUNCH_IO(KERNEL, ...)                                                     \
@@ -515,18 +530,46 @@ hipError_t launch_mixed(int prec, GemmArgs& g, dim3 grid, dim3 block, hipStream_
     default: KERNEL<__VA_ARGS__, float, float><<<grid, block, 0, s>>>(g); break;    \
   }
   switch (prec) {
-    case MM_FP32: MM_LAUNCH_IO(gemm_f32, BT) break;
-    case MM_BF16X3: MM_LAUNCH_IO(gemm_bf16, BT, 2) break;
-    case MM_BF16X6: MM_LAUNCH_IO(gemm_bf16, BT, 3) break;
+    case MM_FP32: MM_LAUNCH_IO(gemm_f32, BT, T) break;
+    case MM_BF16X3: MM_LAUNCH_IO(gemm_bf16, BT, T, 2) break;
+    case MM_BF16X6: MM_LAUNCH_IO(gemm_bf16, BT, T, 3) break;
     default: return hipErrorInvalidValue;
   }
 #undef MM_LAUNCH_IO
   return hipGetLastError();
 }
 
+template <int T>
+hipError_t launch_tile(int prec, GemmArgs& g, hipStream_t s) {
+  g.tiles_m = (g.M + T - 1) / T;
+  g.tiles_n = (g.N + T - 1) / T;
+  const int64_t total = (int64_t)g.tiles_m * g.tiles_n * g.inner * g.groups;
+  if (total >= ((int64_t)1 << 28)) return hipErrorInvalidValue;
+  g.total = (int)total;
+  g.per_xcd = (g.total + 7) / 8;
+  const dim3 grid(8 * g.per_xcd), block(THREADS);
+  if (prec == MM_FP64) {
+    if (g.in_f32 || g.out_f32) return hipErrorInvalidValue;
+    if (g.b_trans) gemm_f64<1, T><<<grid, block, 0, s>>>(g);
+    else gemm_f64<0, T><<<grid, block, 0, s>>>(g);
+    return hipGetLastError();
+  }
+  return g.b_trans ? launch_mixed<1, T>(prec, g, grid, block, s) : launch_mixed<0, T>(prec, g, grid, block, s);
+}
+
+// Workgroups of 128-tiles that fill every compute unit at their occupancy (256 CUs x 2).
+constexpr int64_t kFillSlots = 512;
+
+int choose_tile(const GemmArgs& g) {
+  if (g.tile == 64 || g.tile == 128) return g.tile;
+  const int64_t t128 = (int64_t)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.inner * g.groups;
+  return t128 < kFillSlots ? 64 : 128;
+}
+
 hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.inner <= 0 || g.groups <= 0 || g.groups > kMaxGroups)
     return hipErrorInvalidValue;
+  if (g.tile != 0 && g.tile != 64 && g.tile != 128) return hipErrorInvalidValue;
   // in-batch offsets are 32-bit
   const int64_t lim = (int64_t)1 << 31;
   if ((int64_t)g.M * g.lda >= lim || (int64_t)g.M * g.ldc >= lim ||
@@ -537,20 +580,7 @@ hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s) {
     const int ldf = g.b_trans ? g.lda : g.ldb;
     if (ldf < fac_ld(g.K) || ldf % kFacPad != 0) return hipErrorInvalidValue;
   }
-  g.tiles_m = (g.M + MT - 1) / MT;
-  g.tiles_n = (g.N + NT - 1) / NT;
-  const int64_t total = (int64_t)g.tiles_m * g.tiles_n * g.inner * g.groups;
-  if (total >= lim / 8) return hipErrorInvalidValue;
-  g.total = (int)total;
-  g.per_xcd = (g.total + 7) / 8;
-  const dim3 grid(8 * g.per_xcd), block(THREADS);
-  if (prec == MM_FP64) {
-    if (g.in_f32 || g.out_f32) return hipErrorInvalidValue;
-    if (g.b_trans) gemm_f64<1><<<grid, block, 0, s>>>(g);
-    else gemm_f64<0><<<grid, block, 0, s>>>(g);
-    return hipGetLastError();
-  }
-  return g.b_trans ? launch_mixed<1>(prec, g, grid, block, s) : launch_mixed<0>(prec, g, grid, block, s);
+  return choose_tile(g) == 64 ? launch_tile<64>(prec, g, s) : launch_tile<128>(prec, g, s);
 }
 
 }  // namespace mm

@@ -35,6 +35,7 @@ struct GemmArgs {
   double alpha, beta;
   int in_f32, out_f32;
   int64_t fac_slice;
+  int tile;             // workgroup tile: 0 = chosen by the launcher, 64 or 128
   // filled by the launcher
   int tiles_m, tiles_n, total, per_xcd;
 };
@@ -64,6 +65,9 @@ struct StencilArgs {
 };
 
 hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s);
+// Tile size the launcher takes for g (g.tile if set, else 64 when 128-tiles would not
+// fill the chip once).
+int choose_tile(const GemmArgs& g);
 hipError_t launch_stencil(int d, const StencilArgs& a, hipStream_t s);
 hipError_t launch_max_reduce(const double* x, int64_t n, double* partial, int nparts, double* out,
                              hipStream_t s);
@@ -108,6 +112,9 @@ struct mm_ctx {
   double* reduce_buf = nullptr;   // partial maxima
   int reduce_parts = 0;
   bool timing = false;            // per-kernel event timing
+  int gemm_tile = 0;              // 0 = automatic, else forced 64 or 128
+  int graph_steps = 0;            // >0: step calls replay captured graphs of this many steps
+  hipStream_t capture = nullptr;  // private stream used only to record graphs
   std::vector<mm_timed> timed;
   size_t timed_used = 0;
 };
@@ -138,4 +145,8 @@ struct mm_op {
   int64_t buf_len[6] = {0};
   int* flag = nullptr;                 // sticky non-finite flag
   int64_t bytes = 0;                   // device footprint
+  // recorded step graph: `gsteps` steps on state `gu` (rebuilt when either changes)
+  mutable hipGraphExec_t gexec = nullptr;
+  mutable double* gu = nullptr;
+  mutable int gsteps = 0;
 };
