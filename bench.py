@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "int8": 5.0e15}
 DESCRIPTION = {
     "3d_n255_l2b": "3D Dirichlet ADR 255^3 interior, Lawson2b, tau=1e-3, 100 steps to T=0.1",
     "3d_n127_l2b": "3D Dirichlet ADR 127^3 interior, Lawson2b, tau=5e-4, 200 steps to T=0.1",
@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--workload", default=WORKLOAD, help="one of synth.WORKLOADS")
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--modes", default="fp64,fp32,bf16x6,bf16x3")
+    ap.add_argument("--modes", default="fp64,fp32,bf16x6,bf16x3,sliced6,sliced7")
     ap.add_argument("--headline", default="fp64")
     ap.add_argument("--latency-reps", type=int, default=20)
     ap.add_argument("--graph-steps", type=int, default=0,
@@ -83,6 +83,18 @@ def measured_traffic():
         return None
     sha = hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()
     return float(m_bytes.group(1)) if sha == m_sha.group(1) else None
+
+
+def dtype_name(prec):
+    """Arithmetic type of a mode's contractions."""
+    if prec.startswith("sliced"):
+        return f"i8x{prec[6:]}"          # S int8 digit planes, int32 accumulation, f64 combination
+    return {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}[prec]
+
+
+def slice_products(prec):
+    S = int(prec[6:])
+    return S * (S + 1) // 2
 
 
 def time_mode(mm, ctx, p, prec, steps, warmup, graph_steps=0):
@@ -255,7 +267,12 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
     else:
         dtype_peak = {"fp64": "fp64", "fp32": "fp32"}.get(args.headline, "bf16")
-        if dtype_peak == "bf16":
+        if args.headline.startswith("sliced"):
+            # int8 digit products actually executed: S(S+1)/2 per algorithmic multiply-add
+            achieved = k["work"] * slice_products(args.headline) / (k["total_ms"] * 1e-3)
+            roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["int8"] / 1e12,
+                    "unit": "TOP/s"}
+        elif dtype_peak == "bf16":
             # split-BF16 contractions are bound by HBM: 16 B per grid point per pass
             flops_per_point = 2.0 * p.n[0]
             bytes_ = 16.0 * k["work"] / flops_per_point
@@ -282,7 +299,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}[args.headline],
+        "dtype": dtype_name(args.headline),
         "data": "synthetic",
         "config": {"workload": DESCRIPTION.get(args.workload, args.workload),
                    "dof": p.dof, "scheme": p.scheme, "headline_mode": args.headline,

@@ -51,17 +51,23 @@ typedef enum {
   MM_ENOTFOUND = -6   /* unknown request id                                        */
 } mm_status;
 
-/* Arithmetic of the mu-mode contractions. Setup, the remainder stencil and the stage
- * updates are FP64 in every mode; state between contraction passes is FP64.
+/* Arithmetic of the mu-mode contractions. Setup (factors in FP64), the remainder
+ * stencil and the stage updates are FP64 in every mode, and so is the state u.
  *   MM_FP64      FP64 MFMA, FP64 accumulation (the plain baseline).
- *   MM_FP32      operands rounded to FP32 (nearest even), FP32 MFMA over 16-long
- *                K-chunks, chunk sums accumulated in FP64.
- *   MM_BF16X3    each operand split x = hi + lo into two BF16 values (nearest even);
- *                hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32 over 32-long K-chunks,
- *                chunk sums in FP64 ("split-BF16 x3").
+ *   MM_FP32      factors rounded to FP32 at setup, grid operands rounded to FP32
+ *                (nearest even) while staged; FP32 MFMA with FP32 accumulation. The
+ *                values passed between the passes of one action are FP32.
+ *   MM_BF16X3    factors split at setup, grid operands while staged, into two BF16
+ *                values x = hi + lo (each nearest even); hi*hi + hi*lo + lo*hi on the
+ *                BF16 MFMA with FP32 accumulation; FP32 between passes.
  *   MM_BF16X6    three BF16 slices x = s0 + s1 + s2; the six products s_i*s_j with
- *                i + j <= 2, same accumulation.                                      */
-typedef enum { MM_FP64 = 0, MM_FP32 = 1, MM_BF16X3 = 2, MM_BF16X6 = 3 } mm_prec;
+ *                i + j <= 2, otherwise as MM_BF16X3.
+ *   MM_SLICED    exact slicing: every operand row gets a power-of-two scale and is
+ *                written as S signed base-128 digits (S = `slices`, 3..8, default 7);
+ *                the digit products s + t < S run on the int8 MFMA, where int32
+ *                accumulation is exact, and are combined in FP64. Error about
+ *                2^(-7S) relative to the row scales, whatever K; FP64 between passes. */
+typedef enum { MM_FP64 = 0, MM_FP32 = 1, MM_BF16X3 = 2, MM_BF16X6 = 3, MM_SLICED = 4 } mm_prec;
 
 /* Scheme families and members (Appendix).
  *   family MM_LAWSON: MM_LAWSON_EULER  u+ = e^{tau A}(u + tau g(u))
@@ -105,12 +111,13 @@ const char* mm_version(void);
  * Kronecker factors): a_max by a device reduction, the tridiagonal A_mu, and on the
  * device in FP64 the dense factors E_mu(c) = exp(c tau A_mu) by [13/13] Pade
  * scaling-and-squaring for every c the scheme needs (c = 1 and the quadrature nodes
- * theta_j for MM_ERK), plus FP32 or BF16-slice copies for the mixed modes. Returns
- * after the setup has finished. quad_nodes (q) is 1..7 for MM_ERK and ignored for
- * MM_LAWSON. slices is reserved (0). `a` must be complete when the call is made (the
+ * theta_j for MM_ERK), plus the FP32, BF16-slice or digit-plane forms the precision
+ * needs. Returns after the setup has finished. quad_nodes (q) is 1..7 for MM_ERK and
+ * ignored for MM_LAWSON. slices: digit count of MM_SLICED (0 = 7, else 3..8), ignored
+ * by the other precisions. `a` must be complete when the call is made (the
  * copy runs on the context's own stream, which does not wait for other streams).
  * Errors: MM_EINVAL (d, n < 1, tau <= 0 or not finite, unknown family/scheme/prec,
- * a == NULL), MM_ENOMEM, MM_EDEVICE. */
+ * slices out of range, a == NULL), MM_ENOMEM, MM_EDEVICE. */
 mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int family, int scheme,
                        int quad_nodes, int prec, int slices, mm_op** out);
 /* Release the op. Work enqueued with it must have completed (synchronise first). */
@@ -182,10 +189,12 @@ mm_status mm_set_gemm_tile(mm_ctx* ctx, int tile);
 mm_status mm_set_graph_steps(mm_ctx* ctx, int steps);
 
 /* ---------------------------------------------------------------------------------
- * Serving: a request loop on its own host thread and HIP stream. Requests that arrive
- * while others run are admitted as slots and device memory allow; admitted requests
- * advance one Lawson2b step per round, so their kernels interleave on the device;
- * finished requests are retired and their memory released.
+ * Serving: continuous batching of Lawson2b solves. Four admission threads, each with
+ * its own context and stream, copy a request's data to the device and build its
+ * operator as soon as a slot and its device-memory footprint fit; a step thread then
+ * enqueues all of the request's steps on the least-loaded of four streams, so the
+ * kernels of concurrent requests interleave on the device, and retires finished
+ * requests (result copied back, memory released) as their completion events fire.
  * ------------------------------------------------------------------------------- */
 typedef struct {
   int d;
@@ -199,6 +208,7 @@ typedef struct {
   double tau;
   int steps;
   int prec;              /* mm_prec                                                   */
+  int slices;            /* digit count for MM_SLICED (0 = 7)                          */
 } mm_request;
 
 typedef struct {

@@ -25,7 +25,17 @@ MM_LAWSON, MM_ERK = 0, 1
 MM_LAWSON_EULER, MM_LAWSON2B = 0, 1
 MM_ETD2RK, MM_ERK2P1 = 0, 1
 
+MM_SLICED = 4
 PRECISIONS = {"fp64": MM_FP64, "fp32": MM_FP32, "bf16x3": MM_BF16X3, "bf16x6": MM_BF16X6}
+# exact slicing with S base-128 digits: "sliced3" .. "sliced8"
+PRECISIONS.update({f"sliced{s}": MM_SLICED for s in range(3, 9)})
+
+
+def prec_code(prec: str):
+    """(mm_prec, slices) of a precision name."""
+    if prec not in PRECISIONS:
+        raise ValueError(f"unknown precision {prec!r}; one of {sorted(PRECISIONS)}")
+    return PRECISIONS[prec], (int(prec[6:]) if prec.startswith("sliced") else 0)
 SCHEMES = {"le": (MM_LAWSON, MM_LAWSON_EULER), "l2b": (MM_LAWSON, MM_LAWSON2B),
            "etd2rk": (MM_ERK, MM_ETD2RK), "erk2p1f": (MM_ERK, MM_ERK2P1)}
 STATUS = {0: "MM_OK", 1: "MM_NOT_READY", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EDEVICE",
@@ -49,7 +59,8 @@ class MMProblem(Structure):
 class MMRequest(Structure):
     _fields_ = [("d", c_int), ("n", c_int * 3), ("a", c_void_p), ("u0", c_void_p),
                 ("beta", c_double * 3), ("r", c_double * 4), ("lam", c_double),
-                ("beta_bar", c_double * 3), ("tau", c_double), ("steps", c_int), ("prec", c_int)]
+                ("beta_bar", c_double * 3), ("tau", c_double), ("steps", c_int), ("prec", c_int),
+                ("slices", c_int)]
 
 
 class MMStats(Structure):
@@ -247,7 +258,8 @@ def mumode_setup(ctx: Context, d: int, n: Sequence[int], a, beta: Sequence[float
     _torch().cuda.current_stream(a.device).synchronize()   # a must be complete
     fam, sch = SCHEMES[scheme]
     h = c_void_p()
-    st = lib().mumode_setup(ctx.handle, byref(prob), float(tau), fam, sch, int(q), PRECISIONS[prec], 0,
+    code, slices = prec_code(prec)
+    st = lib().mumode_setup(ctx.handle, byref(prob), float(tau), fam, sch, int(q), code, slices,
                             byref(h))
     ctx.check(st, "mumode_setup")
     return Operator(ctx, h, prob, scheme, prec, q if fam == MM_ERK else 0)

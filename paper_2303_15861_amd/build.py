@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmumode.so")
 
-HIP_SOURCES = ["contract.hip", "stencil.hip"]
+HIP_SOURCES = ["contract.hip", "stencil.hip", "sliced.hip"]
 CPP_SOURCES = ["api.cpp", "server.cpp"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result", "-Wno-unused-value",
           "-I" + os.path.join(ROOT, "include")]
@@ -34,9 +34,8 @@ def _hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc()] + COMMON
-    if src.endswith(".hip"):
-        cmd += HIP_FLAGS
+    # host sources include the HIP runtime headers and go through the same driver
+    cmd = [_hipcc()] + COMMON + HIP_FLAGS
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"

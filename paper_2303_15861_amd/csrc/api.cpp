@@ -240,13 +240,40 @@ struct PassIO {
   bool in_f32 = false, out_f32 = false;
 };
 
+// Low-precision modes pass FP32 values between the passes of an action.
+bool lowp(const mm_op* op) { return op->prec == MM_FP32 || op->prec == MM_BF16X3 || op->prec == MM_BF16X6; }
+
+// padded row stride of the factor operand for contraction length k
+int factor_ld(const mm_op* op, int k) {
+  return op->prec == MM_FP64 ? k : op->prec == MM_SLICED ? slice_ld(k) : fac_ld(k);
+}
+
+// elements per slice plane of a rows x k factor operand (0 for single-plane formats)
+int64_t factor_slice_stride(const mm_op* op, int rows, int k) {
+  if (op->prec == MM_FP64 || op->prec == MM_FP32) return 0;
+  return (int64_t)rows * factor_ld(op, k);
+}
+
+// bytes of one n x n factor operand in the op's precision, all slices
+int64_t factor_bytes(const mm_op* op, int n) {
+  switch (op->prec) {
+    case MM_FP64: return (int64_t)n * n * 8;
+    case MM_FP32: return (int64_t)n * fac_ld(n) * 4;
+    case MM_SLICED: return (int64_t)n * slice_ld(n) * op->slices;
+    default: return (int64_t)n * fac_ld(n) * 2 * factor_slices(op->prec);
+  }
+}
+
 // the factor operand of axis mu, coefficient index j, in the op's precision
 const void* factor_op(const mm_op* op, int mu, int j) {
   if (op->prec == MM_FP64) return op->fac[mu] + (int64_t)j * op->n[mu] * op->n[mu];
-  const int n = op->n[mu];
-  const int64_t per = (int64_t)n * fac_ld(n) * factor_slices(op->prec);
-  const int64_t esz = (op->prec == MM_FP32) ? 4 : 2;
-  return (const char*)op->fac_lp[mu] + j * per * esz;
+  return (const char*)op->fac_lp[mu] + j * factor_bytes(op, op->n[mu]);
+}
+
+// per-row exponents of that factor (MM_SLICED only, else null)
+const int* factor_exp(const mm_op* op, int mu, int j) {
+  if (op->prec != MM_SLICED) return nullptr;
+  return op->fac_exp[mu] + (int64_t)j * op->n[mu];
 }
 
 // the stacked last-axis factor of an ERK stage in the op's precision
@@ -255,23 +282,25 @@ const void* stacked(const mm_op* op, int which) {
   return which == 1 ? op->f3_stage1_lp : which == 2 ? op->f3_stage2_lp : op->f3_phi_lp;
 }
 
-int64_t factor_slice_stride(const mm_op* op, int rows, int k) {
-  return (int64_t)rows * fac_ld(k) * (op->prec == MM_FP32 ? 0 : 1);
+const int* stacked_exp(const mm_op* op, int which) {
+  return which == 1 ? op->f3_stage1_exp : which == 2 ? op->f3_stage2_exp : op->f3_phi_exp;
 }
 
-int factor_ld(const mm_op* op, int k) { return op->prec == MM_FP64 ? k : fac_ld(k); }
-
-// mode 1: C (rows x n1) = A (rows x n1) . E1^T, per group (input, factor, output)
+// mode 1: C (rows x n1) = A (rows x n1) . E1^T, per group (input, factor, output);
+// galpha: optional per-group output scales (sliced mode only)
 hipError_t pass_mode1(const mm_op* op, int groups, const void* const* in, const int* fidx,
-                      void* const* out, int rows, PassIO io, hipStream_t s) {
+                      void* const* out, int rows, PassIO io, hipStream_t s, const double* galpha = nullptr) {
   const int n1 = op->n[0];
   GemmArgs g{};
   for (int i = 0; i < groups; ++i) {
     g.A[i] = in[i];
     g.B[i] = factor_op(op, 0, fidx[i]);
+    g.fexp[i] = factor_exp(op, 0, fidx[i]);
+    g.galpha[i] = galpha ? galpha[i] : 0.0;
     g.C[i] = out[i];
     g.Cadd[i] = nullptr;
   }
+  g.slices = op->slices;
   g.M = rows;
   g.N = n1;
   g.K = n1;
@@ -295,10 +324,12 @@ hipError_t pass_mode2(const mm_op* op, int groups, const int* fidx, const void* 
   GemmArgs g{};
   for (int i = 0; i < groups; ++i) {
     g.A[i] = factor_op(op, 1, fidx[i]);
+    g.fexp[i] = factor_exp(op, 1, fidx[i]);
     g.B[i] = in[i];
     g.C[i] = out[i];
     g.Cadd[i] = nullptr;
   }
+  g.slices = op->slices;
   g.M = op->n[1];
   g.N = op->n[0];
   g.K = op->n[1];
@@ -320,13 +351,16 @@ hipError_t pass_mode2(const mm_op* op, int groups, const int* fidx, const void* 
 
 // last mode: C (nl x P) = alpha * F (nl x K) . B (K x P) + beta * add, K = kmul * nl,
 // P = dof / nl; `inner` stacked vectors of stride dof (same factor). F is the factor
-// operand in the op's precision (row stride factor_ld(K)).
-hipError_t pass_last(const mm_op* op, const void* F, int kmul, const void* in, void* out, const double* add,
-                     double alpha, double beta, int inner, PassIO io, hipStream_t s) {
+// operand in the op's precision (row stride factor_ld(K)), Fexp its row exponents
+// (MM_SLICED).
+hipError_t pass_last(const mm_op* op, const void* F, const int* Fexp, int kmul, const void* in, void* out,
+                     const double* add, double alpha, double beta, int inner, PassIO io, hipStream_t s) {
   const int nl = op->n[last_axis(op)];
   const int P = (int)(op->dof / nl);
   GemmArgs g{};
   g.A[0] = F;
+  g.fexp[0] = Fexp;
+  g.slices = op->slices;
   g.B[0] = in;
   g.C[0] = out;
   g.Cadd[0] = add;
@@ -358,13 +392,14 @@ const double* factor(const mm_op* op, int mu, int j) {
 // modes the intermediates t0, t1 hold floats.
 hipError_t exp_action(const mm_op* op, int j, const void* in, bool in_f32, double* out, int nvec, double* t0,
                       double* t1, hipStream_t s) {
-  const bool mixed = op->prec != MM_FP64;
+  const bool mixed = lowp(op);
   PassIO first{in_f32, mixed}, mid{mixed, mixed}, last_io{mixed, false};
   const int fj[1] = {j};
   const void* i1[1] = {in};
   void* o1[1] = {t0};
   const int la = last_axis(op);
-  const void* Fl = (op->prec == MM_FP64) ? (const void*)factor(op, la, j) : factor_op(op, la, j);
+  const void* Fl = factor_op(op, la, j);
+  const int* Fe = factor_exp(op, la, j);
   if (op->d == 3) {
     hipError_t e = pass_mode1(op, 1, i1, fj, o1, (int)(op->dof / op->n[0]) * nvec, first, s);
     if (e != hipSuccess) return e;
@@ -372,21 +407,22 @@ hipError_t exp_action(const mm_op* op, int j, const void* in, bool in_f32, doubl
     void* o2[1] = {t1};
     e = pass_mode2(op, 1, fj, i2, o2, op->n[2] * nvec, mid, s);
     if (e != hipSuccess) return e;
-    return pass_last(op, Fl, 1, t1, out, nullptr, 1.0, 0.0, nvec, last_io, s);
+    return pass_last(op, Fl, Fe, 1, t1, out, nullptr, 1.0, 0.0, nvec, last_io, s);
   }
   hipError_t e = pass_mode1(op, 1, i1, fj, o1, (int)(op->dof / op->n[0]) * nvec, first, s);
   if (e != hipSuccess) return e;
   PassIO l2{mixed, false};
-  return pass_last(op, Fl, 1, t0, out, nullptr, 1.0, 0.0, nvec, l2, s);
+  return pass_last(op, Fl, Fe, 1, t0, out, nullptr, 1.0, 0.0, nvec, l2, s);
 }
 
 // out = stacked-last-factor contraction over G groups: group g applies modes 1..d-1 with
-// factor index fidx[g] to the FP64 input ins[g]; the last mode sums the groups with the
-// stacked factor F3 (nl x G*nl, in the op's precision) and adds beta*add. t0 and t1
-// hold G grid functions each (floats in the mixed modes).
+// factor index fidx[g] to the FP64 input ins[g] (scaled by w1[g] when given); the last
+// mode sums the groups with the stacked factor F3 (nl x G*nl, in the op's precision)
+// and adds beta*add. t0 and t1 hold G grid functions each (floats in the mixed modes).
 hipError_t grouped_action(const mm_op* op, int G, const double* const* ins, const int* fidx, const void* F3,
-                          double* out, const double* add, double beta, double* t0, double* t1, hipStream_t s) {
-  const bool mixed = op->prec != MM_FP64;
+                          const int* F3exp, double* out, const double* add, double beta, double* t0, double* t1,
+                          hipStream_t s, const double* w1 = nullptr) {
+  const bool mixed = lowp(op);
   const int64_t esz = mixed ? 4 : 8;
   const void* in1[kMaxGroups];
   void* o1[kMaxGroups];
@@ -394,7 +430,7 @@ hipError_t grouped_action(const mm_op* op, int G, const double* const* ins, cons
     in1[g] = ins[g];
     o1[g] = (char*)t0 + g * op->dof * esz;
   }
-  hipError_t e = pass_mode1(op, G, in1, fidx, o1, (int)(op->dof / op->n[0]), PassIO{false, mixed}, s);
+  hipError_t e = pass_mode1(op, G, in1, fidx, o1, (int)(op->dof / op->n[0]), PassIO{false, mixed}, s, w1);
   if (e != hipSuccess) return e;
   if (op->d == 3) {
     const void* i2[kMaxGroups];
@@ -405,9 +441,23 @@ hipError_t grouped_action(const mm_op* op, int G, const double* const* ins, cons
     }
     e = pass_mode2(op, G, fidx, i2, o2, op->n[2], PassIO{mixed, mixed}, s);
     if (e != hipSuccess) return e;
-    return pass_last(op, F3, G, t1, out, add, 1.0, beta, 1, PassIO{mixed, false}, s);
+    return pass_last(op, F3, F3exp, G, t1, out, add, 1.0, beta, 1, PassIO{mixed, false}, s);
   }
-  return pass_last(op, F3, G, t0, out, add, 1.0, beta, 1, PassIO{mixed, false}, s);
+  return pass_last(op, F3, F3exp, G, t0, out, add, 1.0, beta, 1, PassIO{mixed, false}, s);
+}
+
+// Sliced mode keeps the stacked last-axis blocks unweighted (so that one row exponent
+// suits every block) and applies the stage's quadrature weights as per-group scales of
+// the first pass instead; other precisions fold the weights into the stacked factor.
+// which: 1 stage one (ETD2RK: [1, tau w_j]; ERK2P1: [tau w_j]), 2 stage two
+// ([tau/2 w_j]), 3 phi1 ([w_j]). Returns null when the weights are in the factor.
+const double* stage_weights(const mm_op* op, int which, double* w) {
+  if (op->prec != MM_SLICED) return nullptr;
+  int k = 0;
+  if (which == 1 && op->scheme == MM_ETD2RK) w[k++] = 1.0;
+  const double c = (which == 3) ? 1.0 : (which == 2) ? 0.5 * op->tau : op->tau;
+  for (int j = 1; j <= op->q; ++j) w[k++] = c * op->weight[j];
+  return w;
 }
 
 StencilArgs stencil_args(const mm_op* op, const double* u, bool full) {
@@ -519,6 +569,11 @@ void mumode_destroy(mm_op* op) {
   dev_free(op, op->f3_stage1_lp);
   dev_free(op, op->f3_stage2_lp);
   dev_free(op, op->f3_phi_lp);
+  for (size_t i = 0; i < op->fac_exp.size(); ++i)
+    if (op->fac_owned[i]) dev_free(op, op->fac_exp[i]);
+  dev_free(op, op->f3_stage1_exp);
+  dev_free(op, op->f3_stage2_exp);
+  dev_free(op, op->f3_phi_exp);
   for (int i = 0; i < 6; ++i) dev_free(op, op->buf[i]);
   dev_free(op, op->flag);
   if (op->gexec) hipGraphExecDestroy(op->gexec);
@@ -566,15 +621,18 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     set_err(ctx, "quad_nodes must be 1..%d", kMaxGroups - 1);
     return MM_EINVAL;
   }
-  if (prec < MM_FP64 || prec > MM_BF16X6) {
+  if (prec < MM_FP64 || prec > MM_SLICED) {
     set_err(ctx, "unknown precision %d", prec);
+    return MM_EINVAL;
+  }
+  if (prec == MM_SLICED && slices != 0 && (slices < kMinSlices || slices > kMaxSlices)) {
+    set_err(ctx, "slices must be 0 or %d..%d", kMinSlices, kMaxSlices);
     return MM_EINVAL;
   }
   if (!std::isfinite(prob->lambda) || prob->lambda < 0.0) {
     set_err(ctx, "lambda must be finite and >= 0");
     return MM_EINVAL;
   }
-  (void)slices;
   HIPCHK(ctx, hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
 
@@ -593,6 +651,7 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
   op->scheme = scheme;
   op->q = (family == MM_ERK) ? quad_nodes : 0;
   op->prec = prec;
+  op->slices = (prec == MM_SLICED) ? (slices ? slices : kDefaultSlices) : 0;
   op->dof = (int64_t)op->n[0] * op->n[1] * op->n[2];
   int64_t na = 1;
   for (int mu = 0; mu < op->d; ++mu) na *= op->n[mu] + 2;
@@ -681,24 +740,41 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     set_err(ctx, "factor setup failed on the device");
     return fail(MM_EDEVICE);
   }
-  // mixed modes: FP32 or BF16-slice copies with zero-padded rows
-  const int nsl = factor_slices(prec);
-  const int64_t esz = (prec == MM_FP32) ? 4 : 2;
+  // other precisions: FP32, BF16-slice or digit-plane forms with zero-padded rows
   op->fac_lp.assign(op->d, nullptr);
+  op->fac_exp.assign(op->d, nullptr);
+  // convert `rows` x k (row stride lds) FP64 into the op's factor format at dst (exps:
+  // per-row exponents for MM_SLICED)
+  auto convert = [&](void* dst, int* exps, const double* src, int rows, int k, int lds) -> hipError_t {
+    if (prec == MM_SLICED)
+      return launch_slice_rows((signed char*)dst, exps, src, rows, k, lds, slice_ld(k), op->slices, st);
+    return launch_convert_factor(prec, dst, src, rows, k, lds, st);
+  };
+  // bytes of a rows x k factor operand in the op's format
+  auto op_bytes = [&](int rows, int k) -> int64_t {
+    if (prec == MM_SLICED) return (int64_t)rows * slice_ld(k) * op->slices;
+    if (prec == MM_FP32) return (int64_t)rows * fac_ld(k) * 4;
+    return (int64_t)rows * fac_ld(k) * 2 * factor_slices(prec);
+  };
   if (prec != MM_FP64) {
     for (int mu = 0; mu < op->d; ++mu) {
       if (!op->fac_owned[mu]) {
         for (int nu = 0; nu < mu; ++nu)
-          if (op->fac[nu] == op->fac[mu]) op->fac_lp[mu] = op->fac_lp[nu];
+          if (op->fac[nu] == op->fac[mu]) {
+            op->fac_lp[mu] = op->fac_lp[nu];
+            op->fac_exp[mu] = op->fac_exp[nu];
+          }
         continue;
       }
       const int n = op->n[mu];
-      const int64_t per = (int64_t)n * fac_ld(n) * nsl;
+      const int64_t per = op_bytes(n, n);
       char* dst = nullptr;
-      if ((rc = dev_alloc(op, &dst, nf * per * esz)) != MM_OK) return fail(rc);
+      if ((rc = dev_alloc(op, &dst, nf * per)) != MM_OK) return fail(rc);
       op->fac_lp[mu] = dst;
+      if (prec == MM_SLICED && (rc = dev_alloc(op, &op->fac_exp[mu], (int64_t)nf * n)) != MM_OK) return fail(rc);
       for (int j = 0; j < nf; ++j)
-        HIPCHK(ctx, launch_convert_factor(prec, dst + j * per * esz, op->fac[mu] + (int64_t)j * n * n, n, n, n, st));
+        HIPCHK(ctx, convert(dst + j * per, prec == MM_SLICED ? op->fac_exp[mu] + j * n : nullptr,
+                            op->fac[mu] + (int64_t)j * n * n, n, n, n));
     }
   }
 
@@ -717,15 +793,18 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
       HIPCHK(ctx, launch_place_scaled(op->f3_stage1, g1 * nl, 0, factor(op, la, 0), nl, 1.0, st));
       col = nl;
     }
+    // sliced mode: unweighted blocks (the weights scale the first pass instead)
+    const bool unit = prec == MM_SLICED;
     for (int j = 1; j <= q; ++j) {
       HIPCHK(ctx, launch_place_scaled(op->f3_stage1, g1 * nl, col + (j - 1) * nl, factor(op, la, j), nl,
-                                      tau * op->weight[j], st));
+                                      unit ? 1.0 : tau * op->weight[j], st));
       HIPCHK(ctx, launch_place_scaled(op->f3_stage2, q * nl, (j - 1) * nl, factor(op, la, j), nl,
-                                      0.5 * tau * op->weight[j], st));
-      HIPCHK(ctx, launch_place_scaled(op->f3_phi, q * nl, (j - 1) * nl, factor(op, la, j), nl, op->weight[j], st));
+                                      unit ? 1.0 : 0.5 * tau * op->weight[j], st));
+      HIPCHK(ctx, launch_place_scaled(op->f3_phi, q * nl, (j - 1) * nl, factor(op, la, j), nl,
+                                      unit ? 1.0 : op->weight[j], st));
     }
     if (prec != MM_FP64) {
-      const int64_t s1 = (int64_t)nl * fac_ld(g1 * nl) * nsl * esz, s2 = (int64_t)nl * fac_ld(q * nl) * nsl * esz;
+      const int64_t s1 = op_bytes(nl, g1 * nl), s2 = op_bytes(nl, q * nl);
       char *d1 = nullptr, *d2 = nullptr, *d3 = nullptr;
       if ((rc = dev_alloc(op, &d1, s1)) != MM_OK) return fail(rc);
       op->f3_stage1_lp = d1;
@@ -733,9 +812,14 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
       op->f3_stage2_lp = d2;
       if ((rc = dev_alloc(op, &d3, s2)) != MM_OK) return fail(rc);
       op->f3_phi_lp = d3;
-      HIPCHK(ctx, launch_convert_factor(prec, d1, op->f3_stage1, nl, g1 * nl, g1 * nl, st));
-      HIPCHK(ctx, launch_convert_factor(prec, d2, op->f3_stage2, nl, q * nl, q * nl, st));
-      HIPCHK(ctx, launch_convert_factor(prec, d3, op->f3_phi, nl, q * nl, q * nl, st));
+      if (prec == MM_SLICED) {
+        if ((rc = dev_alloc(op, &op->f3_stage1_exp, nl)) != MM_OK) return fail(rc);
+        if ((rc = dev_alloc(op, &op->f3_stage2_exp, nl)) != MM_OK) return fail(rc);
+        if ((rc = dev_alloc(op, &op->f3_phi_exp, nl)) != MM_OK) return fail(rc);
+      }
+      HIPCHK(ctx, convert(d1, op->f3_stage1_exp, op->f3_stage1, nl, g1 * nl, g1 * nl));
+      HIPCHK(ctx, convert(d2, op->f3_stage2_exp, op->f3_stage2, nl, q * nl, q * nl));
+      HIPCHK(ctx, convert(d3, op->f3_phi_exp, op->f3_phi, nl, q * nl, q * nl));
     }
     // buffers: 0 g0, 1 T1 ((q+1) dof), 2 T2 ((q+1) dof), 3 U, 4 D, 5 F0 (ERK2P1)
     const int64_t lens[6] = {dof, (q + 1) * dof, (q + 1) * dof, dof, dof, scheme == MM_ERK2P1 ? dof : 0};
@@ -828,7 +912,9 @@ mm_status mumode_phi1v(mm_ctx* ctx, const mm_op* op, const double* in, double* o
     ins[g] = in;
     fidx[g] = g + 1;
   }
-  HIPCHK(ctx, grouped_action(op, op->q, ins, fidx, stacked(op, 3), out, nullptr, 0.0, op->buf[1], op->buf[2], s));
+  double w[kMaxGroups];
+  HIPCHK(ctx, grouped_action(op, op->q, ins, fidx, stacked(op, 3), stacked_exp(op, 3), out, nullptr, 0.0,
+                                 op->buf[1], op->buf[2], s, stage_weights(op, 3, w)));
   return MM_OK;
 }
 
@@ -842,7 +928,7 @@ mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hi
   const int64_t dof = op->dof;
   double* b0 = op->buf[0];
   double* b1 = op->buf[1];
-  const bool mixed = op->prec != MM_FP64;
+  const bool mixed = lowp(op);
   for (int it = 0; it < nsteps; ++it) {
     if (op->scheme == MM_LAWSON_EULER) {
       // u+ = e^{tau A}(u + tau g(u))
@@ -890,6 +976,7 @@ mm_status enqueue_erk(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hipSt
          *F0 = op->buf[5];
   const double* ins[kMaxGroups];
   int fidx[kMaxGroups];
+  double w1[kMaxGroups], w2[kMaxGroups];
   for (int it = 0; it < nsteps; ++it) {
     StencilArgs a = stencil_args(op, u, false);
     a.out0 = g0;
@@ -902,7 +989,8 @@ mm_status enqueue_erk(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hipSt
         ins[j] = g0;
         fidx[j] = j;
       }
-      HIPCHK(ctx, grouped_action(op, q + 1, ins, fidx, stacked(op, 1), U, nullptr, 0.0, T1, T2, s));
+      HIPCHK(ctx, grouped_action(op, q + 1, ins, fidx, stacked(op, 1), stacked_exp(op, 1), U, nullptr, 0.0, T1, T2,
+                                 s, stage_weights(op, 1, w1)));
     } else {
       // U = u + tau sum_j w_j e^{theta_j tau A} F(u)
       StencilArgs f = stencil_args(op, u, true);
@@ -912,7 +1000,8 @@ mm_status enqueue_erk(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hipSt
         ins[j] = F0;
         fidx[j] = j + 1;
       }
-      HIPCHK(ctx, grouped_action(op, q, ins, fidx, stacked(op, 1), U, u, 1.0, T1, T2, s));
+      HIPCHK(ctx, grouped_action(op, q, ins, fidx, stacked(op, 1), stacked_exp(op, 1), U, u, 1.0, T1, T2, s,
+                                 stage_weights(op, 1, w1)));
     }
     // D = g(U) - g0;  u+ = U + tau/2 sum_j w_j e^{theta_j tau A} D
     StencilArgs b = stencil_args(op, U, false);
@@ -923,7 +1012,8 @@ mm_status enqueue_erk(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hipSt
       ins[j] = D;
       fidx[j] = j + 1;
     }
-    HIPCHK(ctx, grouped_action(op, q, ins, fidx, stacked(op, 2), u, U, 1.0, T1, T2, s));
+    HIPCHK(ctx, grouped_action(op, q, ins, fidx, stacked(op, 2), stacked_exp(op, 2), u, U, 1.0, T1, T2, s,
+                               stage_weights(op, 2, w2)));
   }
   return MM_OK;
 }

@@ -570,11 +570,22 @@ hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.inner <= 0 || g.groups <= 0 || g.groups > kMaxGroups)
     return hipErrorInvalidValue;
   if (g.tile != 0 && g.tile != 64 && g.tile != 128) return hipErrorInvalidValue;
+  if (prec == MM_SLICED && (g.in_f32 || g.out_f32)) return hipErrorInvalidValue;
   // in-batch offsets are 32-bit
   const int64_t lim = (int64_t)1 << 31;
   if ((int64_t)g.M * g.lda >= lim || (int64_t)g.M * g.ldc >= lim ||
       (int64_t)(g.b_trans ? g.K : g.N) * g.ldb >= lim)
     return hipErrorInvalidValue;
+  if (prec != MM_SLICED)
+    for (int i = 0; i < g.groups; ++i)
+      if (g.galpha[i] != 0.0) return hipErrorInvalidValue;   // per-group scales: sliced mode only
+  if (prec == MM_SLICED) {
+    const int ldf = g.b_trans ? g.lda : g.ldb;
+    if (ldf < slice_ld(g.K) || ldf % 64 != 0) return hipErrorInvalidValue;
+    for (int i = 0; i < g.groups; ++i)
+      if (!g.fexp[i]) return hipErrorInvalidValue;
+    return launch_gemm_sliced(g, s);
+  }
   if (prec != MM_FP64) {
     // the pre-converted factor must have its padded row stride
     const int ldf = g.b_trans ? g.lda : g.ldb;

@@ -36,12 +36,19 @@ struct GemmArgs {
   int in_f32, out_f32;
   int64_t fac_slice;
   int tile;             // workgroup tile: 0 = chosen by the launcher, 64 or 128
+  // MM_SLICED: digit count and per-row exponents of the factor operand of each group
+  int slices;
+  const int* fexp[kMaxGroups];
+  double galpha[kMaxGroups];   // MM_SLICED: extra per-group output scale (0 = none)
   // filled by the launcher
   int tiles_m, tiles_n, total, per_xcd;
 };
 
 constexpr int kFacPad = 32;   // k padding of pre-converted factors
 inline int fac_ld(int k) { return (k + kFacPad - 1) / kFacPad * kFacPad; }
+// digit planes of MM_SLICED: rows zero-padded to a multiple of 64 in k
+constexpr int kMinSlices = 3, kMaxSlices = 8, kDefaultSlices = 7;
+inline int slice_ld(int k) { return (k + 63) / 64 * 64; }
 
 // Stencil launch parameters (remainder g and fused stage updates).
 struct StencilArgs {
@@ -68,6 +75,12 @@ hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s);
 // Tile size the launcher takes for g (g.tile if set, else 64 when 128-tiles would not
 // fill the chip once).
 int choose_tile(const GemmArgs& g);
+// MM_SLICED mode product (64 x 64 tiles; factor operand as digit planes).
+hipError_t launch_gemm_sliced(GemmArgs& g, hipStream_t s);
+// Split rows x k (row stride lds) into S digit planes of row stride ldd (plane stride
+// rows*ldd bytes, zero for k <= c < ldd) and per-row exponents.
+hipError_t launch_slice_rows(signed char* dst, int* exps, const double* src, int rows, int k, int lds, int ldd,
+                             int S, hipStream_t s);
 hipError_t launch_stencil(int d, const StencilArgs& a, hipStream_t s);
 hipError_t launch_max_reduce(const double* x, int64_t n, double* partial, int nparts, double* out,
                              hipStream_t s);
@@ -127,6 +140,7 @@ struct mm_op {
   double tau = 0, lam = 1, a_max = 0;
   double beta[3] = {0, 0, 0}, beta_bar[3] = {0, 0, 0}, r[4] = {0, 0, 0, 0};
   int family = 0, scheme = 0, q = 0, prec = 0;
+  int slices = 0;                      // MM_SLICED digit count
   int squarings[3] = {0, 0, 0};
   double theta[8] = {0}, weight[8] = {0};
   // device memory owned by the op
@@ -141,6 +155,11 @@ struct mm_op {
   void* f3_stage1_lp = nullptr;
   void* f3_stage2_lp = nullptr;
   void* f3_phi_lp = nullptr;
+  // MM_SLICED: per-row exponents of the digit-plane factors (same stacking)
+  std::vector<int*> fac_exp;
+  int* f3_stage1_exp = nullptr;
+  int* f3_stage2_exp = nullptr;
+  int* f3_phi_exp = nullptr;
   double* buf[6] = {nullptr};          // scratch
   int64_t buf_len[6] = {0};
   int* flag = nullptr;                 // sticky non-finite flag

@@ -166,7 +166,7 @@ struct mm_server {
     p.a = da;
     // mumode_setup ends with a synchronisation of actx's stream: a, u and the op are
     // ready for any stream afterwards
-    const int st = mumode_setup(actx, &p, r.tau, MM_LAWSON, MM_LAWSON2B, 0, r.prec, 0, &j.op);
+    const int st = mumode_setup(actx, &p, r.tau, MM_LAWSON, MM_LAWSON2B, 0, r.prec, r.slices, &j.op);
     hipFreeAsync(da, cs);
     if (st != MM_OK) {
       j.op = nullptr;
@@ -361,7 +361,8 @@ double mm_server_clock(const mm_server* s) { return s ? s->now() : 0.0; }
 mm_status solve_submit(mm_server* s, const mm_request* r, uint64_t* id) {
   if (!s || !r || !id) return MM_EINVAL;
   if ((r->d != 2 && r->d != 3) || !r->a || !r->u0 || !(r->tau > 0) || r->steps < 0 ||
-      r->prec < MM_FP64 || r->prec > MM_BF16X6)
+      r->prec < MM_FP64 || r->prec > MM_SLICED ||
+      (r->prec == MM_SLICED && r->slices != 0 && (r->slices < mm::kMinSlices || r->slices > mm::kMaxSlices)))
     return MM_EINVAL;
   int64_t dof = 1, na = 1;
   for (int mu = 0; mu < r->d; ++mu) {

@@ -37,7 +37,7 @@ class Server:
 
 def solve_submit(srv: Server, prob, prec: str = "fp64") -> Tuple[int, int]:
     """Queue a Lawson2b solve of a ``synth.Problem``; returns (status, id)."""
-    from . import PRECISIONS, MMRequest
+    from . import MMRequest, prec_code
     req = MMRequest()
     req.d = prob.d
     a = np.ascontiguousarray(prob.a, dtype=np.float64)
@@ -51,7 +51,7 @@ def solve_submit(srv: Server, prob, prec: str = "fp64") -> Tuple[int, int]:
     req.lam = float(prob.lam)
     req.tau = float(prob.tau)
     req.steps = int(prob.steps)
-    req.prec = PRECISIONS[prec]
+    req.prec, req.slices = prec_code(prec)
     req.a = a.ctypes.data
     req.u0 = u0.ctypes.data
     rid = c_uint64()
