@@ -63,10 +63,12 @@ typedef enum {
  *   MM_BF16X6    three BF16 slices x = s0 + s1 + s2; the six products s_i*s_j with
  *                i + j <= 2, otherwise as MM_BF16X3.
  *   MM_SLICED    exact slicing: every operand row gets a power-of-two scale and is
- *                written as S signed base-128 digits (S = `slices`, 3..8, default 7);
- *                the digit products s + t < S run on the int8 MFMA, where int32
- *                accumulation is exact, and are combined in FP64. Error about
- *                2^(-7S) relative to the row scales, whatever K; FP64 between passes. */
+ *                written as S balanced base-256 digits in [-128, 127] (S = `slices`,
+ *                3..7, default 6); the digit products s + t < S run on the int8
+ *                MFMA, where the int32 accumulation is exact, and are combined in
+ *                FP64. Error about 2^(-8S) relative to the row scales, whatever K;
+ *                FP64 between passes. Needs S * 2^14 * K < 2^31 for every
+ *                contraction length K (n, or (q+1) n for the ERK stacked mode). */
 typedef enum { MM_FP64 = 0, MM_FP32 = 1, MM_BF16X3 = 2, MM_BF16X6 = 3, MM_SLICED = 4 } mm_prec;
 
 /* Scheme families and members (Appendix).
@@ -113,7 +115,7 @@ const char* mm_version(void);
  * scaling-and-squaring for every c the scheme needs (c = 1 and the quadrature nodes
  * theta_j for MM_ERK), plus the FP32, BF16-slice or digit-plane forms the precision
  * needs. Returns after the setup has finished. quad_nodes (q) is 1..7 for MM_ERK and
- * ignored for MM_LAWSON. slices: digit count of MM_SLICED (0 = 7, else 3..8), ignored
+ * ignored for MM_LAWSON. slices: digit count of MM_SLICED (0 = 6, else 3..7), ignored
  * by the other precisions. `a` must be complete when the call is made (the
  * copy runs on the context's own stream, which does not wait for other streams).
  * Errors: MM_EINVAL (d, n < 1, tau <= 0 or not finite, unknown family/scheme/prec,
@@ -208,7 +210,7 @@ typedef struct {
   double tau;
   int steps;
   int prec;              /* mm_prec                                                   */
-  int slices;            /* digit count for MM_SLICED (0 = 7)                          */
+  int slices;            /* digit count for MM_SLICED (0 = 6)                          */
 } mm_request;
 
 typedef struct {

@@ -5,24 +5,26 @@ The sliced precision is not from the paper; it is an error-free splitting of the
 operands in the manner of Ozaki, Ogita, Oishi and Rump (Numer. Algorithms 59, 2012),
 used here to run the mu-mode products on integer matrix units.
 
-Definition (S digits).
+Definition (S digits, 3 <= S <= 7).
   * Every factor row and every fiber of the grid operand (the values along the
     contracted axis with all other indices fixed) gets the exponent e with
     max|x| < 2^e (the frexp exponent of the maximum; e = 0 for an all-zero row).
-  * A value x becomes the integer Y = min(round_half_even(|x| 2^(7S - e)), 2^(7S) - 1),
-    written in base 128 as S digits d_0 (most significant) .. d_(S-1), each carrying
-    the sign of x:  x ~ sign(x) 2^e sum_s d_s 2^(-7(s+1)).
+  * A value x becomes the integer Y = round_half_even(x 2^(8S - 2 - e)), so that
+    |Y| <= 2^(8S-2), written in balanced base 256: Y = sum_(i<S) b_i 256^i with every
+    b_i in [-128, 127] (unique; S balanced digits reach about 2^(8S-1), so every such
+    Y has one). Digit planes are kept most significant first, d_s = b_(S-1-s), so that
+        x ~ 2^(e+2) sum_s d_s 2^(-8(s+1)).
   * A factor row (exponent a, digits f_s) contracted with a fiber (exponent b,
     digits v_t) keeps the digit products with s + t < S:
-        sum_k f v ~ 2^(a + b - 14) sum_(l<S) 2^(-7 l) P_l,
+        sum_k f v ~ 2^(a + b - 12) sum_(l<S) 2^(-8 l) P_l,
         P_l = sum_(s+t=l) sum_k f_s[k] v_t[k]      (exact integers),
-    combined from the top level down, v <- v 2^-7 + P_l, in FP64.
-The errors are the dropped levels s + t >= S and the rounding of the last digit,
-both of order 2^(-7S) relative to the row and fiber scales.
+    combined from the top level down, v <- v 2^-8 + P_l, in FP64.
+The errors are the dropped levels s + t >= S and the rounding of Y, both of order
+2^(-8S) relative to the row and fiber scales.
 
-Pins: tests/test_oracle_sliced.py (digit round trip against exact integer arithmetic,
-exactness for 7-bit integer data, a pure-Python evaluation of the definition on small
-cases, the 2^(-7S) error bound and its decay with S).
+Pins: tests/test_oracle_sliced.py (digit expansion against exact integer arithmetic,
+exactness for small-integer data, a pure-Python evaluation of the definition on small
+cases, the 2^(-8S) error bound and its decay with S).
 """
 from __future__ import annotations
 
@@ -41,14 +43,15 @@ def exponents(X: np.ndarray) -> np.ndarray:
 
 
 def digits(X: np.ndarray, e: np.ndarray, S: int) -> np.ndarray:
-    """Signed base-128 digits (S, *X.shape) of X relative to row exponents e (X.shape[:-1])."""
-    Y = np.rint(np.ldexp(np.abs(X), (7 * S - e)[..., None]))
-    Y = np.minimum(Y, np.ldexp(1.0, 7 * S) - 1.0)
-    sign = np.where(X < 0.0, -1.0, 1.0)
+    """Balanced base-256 digits (S, *X.shape), most significant first, of X relative to
+    row exponents e (X.shape[:-1])."""
+    Y = np.rint(np.ldexp(X, (8 * S - 2 - e)[..., None])).astype(np.int64)
     out = np.empty((S,) + X.shape)
-    for s in range(S):
-        p = S - 1 - s
-        out[s] = sign * np.mod(np.floor(np.ldexp(Y, -7 * p)), 128.0)
+    for i in range(S):                          # least significant first
+        b = ((Y + 128) & 255) - 128
+        out[S - 1 - i] = b
+        Y = (Y - b) >> 8
+    assert not np.any(Y), "digit expansion did not terminate"
     return out
 
 
@@ -64,8 +67,8 @@ def matmul_rows(A: np.ndarray, B: np.ndarray, S: int) -> np.ndarray:
             P[s + t] += da[s] @ db[t].T
     v = P[S - 1]
     for lvl in range(S - 2, -1, -1):
-        v = v * 2.0 ** -7 + P[lvl]
-    return np.ldexp(v, ea[:, None] + eb[None, :] - 14)
+        v = v * 2.0 ** -8 + P[lvl]
+    return np.ldexp(v, ea[:, None] + eb[None, :] - 12)
 
 
 def mode_product(V: np.ndarray, M: np.ndarray, mu: int, S: int) -> np.ndarray:

@@ -27,8 +27,8 @@ MM_ETD2RK, MM_ERK2P1 = 0, 1
 
 MM_SLICED = 4
 PRECISIONS = {"fp64": MM_FP64, "fp32": MM_FP32, "bf16x3": MM_BF16X3, "bf16x6": MM_BF16X6}
-# exact slicing with S base-128 digits: "sliced3" .. "sliced8"
-PRECISIONS.update({f"sliced{s}": MM_SLICED for s in range(3, 9)})
+# exact slicing with S balanced base-256 digits: "sliced3" .. "sliced7"
+PRECISIONS.update({f"sliced{s}": MM_SLICED for s in range(3, 8)})
 
 
 def prec_code(prec: str):

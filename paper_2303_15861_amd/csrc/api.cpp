@@ -629,6 +629,17 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     set_err(ctx, "slices must be 0 or %d..%d", kMinSlices, kMaxSlices);
     return MM_EINVAL;
   }
+  if (prec == MM_SLICED) {
+    // exact int32 level sums need S * 2^14 * K < 2^31 for every contraction length K
+    int64_t kmax = 0;
+    for (int mu = 0; mu < prob->d; ++mu) kmax = std::max<int64_t>(kmax, prob->n[mu]);
+    if (family == MM_ERK) kmax = std::max<int64_t>(kmax, (int64_t)(quad_nodes + 1) * prob->n[prob->d - 1]);
+    const int S = slices ? slices : kDefaultSlices;
+    if (kmax * S * 16384 >= ((int64_t)1 << 31)) {
+      set_err(ctx, "contraction length %lld too long for exact %d-digit slicing", (long long)kmax, S);
+      return MM_EINVAL;
+    }
+  }
   if (!std::isfinite(prob->lambda) || prob->lambda < 0.0) {
     set_err(ctx, "lambda must be finite and >= 0");
     return MM_EINVAL;

@@ -47,7 +47,7 @@ struct GemmArgs {
 constexpr int kFacPad = 32;   // k padding of pre-converted factors
 inline int fac_ld(int k) { return (k + kFacPad - 1) / kFacPad * kFacPad; }
 // digit planes of MM_SLICED: rows zero-padded to a multiple of 64 in k
-constexpr int kMinSlices = 3, kMaxSlices = 8, kDefaultSlices = 7;
+constexpr int kMinSlices = 3, kMaxSlices = 7, kDefaultSlices = 6;
 inline int slice_ld(int k) { return (k + 63) / 64 * 64; }
 
 // Stencil launch parameters (remainder g and fused stage updates).

@@ -1,24 +1,25 @@
 // Exact-slice mode products on the int8 matrix cores (v_mfma_i32_16x16x64_i8).
 //
-// Every operand row r (along the contracted index k) gets a power-of-two scale 2^e_r
-// with max_k |x_rk| < 2^e_r, and each value is written as
-//     x = sign(x) * 2^e_r * sum_{s<S} d_s 2^{-7(s+1)},   d_s in [0, 127],
-// the S base-128 digits of round(|x| 2^{7S - e_r}) (signed digits fit int8 exactly).
-// Then
-//     sum_k A_mk B'_nk ~= 2^{e_m + e_n} sum_{l<S} 2^{-7(l+2)} P_l,
-//     P_l = sum_{s+t=l} sum_k dA_s dB_t,
-// where every product and every partial sum of P_l is an integer far below 2^31, so the
-// int32 accumulation of each level is exact; the levels are combined in FP64 in the
-// epilogue. Products with s + t >= S are dropped. The error of the result is set by the
-// dropped products and the rounding of the last digit (both ~2^{-7S} relative to the
-// row scales), independent of K's summation order.
+// Every operand row r (along the contracted index k) gets a power-of-two scale: e_r with
+// max_k |x_rk| < 2^e_r. A value becomes Y = round(x 2^(8S-2-e_r)) (|Y| <= 2^(8S-2))
+// written with S balanced base-256 digits b_i in [-128, 127] (int8 exactly):
+//     x ~ 2^(e_r + 2 - 8S) sum_i b_i 256^i.
+// The digits are the bytes of Y + 0x80..80 each minus 128 (an XOR with 0x80 per byte),
+// so one 64-bit add and two XORs give all of them, packed. Then
+//     sum_k A_mk B'_nk ~= 2^(e_m + e_n - 12) sum_(l<S) 2^(-8l) P_l,
+//     P_l = sum_(s+t=l) sum_k dA_s dB_t     (digit planes s, t most significant first),
+// where every partial sum of P_l is an integer below S 2^14 K < 2^31 (checked at launch),
+// so the int32 accumulation is exact; the levels are combined in FP64 in the epilogue.
+// Products with s + t >= S are dropped; with the rounding of Y they set the error,
+// ~2^(-8S) relative to the row scales whatever the summation order.
 //
 // The factor (n x n, or stacked quadrature factors) is split once at setup into S digit
 // planes with per-row exponents (rows zero-padded to a multiple of 64 in k). The grid
 // operand stays FP64 in memory: each workgroup first finds the exponents of its 64 grid
 // rows (mode 1) or columns (modes 2/3) over the whole k range, then splits values into
-// digits while staging them into LDS. Workgroup tile 64 x 64, four waves of 32 x 32,
-// one accumulator per digit level.
+// digits while staging them into LDS, four consecutive k at a time (a 4 x 4 byte
+// transpose turns four packed values into one dword per digit plane). Workgroup tile
+// 64 x 64, four waves of 32 x 32, one accumulator per digit level.
 #include "mm_internal.h"
 
 namespace mm {
@@ -32,22 +33,49 @@ constexpr int KC8 = 64;     // k per chunk (one int8 MFMA)
 constexpr int PI8 = 80;     // LDS row pitch in bytes (16 lanes of 16-byte reads hit all 64 banks once)
 constexpr int TH = 256;
 
-// Digits of x relative to the row exponent e (MSB first), signed.
+// Balanced base-256 digits of x relative to exponent e, packed: byte i of (lo, hi) is
+// b_i (least significant first) as a two's-complement int8.
 template <int S>
-__device__ __forceinline__ void slice_value(double x, int e, int (&d)[S]) {
-  const double lim = __builtin_ldexp(1.0, 7 * S) - 1.0;
-  const double y = __builtin_fmin(__builtin_rint(__builtin_ldexp(__builtin_fabs(x), 7 * S - e)), lim);
-  const double hf = __builtin_floor(y * 0x1p-28);
-  const unsigned hi = (unsigned)hf;
-  const unsigned lo = (unsigned)__builtin_fma(-hf, 0x1p28, y);
-  const bool neg = x < 0.0;
+__device__ __forceinline__ void slice_bytes(double x, int e, unsigned& lo, unsigned& hi) {
+  const double y = __builtin_rint(__builtin_ldexp(x, 8 * S - 2 - e));   // |y| <= 2^(8S-2)
+  const double hf = __builtin_floor(y * 0x1p-32);
+  const unsigned l = (unsigned)__builtin_fma(-hf, 0x1p32, y);           // exact, in [0, 2^32)
+  const int h = (int)hf;
+  constexpr unsigned long long C = 0x8080808080808080ull >> (64 - 8 * S);
+  const unsigned long long Y = ((((unsigned long long)(unsigned)h) << 32) | l) + C;
+  lo = (unsigned)Y ^ 0x80808080u;
+  hi = (unsigned)(Y >> 32) ^ 0x80808080u;
+}
+
+// o[j] = byte j of w0, w1, w2, w3 (in that order, lowest byte first)
+__device__ __forceinline__ void transpose4(unsigned w0, unsigned w1, unsigned w2, unsigned w3, unsigned (&o)[4]) {
+  const unsigned t0 = __builtin_amdgcn_perm(w1, w0, 0x05010400u);   // w0.b0 w1.b0 w0.b1 w1.b1
+  const unsigned t1 = __builtin_amdgcn_perm(w1, w0, 0x07030602u);   // w0.b2 w1.b2 w0.b3 w1.b3
+  const unsigned t2 = __builtin_amdgcn_perm(w3, w2, 0x05010400u);
+  const unsigned t3 = __builtin_amdgcn_perm(w3, w2, 0x07030602u);
+  o[0] = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
+  o[1] = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
+  o[2] = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
+  o[3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
+}
+
+// Digit planes (most significant first) of four consecutive values: pl[s] holds digit
+// S-1-s of v0..v3 in its bytes 0..3.
+template <int S>
+__device__ __forceinline__ void slice4(double v0, double v1, double v2, double v3, int e, unsigned (&pl)[S]) {
+  unsigned lo[4], hi[4];
+  slice_bytes<S>(v0, e, lo[0], hi[0]);
+  slice_bytes<S>(v1, e, lo[1], hi[1]);
+  slice_bytes<S>(v2, e, lo[2], hi[2]);
+  slice_bytes<S>(v3, e, lo[3], hi[3]);
+  unsigned o[4];
+  transpose4(lo[0], lo[1], lo[2], lo[3], o);
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int p = S - 1 - s;                 // digit position, 0 = least significant
-    const unsigned w = (p < 4) ? lo : hi;
-    const int sh = 7 * ((p < 4) ? p : p - 4);
-    const int v = (int)((w >> sh) & 127u);
-    d[s] = neg ? -v : v;
+  for (int i = 0; i < 4 && i < S; ++i) pl[S - 1 - i] = o[i];
+  if (S > 4) {
+    transpose4(hi[0], hi[1], hi[2], hi[3], o);
+#pragma unroll
+    for (int i = 4; i < S; ++i) pl[S - 1 - i] = o[i - 4];
   }
 }
 
@@ -55,11 +83,6 @@ __device__ __forceinline__ int row_exponent(double mx) {
   int e = 0;
   __builtin_frexp(mx, &e);                   // mx < 2^e (e = 0 for mx = 0)
   return e;
-}
-
-__device__ __forceinline__ unsigned pack4(int a, int b, int c, int d) {
-  return (unsigned)(a & 255) | ((unsigned)(b & 255) << 8) | ((unsigned)(c & 255) << 16) |
-         ((unsigned)(d & 255) << 24);
 }
 
 }  // namespace
@@ -197,28 +220,19 @@ __global__ __launch_bounds__(TH, 2) void gemm_i8(GemmArgs p) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int rloc = r16 + 16 * j;
-        const int e = Ve[rloc];
-        int d0[S], d1[S], d2[S], d3[S];
-        slice_value<S>(rv[4 * j + 0], e, d0);
-        slice_value<S>(rv[4 * j + 1], e, d1);
-        slice_value<S>(rv[4 * j + 2], e, d2);
-        slice_value<S>(rv[4 * j + 3], e, d3);
+        unsigned pl[S];
+        slice4<S>(rv[4 * j + 0], rv[4 * j + 1], rv[4 * j + 2], rv[4 * j + 3], Ve[rloc], pl);
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-          *reinterpret_cast<unsigned*>(&Vs[s][rloc * PI8 + 4 * kq]) = pack4(d0[s], d1[s], d2[s], d3[s]);
+        for (int s = 0; s < S; ++s) *reinterpret_cast<unsigned*>(&Vs[s][rloc * PI8 + 4 * kq]) = pl[s];
       }
     } else {
       const int e = Ve[cn];
 #pragma unroll
       for (int qd = 0; qd < 4; ++qd) {
-        int d0[S], d1[S], d2[S], d3[S];
-        slice_value<S>(rv[4 * qd + 0], e, d0);
-        slice_value<S>(rv[4 * qd + 1], e, d1);
-        slice_value<S>(rv[4 * qd + 2], e, d2);
-        slice_value<S>(rv[4 * qd + 3], e, d3);
+        unsigned pl[S];
+        slice4<S>(rv[4 * qd + 0], rv[4 * qd + 1], rv[4 * qd + 2], rv[4 * qd + 3], e, pl);
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-          *reinterpret_cast<unsigned*>(&Vs[s][cn * PI8 + 16 * kg + 4 * qd]) = pack4(d0[s], d1[s], d2[s], d3[s]);
+        for (int s = 0; s < S; ++s) *reinterpret_cast<unsigned*>(&Vs[s][cn * PI8 + 16 * kg + 4 * qd]) = pl[s];
       }
     }
     __syncthreads();
@@ -259,8 +273,8 @@ __global__ __launch_bounds__(TH, 2) void gemm_i8(GemmArgs p) {
         if (m < M && n < N) {
           double v = (double)acc[S - 1][i][j][t];
 #pragma unroll
-          for (int l = S - 2; l >= 0; --l) v = __builtin_fma(v, 0x1p-7, (double)acc[l][i][j][t]);
-          const int e = (BT ? Fe[ml] + Ve[nl] : Ve[ml] + Fe[nl]) - 14;
+          for (int l = S - 2; l >= 0; --l) v = __builtin_fma(v, 0x1p-8, (double)acc[l][i][j][t]);
+          const int e = (BT ? Fe[ml] + Ve[nl] : Ve[ml] + Fe[nl]) - 12;
           double o = alpha * __builtin_ldexp(v, e);
           if (Cadd) o += beta * Cadd[m * p.ldc + n];
           C[m * p.ldc + n] = o;
@@ -288,17 +302,17 @@ __global__ __launch_bounds__(TH) void slice_rows(signed char* dst, int* exps, co
   if (threadIdx.x == 0) exps[r] = e;
   const int64_t plane = (int64_t)rows * ldd;
   for (int c = threadIdx.x; c < ldd; c += TH) {
+    // Y = round(x 2^(8S-2-e)) as a 64-bit integer; its balanced base-256 digits follow
+    // from the bytes of Y + 0x80..80
     const double x = (c < k) ? row[c] : 0.0;
-    const double y = __builtin_fmin(__builtin_rint(__builtin_ldexp(__builtin_fabs(x), 7 * S - e)),
-                                    __builtin_ldexp(1.0, 7 * S) - 1.0);
-    // digits from the top: y = sum_s d_s 128^{S-1-s}
-    double rem = y;
+    const double y = __builtin_rint(__builtin_ldexp(x, 8 * S - 2 - e));
+    long long Y = (long long)__builtin_floor(y * 0x1p-32) * 4294967296ll +
+                  (long long)(unsigned)__builtin_fma(-__builtin_floor(y * 0x1p-32), 0x1p32, y);
+    const unsigned long long U = (unsigned long long)Y + (0x8080808080808080ull >> (64 - 8 * S));
     for (int s = 0; s < S; ++s) {
-      const double unit = __builtin_ldexp(1.0, 7 * (S - 1 - s));
-      const double dv = __builtin_floor(rem / unit);
-      rem = __builtin_fma(-dv, unit, rem);
-      const int v = (int)dv;
-      dst[s * plane + (int64_t)r * ldd + c] = (signed char)(x < 0.0 ? -v : v);
+      const int i = S - 1 - s;                                  // digit i, plane s
+      const int byte = (int)((U >> (8 * i)) & 255ull);
+      dst[s * plane + (int64_t)r * ldd + c] = (signed char)(byte - 128);
     }
   }
 }
@@ -311,6 +325,8 @@ hipError_t launch_slice_rows(signed char* dst, int* exps, const double* src, int
 }
 
 hipError_t launch_gemm_sliced(GemmArgs& g, hipStream_t s) {
+  // every level sum must stay an exact int32: S products of at most 2^14 per k
+  if ((int64_t)g.K * g.slices * 16384 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
   g.tiles_m = (g.M + T8 - 1) / T8;
   g.tiles_n = (g.N + T8 - 1) / T8;
   const int64_t total = (int64_t)g.tiles_m * g.tiles_n * g.inner * g.groups;
@@ -329,7 +345,6 @@ hipError_t launch_gemm_sliced(GemmArgs& g, hipStream_t s) {
     MM_SLICED_CASE(5)
     MM_SLICED_CASE(6)
     MM_SLICED_CASE(7)
-    MM_SLICED_CASE(8)
     default: return hipErrorInvalidValue;
   }
 #undef MM_SLICED_CASE

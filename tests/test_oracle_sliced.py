@@ -1,6 +1,6 @@
 """Pins of the exact-slice oracle (oracle/sliced.py) against facts that do not depend
 on it: exact integer arithmetic, a pure-Python evaluation of the definition, exact
-products for 7-bit integer data, and the 2^(-7S) error bound with its decay in S."""
+products for small-integer data, and the 2^(-8S) error bound with its decay in S."""
 from fractions import Fraction
 
 import numpy as np
@@ -11,16 +11,16 @@ from oracle import adr, expo, sliced
 
 
 def py_digits(x: float, e: int, S: int):
-    """Digits of x by exact rational arithmetic (round half to even)."""
-    y = Fraction(abs(x)) * Fraction(2) ** (7 * S - e)
-    Y = round(y)                       # Python rounds halves to even
-    Y = min(Y, 2 ** (7 * S) - 1)
+    """Balanced base-256 digits of x by exact integer arithmetic (MSB first)."""
+    Y = round(Fraction(x) * Fraction(2) ** (8 * S - 2 - e))     # halves to even
+    Y0 = Y
     ds = []
-    for s in range(S):
-        p = S - 1 - s
-        ds.append((Y // 128 ** p) % 128)
-    sgn = -1 if x < 0 else 1
-    return [sgn * d for d in ds], Y
+    for _ in range(S):
+        b = (Y + 128) % 256 - 128
+        ds.append(b)
+        Y = (Y - b) // 256
+    assert Y == 0
+    return ds[::-1], Y0
 
 
 def py_exponent(row):
@@ -35,23 +35,26 @@ def py_exponent(row):
     return e
 
 
-@pytest.mark.parametrize("S", [3, 5, 7, 8])
+@pytest.mark.parametrize("S", [3, 4, 5, 6, 7])
 def test_digits_round_trip_exact(S):
     rng = np.random.default_rng(S)
     X = rng.standard_normal((5, 9)) * np.exp(rng.uniform(-20, 20, (5, 1)))
     X[1, 3] = 0.0
     X[2] = 0.0
+    X[3, 4] = -np.max(np.abs(X[3]))                 # the row maximum with a negative sign
     e = sliced.exponents(X)
     D = sliced.digits(X, e, S)
+    assert np.all(D >= -128) and np.all(D <= 127)
     for i in range(X.shape[0]):
         assert e[i] == py_exponent(X[i])
         for k in range(X.shape[1]):
             ds, Y = py_digits(X[i, k], int(e[i]), S)
             assert [int(D[s, i, k]) for s in range(S)] == ds
             # the digits represent x to half a unit of the last digit
-            rep = sum(Fraction(d) * Fraction(128) ** (S - 1 - s) for s, d in enumerate(ds))
-            err = abs(rep * Fraction(2) ** (int(e[i]) - 7 * S) - Fraction(X[i, k]))
-            assert err <= Fraction(2) ** (int(e[i]) - 7 * S - 1) + Fraction(2) ** (int(e[i]) - 7 * S) * (Y == 2 ** (7 * S) - 1)
+            rep = sum(Fraction(d) * Fraction(256) ** (S - 1 - s) for s, d in enumerate(ds))
+            assert rep == Y
+            err = abs(rep * Fraction(2) ** (int(e[i]) + 2 - 8 * S) - Fraction(X[i, k]))
+            assert err <= Fraction(2) ** (int(e[i]) + 1 - 8 * S)
 
 
 def py_matmul_rows(A, B, S):
@@ -70,12 +73,12 @@ def py_matmul_rows(A, B, S):
             # top level down, one rounding per level as in FP64
             v = float(P[S - 1])
             for lvl in range(S - 2, -1, -1):
-                v = v * 2.0 ** -7 + float(P[lvl])
-            out[i, j] = np.ldexp(v, a + b - 14)
+                v = v * 2.0 ** -8 + float(P[lvl])
+            out[i, j] = np.ldexp(v, a + b - 12)
     return out
 
 
-@pytest.mark.parametrize("S", [3, 4, 6, 8])
+@pytest.mark.parametrize("S", [3, 4, 6, 7])
 def test_matmul_matches_pure_python_definition(S):
     rng = np.random.default_rng(10 + S)
     A = rng.standard_normal((4, 11)) * np.array([[1.0], [1e-3], [3e5], [0.5]])
@@ -84,21 +87,23 @@ def test_matmul_matches_pure_python_definition(S):
     assert np.array_equal(sliced.matmul_rows(A, B, S), py_matmul_rows(A, B, S))
 
 
-def test_seven_bit_integers_are_exact():
-    """Rows whose entries are integers |x| <= 127 with max 127 have one nonzero digit:
-    only level 0 survives and the product is the exact integer product."""
+def test_small_integers_are_exact():
+    """Rows of integers |x| <= 127 (max 127, e = 7) are exact in the top two digits
+    (Y = x 2^(8S-9)), so every product falls in levels s + t <= 2 < S and the result is
+    the exact integer product."""
     rng = np.random.default_rng(3)
     A = rng.integers(-127, 128, (6, 40)).astype(float)
     B = rng.integers(-127, 128, (7, 40)).astype(float)
     A[:, 0] = 127.0
     B[:, 0] = -127.0
-    for S in (3, 5, 8):
+    for S in (3, 5, 7):
         assert np.array_equal(sliced.matmul_rows(A, B, S), A @ B.T)
 
 
 def test_error_bound_and_decay():
-    """|C - A B^T| <= 2^(-7S) * 4 S * K * max|A_i| max|B_j|, and each extra digit gains
-    about 2^7."""
+    """|C - A B^T| <= 2^(-8S) * 16 S * K * max|A_i| max|B_j| (each value is within
+    2^(e+1-8S) <= 4 2^(-8S) max of its digits, and the first dropped level holds S - 1
+    products of at most 2^14 * 2^(a+b+4-8S-16)), and each extra digit gains about 2^8."""
     rng = np.random.default_rng(4)
     K = 200
     A = rng.standard_normal((20, K))
@@ -106,12 +111,12 @@ def test_error_bound_and_decay():
     ref = A @ B.T
     scale = np.max(np.abs(A), axis=1)[:, None] * np.max(np.abs(B), axis=1)[None, :]
     errs = {}
-    for S in range(3, 9):
+    for S in range(3, 8):
         err = np.abs(sliced.matmul_rows(A, B, S) - ref)
-        assert np.all(err <= 2.0 ** (-7 * S) * 4 * S * K * scale + 1e-13 * np.abs(ref).max())
+        assert np.all(err <= 2.0 ** (-8 * S) * 16 * S * K * scale + 1e-13 * np.abs(ref).max())
         errs[S] = float(np.max(err / scale))
     for S in range(3, 6):
-        assert 2 ** 4 < errs[S] / errs[S + 1] < 2 ** 10, errs
+        assert 2 ** 5 < errs[S] / errs[S + 1] < 2 ** 11, errs
 
 
 def test_sliced_action_within_bound():
@@ -126,7 +131,7 @@ def test_sliced_action_within_bound():
     emax = max(float(np.max(np.abs(M))) for M in mats)
     for S in (3, 5, 7):
         got = sliced.tucker(V, mats, S)
-        bound = 3 * 2.0 ** (-7 * S) * 4 * S * K * emax * np.max(np.abs(V))
+        bound = 3 * 2.0 ** (-8 * S) * 16 * S * K * emax * np.max(np.abs(V))
         assert np.max(np.abs(got - ref)) <= bound + 1e-14 * np.max(np.abs(V))
 
 
@@ -134,7 +139,7 @@ def test_sliced_solve_converges_to_fp64_solve():
     p = synth.smooth_problem((12, 10, 9), 6, tau=1e-3, steps=5, scheme="l2b")
     from oracle import schemes as Sch
     ref = Sch.solve(p)
-    e5 = np.max(np.abs(sliced.solve(p, 5) - ref))
-    e8 = np.max(np.abs(sliced.solve(p, 8) - ref))
-    assert e8 < 1e-12 * np.max(np.abs(ref))
-    assert e8 < e5
+    e4 = np.max(np.abs(sliced.solve(p, 4) - ref))
+    e7 = np.max(np.abs(sliced.solve(p, 7) - ref))
+    assert e7 < 1e-12 * np.max(np.abs(ref))
+    assert e7 < e4
