@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--workload", default=WORKLOAD, help="one of synth.WORKLOADS")
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--modes", default="fp64,fp32,bf16x6,bf16x3,sliced6,sliced7")
+    ap.add_argument("--modes", default="fp64,fp32,bf16x6,bf16x3,sliced4,sliced5,sliced6,sliced7")
     ap.add_argument("--headline", default="fp64")
     ap.add_argument("--latency-reps", type=int, default=20)
     ap.add_argument("--graph-steps", type=int, default=0,
