@@ -82,7 +82,10 @@ typedef enum { MM_FP64 = 0, MM_FP32 = 1, MM_BF16X3 = 2, MM_BF16X6 = 3, MM_SLICED
  *                                      U = u + tau phi1(tau A) F(u),
  *                                      u+ = U + tau/2 phi1(tau A)(g(U) - g(u))
  * phi1(tau A) is replaced by the q-node Gauss-Legendre rule
- *   phi1(tau A) v ~ sum_j w_j exp(theta_j tau A) v,  theta_j, w_j on [0, 1].         */
+ *   phi1(tau A) v ~ sum_j w_j exp(theta_j tau A) v,  theta_j, w_j on [0, 1],
+ * or (q = 0) evaluated exactly in the joint eigenbasis of the Kronecker sum: with
+ * A_mu = L_mu diag(ev_mu) R_mu (closed form for the tridiagonal Toeplitz A_mu),
+ *   f(tau A) v = (v x_mu R_mu over mu) scaled by f(tau (ev_1 + ev_2 + ev_3)) x_mu L_mu.  */
 enum { MM_LAWSON = 0, MM_ERK = 1 };
 enum { MM_LAWSON_EULER = 0, MM_LAWSON2B = 1 };
 enum { MM_ETD2RK = 0, MM_ERK2P1 = 1 };
@@ -115,11 +118,14 @@ const char* mm_version(void);
  * scaling-and-squaring for every c the scheme needs (c = 1 and the quadrature nodes
  * theta_j for MM_ERK), plus the FP32, BF16-slice or digit-plane forms the precision
  * needs. Returns after the setup has finished. quad_nodes (q) is 1..7 for MM_ERK and
- * ignored for MM_LAWSON. slices: digit count of MM_SLICED (0 = 6, else 3..7), ignored
- * by the other precisions. `a` must be complete when the call is made (the
- * copy runs on the context's own stream, which does not wait for other streams).
+ * ignored for MM_LAWSON; q = 0 selects exact phi1 through the eigenbasis (FP64 only;
+ * needs |beta_bar_mu| h_mu < 2 lambda a_max so that the eigenvalues are real), and
+ * the op then also stores R_mu and L_mu. slices: digit count of MM_SLICED (0 = 6,
+ * else 3..7), ignored by the other precisions. `a` must be complete when the call is
+ * made (the copy runs on the context's own stream, which does not wait for others).
  * Errors: MM_EINVAL (d, n < 1, tau <= 0 or not finite, unknown family/scheme/prec,
- * slices out of range, a == NULL), MM_ENOMEM, MM_EDEVICE. */
+ * slices out of range, exact phi1 with another precision or complex eigenvalues,
+ * a == NULL), MM_ENOMEM, MM_EDEVICE. */
 mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int family, int scheme,
                        int quad_nodes, int prec, int slices, mm_op** out);
 /* Release the op. Work enqueued with it must have completed (synchronise first). */
@@ -132,8 +138,9 @@ mm_status mm_synchronize(mm_ctx* ctx);
  * axis mu (diagnostics). */
 mm_status mumode_info(const mm_op* op, double* a_max, int* squarings);
 
-/* Copy the FP64 factor exp(c tau A_mu) for quadrature index j (j = 0: c = 1; j >= 1:
- * c = theta_j) of axis mu into host memory (n_mu*n_mu values, row-major E[row][col]). */
+/* Copy the FP64 factor of index j of axis mu into host memory (n_mu*n_mu values,
+ * row-major E[row][col]): exp(c tau A_mu) with c = 1 (j = 0) or c = theta_j (j = 1..q);
+ * with exact phi1 (q = 0), j = 1 is R_mu and j = 2 is L_mu. */
 mm_status mumode_get_factor(const mm_op* op, int mu, int j, double* host_out);
 
 /* Remainder (eq. (eq:nonlin)) on the grid, flux-form centred differences, face
@@ -145,12 +152,15 @@ mm_status mumode_get_factor(const mm_op* op, int mu, int j, double* host_out);
 mm_status remainder_eval(mm_ctx* ctx, const mm_op* op, const double* u, double* g, double* F,
                          void* stream);
 
-/* out = exp(c tau A) in with c = 1 (j = 0) or c = theta_j (j >= 1, MM_ERK only), as
- * three (two) mu-mode passes in the op's precision. in/out: device, may alias. */
+/* out = in x_mu M_mu over all axes, three (two) mu-mode passes in the op's precision,
+ * with M the factors of index j (see mumode_get_factor): exp(c tau A) in for j = 0 and
+ * the quadrature nodes, the eigenbasis transforms R and L with exact phi1. in/out:
+ * device, may alias. */
 mm_status mumode_expv(mm_ctx* ctx, const mm_op* op, int j, const double* in, double* out,
                       void* stream);
 
-/* out = sum_j w_j exp(theta_j tau A) in, the q-node quadrature phi1 action (MM_ERK). */
+/* out = phi1(tau A) in (MM_ERK): the q-node quadrature sum_j w_j exp(theta_j tau A) in,
+ * or exact through the eigenbasis when q = 0. */
 mm_status mumode_phi1v(mm_ctx* ctx, const mm_op* op, const double* in, double* out, void* stream);
 
 /* Advance u (device, in place) by nsteps Lawson steps (family MM_LAWSON). */

@@ -115,7 +115,8 @@ def rel_inf_error(u: np.ndarray, ref: np.ndarray) -> float:
 class GridBackend:
     """Finite-difference backend of the schemes on one ADR problem (synth.Problem).
 
-    phi="quad" uses the q-point Gauss-Legendre phi1; phi="exact" the joint eigenbasis.
+    phi="quad" uses the q-point Gauss-Legendre phi1; phi="exact" the joint eigenbasis,
+    which is also what a problem with q = 0 (no quadrature nodes) asks for.
     """
 
     def __init__(self, prob, phi: str = "quad"):
@@ -125,7 +126,7 @@ class GridBackend:
         self.a_max = extracted_amax(prob.a)
         self.op = KronOperator(prob.n, self.a_max, prob.lam, prob.beta_bar, prob.tau)
         self._remainder, self._full = remainder, full_rhs
-        self.phi = phi
+        self.phi = "exact" if prob.q == 0 else phi
 
     def expv(self, c, v):
         return self.op.expv(c, v)

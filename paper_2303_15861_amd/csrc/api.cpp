@@ -391,7 +391,7 @@ const double* factor(const mm_op* op, int mu, int j) {
 // in_f32: the input is float (mixed modes only); out is always double. In the mixed
 // modes the intermediates t0, t1 hold floats.
 hipError_t exp_action(const mm_op* op, int j, const void* in, bool in_f32, double* out, int nvec, double* t0,
-                      double* t1, hipStream_t s) {
+                      double* t1, hipStream_t s, const double* add = nullptr) {
   const bool mixed = lowp(op);
   PassIO first{in_f32, mixed}, mid{mixed, mixed}, last_io{mixed, false};
   const int fj[1] = {j};
@@ -407,12 +407,12 @@ hipError_t exp_action(const mm_op* op, int j, const void* in, bool in_f32, doubl
     void* o2[1] = {t1};
     e = pass_mode2(op, 1, fj, i2, o2, op->n[2] * nvec, mid, s);
     if (e != hipSuccess) return e;
-    return pass_last(op, Fl, Fe, 1, t1, out, nullptr, 1.0, 0.0, nvec, last_io, s);
+    return pass_last(op, Fl, Fe, 1, t1, out, add, 1.0, add ? 1.0 : 0.0, nvec, last_io, s);
   }
   hipError_t e = pass_mode1(op, 1, i1, fj, o1, (int)(op->dof / op->n[0]) * nvec, first, s);
   if (e != hipSuccess) return e;
   PassIO l2{mixed, false};
-  return pass_last(op, Fl, Fe, 1, t0, out, nullptr, 1.0, 0.0, nvec, l2, s);
+  return pass_last(op, Fl, Fe, 1, t0, out, add, 1.0, add ? 1.0 : 0.0, nvec, l2, s);
 }
 
 // out = stacked-last-factor contraction over G groups: group g applies modes 1..d-1 with
@@ -460,6 +460,15 @@ const double* stage_weights(const mm_op* op, int which, double* w) {
   return w;
 }
 
+// exact phi1: factor slots of the eigenvector matrices (A_mu = L diag(ev) R)
+constexpr int kFacR = 1, kFacL = 2;
+
+hipError_t eig_scale(const mm_op* op, double* out, const double* a, double ca, int fa, const double* b, double cb,
+                     int fb, hipStream_t s) {
+  return launch_eig_scale(out, a, ca, fa, b, cb, fb, op->ev[0], op->ev[1], op->d == 3 ? op->ev[2] : nullptr,
+                          op->n[0], op->n[1], op->d == 3 ? op->n[2] : 1, op->tau, s);
+}
+
 StencilArgs stencil_args(const mm_op* op, const double* u, bool full) {
   StencilArgs a{};
   a.u = u;
@@ -482,6 +491,40 @@ StencilArgs stencil_args(const mm_op* op, const double* u, bool full) {
   a.c1 = 1.0;
   a.flag = op->flag;
   return a;
+}
+
+// Closed-form eigen-decomposition of the tridiagonal Toeplitz matrix with sub-diagonal
+// s, diagonal delta and super-diagonal t (s t > 0, or s = t = 0): with rho = sqrt(s/t),
+// D = diag(rho^j), the similar matrix D^-1 A D is symmetric tridiagonal with off-diagonal
+// sigma = sign(t) sqrt(s t), diagonalised by the orthogonal symmetric sine matrix
+// S[j][k] = sqrt(2/(n+1)) sin(j k pi/(n+1)), eigenvalues delta + 2 sigma cos(k pi/(n+1)).
+// Hence A = L diag(ev) R with L = D S and R = S D^-1 (R L = I), both row-major n x n.
+bool eigen_closed_form(int n, double s, double delta, double t, std::vector<double>& ev, std::vector<double>& R,
+                       std::vector<double>& L) {
+  double rho = 1.0, sigma = 0.0;
+  if (s * t > 0.0) {
+    rho = std::sqrt(s / t);
+    sigma = (t > 0.0 ? 1.0 : -1.0) * std::sqrt(s * t);
+  } else if (!(s == 0.0 && t == 0.0)) {
+    return false;
+  }
+  const double pi = 3.14159265358979323846;
+  const double c = std::sqrt(2.0 / (n + 1));
+  const int64_t per = 2 * (int64_t)(n + 1);             // sin(m pi/(n+1)) has period 2(n+1) in m
+  ev.resize(n);
+  R.resize((size_t)n * n);
+  L.resize((size_t)n * n);
+  std::vector<double> dpow(n);
+  for (int j = 0; j < n; ++j) dpow[j] = std::pow(rho, j + 1);
+  for (int k = 0; k < n; ++k) ev[k] = delta + 2.0 * sigma * std::cos((k + 1) * pi / (n + 1));
+  for (int j = 0; j < n; ++j)
+    for (int k = 0; k < n; ++k) {
+      const int64_t m = ((int64_t)(j + 1) * (k + 1)) % per;   // exact argument reduction
+      const double sjk = c * std::sin(m * pi / (n + 1));
+      L[(size_t)j * n + k] = dpow[j] * sjk;                  // (D S)[j][k]
+      R[(size_t)k * n + j] = sjk / dpow[j];                  // (S D^-1)[k][j]
+    }
+  return true;
 }
 
 mm_status check_op(mm_ctx* ctx, const mm_op* op) {
@@ -574,6 +617,7 @@ void mumode_destroy(mm_op* op) {
   dev_free(op, op->f3_stage1_exp);
   dev_free(op, op->f3_stage2_exp);
   dev_free(op, op->f3_phi_exp);
+  for (int mu = 0; mu < 3; ++mu) dev_free(op, op->ev[mu]);
   for (int i = 0; i < 6; ++i) dev_free(op, op->buf[i]);
   dev_free(op, op->flag);
   if (op->gexec) hipGraphExecDestroy(op->gexec);
@@ -617,8 +661,12 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     set_err(ctx, "unknown ERK scheme %d", scheme);
     return MM_EINVAL;
   }
-  if (family == MM_ERK && (quad_nodes < 1 || quad_nodes > kMaxGroups - 1)) {
-    set_err(ctx, "quad_nodes must be 1..%d", kMaxGroups - 1);
+  if (family == MM_ERK && (quad_nodes < 0 || quad_nodes > kMaxGroups - 1)) {
+    set_err(ctx, "quad_nodes must be 0 (exact phi1) or 1..%d", kMaxGroups - 1);
+    return MM_EINVAL;
+  }
+  if (family == MM_ERK && quad_nodes == 0 && prec != MM_FP64) {
+    set_err(ctx, "exact phi1 (quad_nodes = 0) is FP64 only");
     return MM_EINVAL;
   }
   if (prec < MM_FP64 || prec > MM_SLICED) {
@@ -661,6 +709,7 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
   op->family = family;
   op->scheme = scheme;
   op->q = (family == MM_ERK) ? quad_nodes : 0;
+  op->exact = (family == MM_ERK && quad_nodes == 0);
   op->prec = prec;
   op->slices = (prec == MM_SLICED) ? (slices ? slices : kDefaultSlices) : 0;
   op->dof = (int64_t)op->n[0] * op->n[1] * op->n[2];
@@ -697,7 +746,10 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
   op->a_max = amax;
 
   // coefficients c of the factors exp(c tau A_mu): c_0 = 1, c_j = theta_j
+  // Pade factors exp(c tau A_mu) for c = 1 and the quadrature nodes; the exact-phi1 mode
+  // stores two more per axis, the eigenvector matrices R and L (A_mu = L diag(ev) R)
   const int nf = 1 + op->q;
+  op->nfac = op->exact ? 3 : nf;
   double cs[kMaxGroups];
   cs[0] = 1.0;
   if (op->q > 0) {
@@ -726,7 +778,7 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
       continue;
     }
     const int n = op->n[mu];
-    if ((rc = dev_alloc(op, &op->fac[mu], (int64_t)nf * n * n)) != MM_OK) {
+    if ((rc = dev_alloc(op, &op->fac[mu], (int64_t)op->nfac * n * n)) != MM_OK) {
       hipFreeAsync(ws, st);
       return fail(rc);
     }
@@ -750,6 +802,29 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
   if (hipStreamSynchronize(st) != hipSuccess) {
     set_err(ctx, "factor setup failed on the device");
     return fail(MM_EDEVICE);
+  }
+  if (op->exact) {
+    // closed-form eigen-decomposition of every 1D operator (uploaded next to E(1))
+    for (int mu = 0; mu < op->d; ++mu) {
+      const int n = op->n[mu];
+      const double h = 1.0 / (n + 1);
+      const double diff = op->lam * op->a_max / (h * h);
+      const double adv = op->beta_bar[mu] / (2.0 * h);
+      std::vector<double> ev, R, L;
+      if (!eigen_closed_form(n, diff - adv, -2.0 * diff, diff + adv, ev, R, L)) {
+        set_err(ctx, "exact phi1 needs |beta_bar| h < 2 lambda a_max on every axis (real eigenvalues)");
+        return fail(MM_EINVAL);
+      }
+      if ((rc = dev_alloc(op, &op->ev[mu], n)) != MM_OK) return fail(rc);
+      const int64_t nn = (int64_t)n * n;
+      if (hipMemcpy(op->ev[mu], ev.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+          (op->fac_owned[mu] &&
+           (hipMemcpy(op->fac[mu] + nn, R.data(), nn * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(op->fac[mu] + 2 * nn, L.data(), nn * sizeof(double), hipMemcpyHostToDevice) != hipSuccess))) {
+        set_err(ctx, "upload of the eigen-decomposition failed");
+        return fail(MM_EDEVICE);
+      }
+    }
   }
   // other precisions: FP32, BF16-slice or digit-plane forms with zero-padded rows
   op->fac_lp.assign(op->d, nullptr);
@@ -792,7 +867,14 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
   const int la = last_axis(op);
   const int nl = op->n[la];
   const int64_t dof = op->dof;
-  if (family == MM_ERK) {
+  if (family == MM_ERK && op->exact) {
+    // buffers: 0 [u, g0] (or [-, F0]), 1 and 2 pairs of scratch, 3 U, 4 D, 5 F0
+    const int64_t lens[6] = {2 * dof, 2 * dof, 2 * dof, dof, dof, scheme == MM_ERK2P1 ? dof : 0};
+    for (int i = 0; i < 6; ++i) {
+      op->buf_len[i] = lens[i];
+      if (lens[i] > 0 && (rc = dev_alloc(op, &op->buf[i], lens[i])) != MM_OK) return fail(rc);
+    }
+  } else if (family == MM_ERK) {
     const int q = op->q;
     // stage 1: ETD2RK [E(1) | tau w_j E(theta_j)], ERK2P1 [tau w_j E(theta_j)]
     const int g1 = (scheme == MM_ETD2RK) ? q + 1 : q;
@@ -862,7 +944,7 @@ mm_status mumode_info(const mm_op* op, double* a_max, int* squarings) {
 }
 
 mm_status mumode_get_factor(const mm_op* op, int mu, int j, double* host_out) {
-  if (!op || !host_out || mu < 0 || mu >= op->d || j < 0 || j > op->q) return MM_EINVAL;
+  if (!op || !host_out || mu < 0 || mu >= op->d || j < 0 || j >= op->nfac) return MM_EINVAL;
   hipSetDevice(op->ctx->device);
   const int64_t nn = (int64_t)op->n[mu] * op->n[mu];
   if (hipMemcpy(host_out, factor(op, mu, j), nn * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
@@ -894,7 +976,7 @@ mm_status remainder_eval(mm_ctx* ctx, const mm_op* op, const double* u, double* 
 mm_status mumode_expv(mm_ctx* ctx, const mm_op* op, int j, const double* in, double* out, void* stream) {
   mm_status rc = check_op(ctx, op);
   if (rc != MM_OK) return rc;
-  if (!in || !out || j < 0 || j > op->q) {
+  if (!in || !out || j < 0 || j >= op->nfac) {
     set_err(ctx, "bad arguments to mumode_expv");
     return MM_EINVAL;
   }
@@ -917,6 +999,15 @@ mm_status mumode_phi1v(mm_ctx* ctx, const mm_op* op, const double* in, double* o
     return MM_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;
+  if (op->exact) {
+    // R transform, scale by phi1(tau Lambda), L transform
+    double* S1 = op->buf[1];
+    double* S2 = op->buf[2];
+    HIPCHK(ctx, exp_action(op, kFacR, in, false, S2, 1, S1, S1 + op->dof, s));
+    HIPCHK(ctx, eig_scale(op, S2, S2, 1.0, MM_EIG_PHI1, nullptr, 0.0, MM_EIG_ONE, s));
+    HIPCHK(ctx, exp_action(op, kFacL, S2, false, out, 1, S1, S1 + op->dof, s));
+    return MM_OK;
+  }
   const double* ins[kMaxGroups];
   int fidx[kMaxGroups];
   for (int g = 0; g < op->q; ++g) {
@@ -979,8 +1070,55 @@ mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hi
   return MM_OK;
 }
 
+// ERK steps with exact phi1 through the joint eigenbasis (A = L diag(Lambda) R per
+// axis): every phi1 or exponential action is an R transform, a diagonal scaling and an
+// L transform, so a step is 12 mode products instead of the quadrature's 2q+1 actions.
+mm_status enqueue_erk_exact(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hipStream_t s) {
+  const double tau = op->tau;
+  const int64_t dof = op->dof;
+  double *TG = op->buf[0], *S1 = op->buf[1], *S2 = op->buf[2], *U = op->buf[3], *D = op->buf[4], *F0 = op->buf[5];
+  double* g0 = TG + dof;
+  for (int it = 0; it < nsteps; ++it) {
+    // g0 = g(u), with u copied alongside so that [u, g0] transform together
+    StencilArgs a = stencil_args(op, u, false);
+    a.out0 = g0;
+    a.base1 = u;
+    a.c1 = 0.0;
+    a.out1 = TG;
+    HIPCHK(ctx, stencil(op, a, s));
+    if (op->scheme == MM_ETD2RK) {
+      // U = L (e^{tau Lambda} R u + tau phi1(tau Lambda) R g0). The transformed pair H
+      // comes out of the last pass: S1 in 3D (TG -> S1 -> S2 -> S1), S2 in 2D (TG -> S1
+      // -> S2); the scaled combination goes to the other buffer.
+      double* H = (op->d == 3) ? S1 : S2;
+      double* W = (op->d == 3) ? S2 : S1;
+      HIPCHK(ctx, exp_action(op, kFacR, TG, false, H, 2, S1, S2, s));
+      HIPCHK(ctx, eig_scale(op, W, H, 1.0, MM_EIG_EXP, H + dof, tau, MM_EIG_PHI1, s));
+      HIPCHK(ctx, exp_action(op, kFacL, W, false, U, 1, H, H + dof, s));
+    } else {
+      // U = u + L tau phi1(tau Lambda) R F(u)
+      StencilArgs f = stencil_args(op, u, true);
+      f.out0 = F0;
+      HIPCHK(ctx, stencil(op, f, s));
+      HIPCHK(ctx, exp_action(op, kFacR, F0, false, S2, 1, S1, S1 + dof, s));
+      HIPCHK(ctx, eig_scale(op, S2, S2, tau, MM_EIG_PHI1, nullptr, 0.0, MM_EIG_ONE, s));
+      HIPCHK(ctx, exp_action(op, kFacL, S2, false, U, 1, S1, S1 + dof, s, u));
+    }
+    // D = g(U) - g0;  u+ = U + L tau/2 phi1(tau Lambda) R D
+    StencilArgs b = stencil_args(op, U, false);
+    b.sub = g0;
+    b.out0 = D;
+    HIPCHK(ctx, stencil(op, b, s));
+    HIPCHK(ctx, exp_action(op, kFacR, D, false, S2, 1, S1, S1 + dof, s));
+    HIPCHK(ctx, eig_scale(op, S2, S2, 0.5 * tau, MM_EIG_PHI1, nullptr, 0.0, MM_EIG_ONE, s));
+    HIPCHK(ctx, exp_action(op, kFacL, S2, false, u, 1, S1, S1 + dof, s, U));
+  }
+  return MM_OK;
+}
+
 // Enqueue nsteps ERK steps on s (arguments already validated).
 mm_status enqueue_erk(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hipStream_t s) {
+  if (op->exact) return enqueue_erk_exact(ctx, op, u, nsteps, s);
   const double tau = op->tau;
   const int q = op->q;
   double *g0 = op->buf[0], *T1 = op->buf[1], *T2 = op->buf[2], *U = op->buf[3], *D = op->buf[4],

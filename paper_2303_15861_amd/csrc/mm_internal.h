@@ -99,6 +99,12 @@ hipError_t launch_lu_solve(double* Q, double* P, int n, int count, hipStream_t s
 hipError_t launch_place_scaled(double* dst, int ldd, int col0, const double* src, int n, double w,
                                hipStream_t s);
 hipError_t launch_fill(double* dst, double v, int64_t count, hipStream_t s);
+// Joint-eigenbasis scaling: out = ca f_a(tau L) a + cb f_b(tau L) b elementwise, with
+// L(k3,k2,k1) = ev1[k1] + ev2[k2] + ev3[k3] (ev3 null in 2D, n3 = 1); b may be null.
+enum { MM_EIG_ONE = 0, MM_EIG_EXP = 1, MM_EIG_PHI1 = 2 };
+hipError_t launch_eig_scale(double* out, const double* a, double ca, int fa, const double* b, double cb, int fb,
+                            const double* ev1, const double* ev2, const double* ev3, int n1, int n2, int n3,
+                            double tau, hipStream_t s);
 // out[0] = ||Q||_1, out[1] = ||Q||_inf (device); X = alpha Q^T; out[0] = max |R - I|
 hipError_t launch_norms(const double* Q, int n, double* out, hipStream_t s);
 hipError_t launch_scaled_transpose(double* X, const double* Q, int n, double alpha, hipStream_t s);
@@ -141,6 +147,9 @@ struct mm_op {
   double beta[3] = {0, 0, 0}, beta_bar[3] = {0, 0, 0}, r[4] = {0, 0, 0, 0};
   int family = 0, scheme = 0, q = 0, prec = 0;
   int slices = 0;                      // MM_SLICED digit count
+  bool exact = false;                  // MM_ERK with exact phi1 through the eigenbasis
+  int nfac = 1;                        // factors stored per axis
+  double* ev[3] = {nullptr, nullptr, nullptr};   // exact: 1D eigenvalues per axis
   int squarings[3] = {0, 0, 0};
   double theta[8] = {0}, weight[8] = {0};
   // device memory owned by the op

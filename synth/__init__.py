@@ -196,10 +196,17 @@ def workload(name: str, seed: int = 0) -> Problem:
                               tau=1e-3, steps=100, scheme="l2b", name=name)
     if name == "3d_n383_etd2rk":
         return anisotropic_problem(383, seed, tau=2e-3, steps=50, scheme="etd2rk", q=6, name=name)
+    # the same ETD2RK workloads with exact phi1 (q = 0: no quadrature nodes)
+    if name == "3d_n127_etd2rk_exact":
+        return smooth_problem((127,) * 3, seed, a_amp=0.9, beta=(10.0,) * 3, r=R_CUBIC,
+                              tau=5e-4, steps=200, scheme="etd2rk", q=0, name=name)
+    if name == "3d_n383_etd2rk_exact":
+        return anisotropic_problem(383, seed, tau=2e-3, steps=50, scheme="etd2rk", q=0, name=name)
     raise KeyError(name)
 
 
-WORKLOADS = ("2d_n63_le", "3d_n127_l2b", "3d_n127_etd2rk", "3d_n255_l2b", "3d_n383_etd2rk")
+WORKLOADS = ("2d_n63_le", "3d_n127_l2b", "3d_n127_etd2rk", "3d_n255_l2b", "3d_n383_etd2rk",
+             "3d_n127_etd2rk_exact", "3d_n383_etd2rk_exact")
 
 
 # --------------------------------------------------------------------------

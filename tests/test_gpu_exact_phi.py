@@ -1,0 +1,134 @@
+"""Exact phi1 through the joint eigenbasis (MM_ERK with quad_nodes = 0) against the
+FP64 oracle's eigenbasis phi1, which the CPU tests pin to the augmented-matrix
+exponential identity. The GPU's eigenvector matrices come from the closed form for
+tridiagonal Toeplitz matrices; the oracle's from its own implementation of it.
+
+Bar (FP64): 1e-12 relative to max |oracle|, as for every FP64 path (a transform is
+three K = n FP64 contractions with orthogonal-like factors).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import adr, expo
+from oracle import schemes as S
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def mm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_15861_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mm):
+    c = mm.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(got, ref):
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def oracle_op(p):
+    return expo.KronOperator(p.n, adr.extracted_amax(p.a), p.lam, p.beta_bar, p.tau)
+
+
+SHAPES = [((9, 13), (0.0, 0.0)), ((63, 63), (0.0, 0.0)), ((40, 33), (5.0, -3.0)), ((5, 6, 7), (0.0, 0.0, 0.0)),
+          ((31, 20, 17), (4.0, -2.0, 1.0)), ((70, 65, 66), (0.0, 0.0, 0.0))]
+
+
+@pytest.mark.parametrize("n,bb", SHAPES)
+def test_transforms_invert_and_phi1(mm, ctx, n, bb):
+    p = synth.smooth_problem(n, 21, tau=1e-3, scheme="etd2rk", q=0, beta_bar=bb, lam=0.9)
+    V = np.random.default_rng(22).standard_normal(p.shape)
+    op = mm.setup_problem(ctx, p)
+    x, y, z = dev(V), dev(np.zeros(p.shape)), dev(np.zeros(p.shape))
+    mm.mumode_expv(op, x, y, j=1)          # R transform
+    mm.mumode_expv(op, y, z, j=2)          # L transform: L R = identity
+    back = host(z)
+    w = dev(np.zeros(p.shape))
+    mm.mumode_phi1v(op, x, w)
+    got = host(w)
+    E0 = op.factor(0, 0)
+    op.close()
+    assert relerr(back, V) <= 1e-13
+    oop = oracle_op(p)
+    assert relerr(got, oop.phi1v_exact(V)) <= FP64_TOL
+    assert np.max(np.abs(E0 - oop.factors(1.0)[0])) <= FP64_TOL * np.max(np.abs(E0))
+
+
+CASES = [("etd2rk", (63, 63), 20), ("erk2p1f", (40, 33), 15), ("etd2rk", (24, 20, 18), 10),
+         ("erk2p1f", (21, 19, 17), 8)]
+
+
+@pytest.mark.parametrize("scheme,n,steps", CASES)
+def test_erk_exact_solve(mm, ctx, scheme, n, steps):
+    d = len(n)
+    p = synth.smooth_problem(n, 23, tau=1e-3, steps=steps, scheme=scheme, q=0,
+                             beta=(3.0, -2.0, 1.0)[:d], beta_bar=(1.0, 0.5, -0.5)[:d], lam=0.95)
+    op = mm.setup_problem(ctx, p)
+    u = dev(p.u0)
+    mm.step(op, u, p.steps)
+    assert mm.mm_check(op) == mm.MM_OK
+    got = host(u)
+    op.close()
+    ref = S.solve(p, phi="exact")
+    assert relerr(got, ref) <= FP64_TOL
+
+
+def test_exact_full_size_step_127(mm, ctx):
+    p = synth.workload("3d_n127_etd2rk_exact")
+    op = mm.setup_problem(ctx, p)
+    u = dev(p.u0)
+    mm.step(op, u, 1)
+    got = host(u)
+    op.close()
+    ref = S.solve(p, steps=1)
+    assert relerr(got, ref) <= FP64_TOL
+
+
+def test_exact_graph_replay(mm):
+    """Recorded graphs of the exact-phi1 step give the same bits as direct launches."""
+    p = synth.smooth_problem((20, 18, 16), 24, tau=1e-3, steps=6, scheme="etd2rk", q=0)
+    outs = []
+    for gs in (0, 2):
+        c = mm.Context(0)
+        c.set_graph_steps(gs)
+        op = mm.setup_problem(c, p)
+        u = dev(p.u0)
+        mm.step(op, u, 6)
+        outs.append(host(u))
+        op.close()
+        c.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_exact_rejections(mm, ctx):
+    p = synth.smooth_problem((12, 10, 9), 25, tau=1e-3, scheme="etd2rk", q=0)
+    with pytest.raises(mm.MumodeError):
+        mm.setup_problem(ctx, p, prec="fp32")
+    # cell Peclet number above 2 on x1: complex eigenvalues, no real closed form
+    q = synth.smooth_problem((12, 10, 9), 25, tau=1e-3, scheme="etd2rk", q=0, beta_bar=(1e4, 0.0, 0.0))
+    with pytest.raises(mm.MumodeError):
+        mm.setup_problem(ctx, q)
+    assert "eigenvalues" in ctx.error()
