@@ -81,6 +81,11 @@ typedef enum { MM_FP64 = 0, MM_FP32 = 1, MM_BF16X3 = 2, MM_BF16X6 = 3, MM_SLICED
  *                     MM_ERK2P1        the same scheme in the Appendix form
  *                                      U = u + tau phi1(tau A) F(u),
  *                                      u+ = U + tau/2 phi1(tau A)(g(U) - g(u))
+ *                     MM_EE            exponential Euler u+ = u + tau phi1(tau A) F(u)
+ *                     MM_ERK2P2        second-order ERK with phi2 (Appendix, c2 = 1):
+ *                                      U = u + tau phi1(tau A) F(u),
+ *                                      u+ = U + tau phi2(tau A)(g(U) - g(u))
+ *                                      (MM_EE and MM_ERK2P2 need exact phi, q = 0)
  * phi1(tau A) is replaced by the q-node Gauss-Legendre rule
  *   phi1(tau A) v ~ sum_j w_j exp(theta_j tau A) v,  theta_j, w_j on [0, 1],
  * or (q = 0) evaluated exactly in the joint eigenbasis of the Kronecker sum: with
@@ -88,7 +93,7 @@ typedef enum { MM_FP64 = 0, MM_FP32 = 1, MM_BF16X3 = 2, MM_BF16X6 = 3, MM_SLICED
  *   f(tau A) v = (v x_mu R_mu over mu) scaled by f(tau (ev_1 + ev_2 + ev_3)) x_mu L_mu.  */
 enum { MM_LAWSON = 0, MM_ERK = 1 };
 enum { MM_LAWSON_EULER = 0, MM_LAWSON2B = 1 };
-enum { MM_ETD2RK = 0, MM_ERK2P1 = 1 };
+enum { MM_ETD2RK = 0, MM_ERK2P1 = 1, MM_EE = 2, MM_ERK2P2 = 3 };
 
 typedef struct {
   int d;                 /* 2 or 3                                                    */

@@ -37,7 +37,9 @@ def prec_code(prec: str):
         raise ValueError(f"unknown precision {prec!r}; one of {sorted(PRECISIONS)}")
     return PRECISIONS[prec], (int(prec[6:]) if prec.startswith("sliced") else 0)
 SCHEMES = {"le": (MM_LAWSON, MM_LAWSON_EULER), "l2b": (MM_LAWSON, MM_LAWSON2B),
-           "etd2rk": (MM_ERK, MM_ETD2RK), "erk2p1f": (MM_ERK, MM_ERK2P1)}
+           "etd2rk": (MM_ERK, MM_ETD2RK), "erk2p1f": (MM_ERK, MM_ERK2P1),
+           # exact phi functions only (q = 0)
+           "ee": (MM_ERK, 2), "erk2p2": (MM_ERK, 3)}
 STATUS = {0: "MM_OK", 1: "MM_NOT_READY", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_EDEVICE",
           -4: "MM_EUNSTABLE", -5: "MM_EBUSY", -6: "MM_ENOTFOUND"}
 

@@ -657,8 +657,12 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     set_err(ctx, "unknown Lawson scheme %d", scheme);
     return MM_EINVAL;
   }
-  if (family == MM_ERK && scheme != MM_ETD2RK && scheme != MM_ERK2P1) {
+  if (family == MM_ERK && scheme != MM_ETD2RK && scheme != MM_ERK2P1 && scheme != MM_EE && scheme != MM_ERK2P2) {
     set_err(ctx, "unknown ERK scheme %d", scheme);
+    return MM_EINVAL;
+  }
+  if (family == MM_ERK && (scheme == MM_EE || scheme == MM_ERK2P2) && quad_nodes != 0) {
+    set_err(ctx, "exponential Euler and ERK2 with phi2 need exact phi functions (quad_nodes = 0)");
     return MM_EINVAL;
   }
   if (family == MM_ERK && (quad_nodes < 0 || quad_nodes > kMaxGroups - 1)) {
@@ -869,7 +873,7 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
   const int64_t dof = op->dof;
   if (family == MM_ERK && op->exact) {
     // buffers: 0 [u, g0] (or [-, F0]), 1 and 2 pairs of scratch, 3 U, 4 D, 5 F0
-    const int64_t lens[6] = {2 * dof, 2 * dof, 2 * dof, dof, dof, scheme == MM_ERK2P1 ? dof : 0};
+    const int64_t lens[6] = {2 * dof, 2 * dof, 2 * dof, dof, dof, scheme != MM_ETD2RK ? dof : 0};
     for (int i = 0; i < 6; ++i) {
       op->buf_len[i] = lens[i];
       if (lens[i] > 0 && (rc = dev_alloc(op, &op->buf[i], lens[i])) != MM_OK) return fail(rc);
@@ -1070,23 +1074,31 @@ mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hi
   return MM_OK;
 }
 
-// ERK steps with exact phi1 through the joint eigenbasis (A = L diag(Lambda) R per
-// axis): every phi1 or exponential action is an R transform, a diagonal scaling and an
-// L transform, so a step is 12 mode products instead of the quadrature's 2q+1 actions.
+// ERK steps with exact phi functions through the joint eigenbasis (A = L diag(Lambda) R
+// per axis): every phi or exponential action is an R transform, a diagonal scaling and
+// an L transform, so an ETD2RK step is 12 mode products instead of the quadrature's 2q+1
+// actions.
 mm_status enqueue_erk_exact(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hipStream_t s) {
   const double tau = op->tau;
   const int64_t dof = op->dof;
   double *TG = op->buf[0], *S1 = op->buf[1], *S2 = op->buf[2], *U = op->buf[3], *D = op->buf[4], *F0 = op->buf[5];
   double* g0 = TG + dof;
+  const int sch = op->scheme;
   for (int it = 0; it < nsteps; ++it) {
-    // g0 = g(u), with u copied alongside so that [u, g0] transform together
-    StencilArgs a = stencil_args(op, u, false);
-    a.out0 = g0;
-    a.base1 = u;
-    a.c1 = 0.0;
-    a.out1 = TG;
-    HIPCHK(ctx, stencil(op, a, s));
-    if (op->scheme == MM_ETD2RK) {
+    if (sch != MM_EE) {
+      // g0 = g(u); ETD2RK also copies u alongside so that [u, g0] transform together
+      StencilArgs a = stencil_args(op, u, false);
+      a.out0 = g0;
+      if (sch == MM_ETD2RK) {
+        a.base1 = u;
+        a.c1 = 0.0;
+        a.out1 = TG;
+      }
+      HIPCHK(ctx, stencil(op, a, s));
+    }
+    // first stage into U (exponential Euler: straight into u)
+    double* U1 = (sch == MM_EE) ? u : U;
+    if (sch == MM_ETD2RK) {
       // U = L (e^{tau Lambda} R u + tau phi1(tau Lambda) R g0). The transformed pair H
       // comes out of the last pass: S1 in 3D (TG -> S1 -> S2 -> S1), S2 in 2D (TG -> S1
       // -> S2); the scaled combination goes to the other buffer.
@@ -1094,7 +1106,7 @@ mm_status enqueue_erk_exact(mm_ctx* ctx, const mm_op* op, double* u, int nsteps,
       double* W = (op->d == 3) ? S2 : S1;
       HIPCHK(ctx, exp_action(op, kFacR, TG, false, H, 2, S1, S2, s));
       HIPCHK(ctx, eig_scale(op, W, H, 1.0, MM_EIG_EXP, H + dof, tau, MM_EIG_PHI1, s));
-      HIPCHK(ctx, exp_action(op, kFacL, W, false, U, 1, H, H + dof, s));
+      HIPCHK(ctx, exp_action(op, kFacL, W, false, U1, 1, H, H + dof, s));
     } else {
       // U = u + L tau phi1(tau Lambda) R F(u)
       StencilArgs f = stencil_args(op, u, true);
@@ -1102,15 +1114,20 @@ mm_status enqueue_erk_exact(mm_ctx* ctx, const mm_op* op, double* u, int nsteps,
       HIPCHK(ctx, stencil(op, f, s));
       HIPCHK(ctx, exp_action(op, kFacR, F0, false, S2, 1, S1, S1 + dof, s));
       HIPCHK(ctx, eig_scale(op, S2, S2, tau, MM_EIG_PHI1, nullptr, 0.0, MM_EIG_ONE, s));
-      HIPCHK(ctx, exp_action(op, kFacL, S2, false, U, 1, S1, S1 + dof, s, u));
+      HIPCHK(ctx, exp_action(op, kFacL, S2, false, U1, 1, S1, S1 + dof, s, u));
     }
-    // D = g(U) - g0;  u+ = U + L tau/2 phi1(tau Lambda) R D
+    if (sch == MM_EE) continue;
+    // D = g(U) - g0;  u+ = U + L c f(tau Lambda) R D with c f = tau/2 phi1 (ETD2RK,
+    // ERK2P1) or tau phi2 (ERK2P2)
     StencilArgs b = stencil_args(op, U, false);
     b.sub = g0;
     b.out0 = D;
     HIPCHK(ctx, stencil(op, b, s));
     HIPCHK(ctx, exp_action(op, kFacR, D, false, S2, 1, S1, S1 + dof, s));
-    HIPCHK(ctx, eig_scale(op, S2, S2, 0.5 * tau, MM_EIG_PHI1, nullptr, 0.0, MM_EIG_ONE, s));
+    if (sch == MM_ERK2P2)
+      HIPCHK(ctx, eig_scale(op, S2, S2, tau, MM_EIG_PHI2, nullptr, 0.0, MM_EIG_ONE, s));
+    else
+      HIPCHK(ctx, eig_scale(op, S2, S2, 0.5 * tau, MM_EIG_PHI1, nullptr, 0.0, MM_EIG_ONE, s));
     HIPCHK(ctx, exp_action(op, kFacL, S2, false, u, 1, S1, S1 + dof, s, U));
   }
   return MM_OK;

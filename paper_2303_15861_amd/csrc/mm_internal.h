@@ -101,7 +101,7 @@ hipError_t launch_place_scaled(double* dst, int ldd, int col0, const double* src
 hipError_t launch_fill(double* dst, double v, int64_t count, hipStream_t s);
 // Joint-eigenbasis scaling: out = ca f_a(tau L) a + cb f_b(tau L) b elementwise, with
 // L(k3,k2,k1) = ev1[k1] + ev2[k2] + ev3[k3] (ev3 null in 2D, n3 = 1); b may be null.
-enum { MM_EIG_ONE = 0, MM_EIG_EXP = 1, MM_EIG_PHI1 = 2 };
+enum { MM_EIG_ONE = 0, MM_EIG_EXP = 1, MM_EIG_PHI1 = 2, MM_EIG_PHI2 = 3 };
 hipError_t launch_eig_scale(double* out, const double* a, double ca, int fa, const double* b, double cb, int fb,
                             const double* ev1, const double* ev2, const double* ev3, int n1, int n2, int n3,
                             double tau, hipStream_t s);

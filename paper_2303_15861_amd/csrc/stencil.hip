@@ -214,9 +214,25 @@ hipError_t launch_place_scaled(double* dst, int ldd, int col0, const double* src
 // ---------------------------------------------------------------- eigenbasis scaling
 // In the joint eigenbasis of A = A_1 (+) A_2 (+) A_3 every function of tau A is diagonal:
 // the entry (k3, k2, k1) is scaled by f(tau (ev1[k1] + ev2[k2] + ev3[k3])).
+// phi2(z) = (e^z - 1 - z)/z^2 = sum_k z^k/(k+2)!; the series for |z| < 1/2 (where the
+// closed form cancels), the closed form through expm1 elsewhere.
+__device__ __forceinline__ double phi2_fn(double z) {
+  if (fabs(z) < 0.5) {
+    double term = 0.5, acc = 0.0;   // term = z^k/(k+2)!
+#pragma unroll 1
+    for (int k = 0; k < 24; ++k) {
+      acc += term;
+      term *= z / (k + 3);
+    }
+    return acc;
+  }
+  return (expm1(z) - z) / (z * z);
+}
+
 __device__ __forceinline__ double eig_fn(int f, double z) {
   if (f == MM_EIG_EXP) return exp(z);
   if (f == MM_EIG_PHI1) return (z == 0.0) ? 1.0 : expm1(z) / z;   // phi1(z) = (e^z - 1)/z
+  if (f == MM_EIG_PHI2) return phi2_fn(z);
   return 1.0;
 }
 

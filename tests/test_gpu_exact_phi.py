@@ -78,7 +78,8 @@ def test_transforms_invert_and_phi1(mm, ctx, n, bb):
 
 
 CASES = [("etd2rk", (63, 63), 20), ("erk2p1f", (40, 33), 15), ("etd2rk", (24, 20, 18), 10),
-         ("erk2p1f", (21, 19, 17), 8)]
+         ("erk2p1f", (21, 19, 17), 8), ("ee", (50, 45), 12), ("ee", (22, 19, 18), 6),
+         ("erk2p2", (47, 41), 12), ("erk2p2", (23, 21, 17), 6)]
 
 
 @pytest.mark.parametrize("scheme,n,steps", CASES)
@@ -127,6 +128,10 @@ def test_exact_rejections(mm, ctx):
     p = synth.smooth_problem((12, 10, 9), 25, tau=1e-3, scheme="etd2rk", q=0)
     with pytest.raises(mm.MumodeError):
         mm.setup_problem(ctx, p, prec="fp32")
+    # phi2 schemes have no quadrature form here
+    e = synth.smooth_problem((12, 10, 9), 25, tau=1e-3, scheme="erk2p2", q=4)
+    with pytest.raises(mm.MumodeError):
+        mm.setup_problem(ctx, e)
     # cell Peclet number above 2 on x1: complex eigenvalues, no real closed form
     q = synth.smooth_problem((12, 10, 9), 25, tau=1e-3, scheme="etd2rk", q=0, beta_bar=(1e4, 0.0, 0.0))
     with pytest.raises(mm.MumodeError):
