@@ -75,6 +75,13 @@ typedef enum { MM_FP64 = 0, MM_FP32 = 1, MM_BF16X3 = 2, MM_BF16X6 = 3, MM_SLICED
  *   family MM_LAWSON: MM_LAWSON_EULER  u+ = e^{tau A}(u + tau g(u))
  *                     MM_LAWSON2B      U = e^{tau A}(u + tau g(u)),
  *                                      u+ = e^{tau A}(u + tau/2 g(u)) + tau/2 g(U)
+ *                     MM_SLE           stabilized Lawson-Euler u+ = u + tau e^{tau A} F(u)
+ *                     MM_LAWSON2A      U = e^{tau/2 A}(u + tau/2 g(u)),
+ *                                      u+ = e^{tau A} u + tau e^{tau/2 A} g(U)
+ *                     MM_SL2           stabilized Lawson2, alpha = 0.327:
+ *                                      U = u + alpha tau e^{alpha tau A} F(u),
+ *                                      u+ = u + tau e^{tau/2 A} F(u)
+ *                                           + tau/(2 alpha) e^{tau A}(g(U) - g(u))
  *   family MM_ERK:    MM_ETD2RK        second-order ERK with phi1, c2 = 1, in the form
  *                                      U = e^{tau A}u + tau phi1(tau A) g(u),
  *                                      u+ = U + tau/2 phi1(tau A)(g(U) - g(u))
@@ -92,7 +99,7 @@ typedef enum { MM_FP64 = 0, MM_FP32 = 1, MM_BF16X3 = 2, MM_BF16X6 = 3, MM_SLICED
  * A_mu = L_mu diag(ev_mu) R_mu (closed form for the tridiagonal Toeplitz A_mu),
  *   f(tau A) v = (v x_mu R_mu over mu) scaled by f(tau (ev_1 + ev_2 + ev_3)) x_mu L_mu.  */
 enum { MM_LAWSON = 0, MM_ERK = 1 };
-enum { MM_LAWSON_EULER = 0, MM_LAWSON2B = 1 };
+enum { MM_LAWSON_EULER = 0, MM_LAWSON2B = 1, MM_SLE = 2, MM_LAWSON2A = 3, MM_SL2 = 4 };
 enum { MM_ETD2RK = 0, MM_ERK2P1 = 1, MM_EE = 2, MM_ERK2P2 = 3 };
 
 typedef struct {
@@ -145,7 +152,8 @@ mm_status mumode_info(const mm_op* op, double* a_max, int* squarings);
 
 /* Copy the FP64 factor of index j of axis mu into host memory (n_mu*n_mu values,
  * row-major E[row][col]): exp(c tau A_mu) with c = 1 (j = 0) or c = theta_j (j = 1..q);
- * with exact phi1 (q = 0), j = 1 is R_mu and j = 2 is L_mu. */
+ * with exact phi1 (q = 0), j = 1 is R_mu and j = 2 is L_mu; Lawson2a and stabilized
+ * Lawson2 add c = 1/2 (j = 1) and, for the latter, c = alpha (j = 2). */
 mm_status mumode_get_factor(const mm_op* op, int mu, int j, double* host_out);
 
 /* Remainder (eq. (eq:nonlin)) on the grid, flux-form centred differences, face

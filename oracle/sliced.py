@@ -112,7 +112,7 @@ class SlicedBackend:
 def solve(prob, S: int, steps=None) -> np.ndarray:
     """The problem's Lawson scheme with sliced exponential actions."""
     from .schemes import integrate
-    if prob.scheme not in ("le", "l2b"):
-        raise ValueError("the sliced oracle covers the Lawson schemes le and l2b")
+    if prob.scheme not in ("le", "l2b", "sle", "l2a", "sl2"):
+        raise ValueError("the sliced oracle covers the Lawson schemes (only exponential actions)")
     be = SlicedBackend(prob, S)
     return integrate(prob.u0, be, prob.tau, prob.steps if steps is None else steps, prob.scheme)

@@ -37,6 +37,7 @@ def prec_code(prec: str):
         raise ValueError(f"unknown precision {prec!r}; one of {sorted(PRECISIONS)}")
     return PRECISIONS[prec], (int(prec[6:]) if prec.startswith("sliced") else 0)
 SCHEMES = {"le": (MM_LAWSON, MM_LAWSON_EULER), "l2b": (MM_LAWSON, MM_LAWSON2B),
+           "sle": (MM_LAWSON, 2), "l2a": (MM_LAWSON, 3), "sl2": (MM_LAWSON, 4),
            "etd2rk": (MM_ERK, MM_ETD2RK), "erk2p1f": (MM_ERK, MM_ERK2P1),
            # exact phi functions only (q = 0)
            "ee": (MM_ERK, 2), "erk2p2": (MM_ERK, 3)}

@@ -390,8 +390,10 @@ const double* factor(const mm_op* op, int mu, int j) {
 // out = exp(c_j tau A) in for `nvec` stacked vectors (stride dof): in -> t0 [-> t1] -> out.
 // in_f32: the input is float (mixed modes only); out is always double. In the mixed
 // modes the intermediates t0, t1 hold floats.
+// out = alpha exp(c_j tau A) in + beta add (add optional).
 hipError_t exp_action(const mm_op* op, int j, const void* in, bool in_f32, double* out, int nvec, double* t0,
-                      double* t1, hipStream_t s, const double* add = nullptr) {
+                      double* t1, hipStream_t s, const double* add = nullptr, double alpha = 1.0,
+                      double beta = 1.0) {
   const bool mixed = lowp(op);
   PassIO first{in_f32, mixed}, mid{mixed, mixed}, last_io{mixed, false};
   const int fj[1] = {j};
@@ -407,12 +409,12 @@ hipError_t exp_action(const mm_op* op, int j, const void* in, bool in_f32, doubl
     void* o2[1] = {t1};
     e = pass_mode2(op, 1, fj, i2, o2, op->n[2] * nvec, mid, s);
     if (e != hipSuccess) return e;
-    return pass_last(op, Fl, Fe, 1, t1, out, add, 1.0, add ? 1.0 : 0.0, nvec, last_io, s);
+    return pass_last(op, Fl, Fe, 1, t1, out, add, alpha, add ? beta : 0.0, nvec, last_io, s);
   }
   hipError_t e = pass_mode1(op, 1, i1, fj, o1, (int)(op->dof / op->n[0]) * nvec, first, s);
   if (e != hipSuccess) return e;
   PassIO l2{mixed, false};
-  return pass_last(op, Fl, Fe, 1, t0, out, add, 1.0, add ? 1.0 : 0.0, nvec, l2, s);
+  return pass_last(op, Fl, Fe, 1, t0, out, add, alpha, add ? beta : 0.0, nvec, l2, s);
 }
 
 // out = stacked-last-factor contraction over G groups: group g applies modes 1..d-1 with
@@ -653,7 +655,7 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     set_err(ctx, "unknown family %d", family);
     return MM_EINVAL;
   }
-  if (family == MM_LAWSON && scheme != MM_LAWSON_EULER && scheme != MM_LAWSON2B) {
+  if (family == MM_LAWSON && (scheme < MM_LAWSON_EULER || scheme > MM_SL2)) {
     set_err(ctx, "unknown Lawson scheme %d", scheme);
     return MM_EINVAL;
   }
@@ -752,14 +754,20 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
   // coefficients c of the factors exp(c tau A_mu): c_0 = 1, c_j = theta_j
   // Pade factors exp(c tau A_mu) for c = 1 and the quadrature nodes; the exact-phi1 mode
   // stores two more per axis, the eigenvector matrices R and L (A_mu = L diag(ev) R)
-  const int nf = 1 + op->q;
-  op->nfac = op->exact ? 3 : nf;
+  int nf = 1 + op->q;
   double cs[kMaxGroups];
   cs[0] = 1.0;
   if (op->q > 0) {
     gauss_legendre(op->q, op->theta + 1, op->weight + 1);
     for (int j = 1; j <= op->q; ++j) cs[j] = op->theta[j];
   }
+  // Lawson2a uses exp(tau A / 2) too; stabilized Lawson2 exp(tau A / 2) and exp(alpha tau A)
+  if (family == MM_LAWSON && (scheme == MM_LAWSON2A || scheme == MM_SL2)) {
+    cs[nf++] = 0.5;
+    if (scheme == MM_SL2) cs[nf++] = kAlphaSL2;
+    for (int j = 1; j < nf; ++j) op->theta[j] = cs[j];
+  }
+  op->nfac = op->exact ? 3 : nf;
   op->theta[0] = 1.0;
   op->weight[0] = 1.0;
 
@@ -925,10 +933,15 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
       if (lens[i] > 0 && (rc = dev_alloc(op, &op->buf[i], lens[i])) != MM_OK) return fail(rc);
     }
   } else {
-    // buffers: 0 and 1 hold two stacked grid functions each
+    // buffers: 0 and 1 hold two stacked grid functions each; stabilized Lawson2 needs a
+    // fifth grid function (buffer 2)
     for (int i = 0; i < 2; ++i) {
       op->buf_len[i] = 2 * dof;
       if ((rc = dev_alloc(op, &op->buf[i], 2 * dof)) != MM_OK) return fail(rc);
+    }
+    if (scheme == MM_SL2) {
+      op->buf_len[2] = dof;
+      if ((rc = dev_alloc(op, &op->buf[2], dof)) != MM_OK) return fail(rc);
     }
   }
   if (hipStreamSynchronize(st) != hipSuccess) {
@@ -1047,6 +1060,43 @@ mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hi
         a.out0 = b0;
       HIPCHK(ctx, stencil(op, a, s));
       HIPCHK(ctx, exp_action(op, 0, b0, mixed, u, 1, b1, b0, s));
+    } else if (op->scheme == MM_SLE) {
+      // u+ = u + tau e^{tau A} F(u)
+      StencilArgs f = stencil_args(op, u, true);
+      f.out0 = b0;
+      HIPCHK(ctx, stencil(op, f, s));
+      HIPCHK(ctx, exp_action(op, 0, b0, false, u, 1, b1, b1 + dof, s, u, tau, 1.0));
+    } else if (op->scheme == MM_LAWSON2A) {
+      // U = e^{tau/2 A}(u + tau/2 g(u)); u+ = e^{tau A} u + tau e^{tau/2 A} g(U)
+      StencilArgs a = stencil_args(op, u, false);
+      a.base0 = u;
+      a.c0 = 0.5 * tau;
+      a.out0 = b0;
+      HIPCHK(ctx, stencil(op, a, s));
+      double* U = b0 + dof;
+      HIPCHK(ctx, exp_action(op, 1, b0, false, U, 1, b1, b1 + dof, s));
+      StencilArgs c = stencil_args(op, U, false);
+      c.out0 = b0;
+      HIPCHK(ctx, stencil(op, c, s));
+      HIPCHK(ctx, exp_action(op, 1, b0, false, U, 1, b1, b1 + dof, s));
+      HIPCHK(ctx, exp_action(op, 0, u, false, u, 1, b1, b1 + dof, s, U, 1.0, tau));
+    } else if (op->scheme == MM_SL2) {
+      // U = u + alpha tau e^{alpha tau A} F(u);
+      // u+ = u + tau e^{tau/2 A} F(u) + tau/(2 alpha) e^{tau A}(g(U) - g(u))
+      double *F0 = b0, *g0 = b0 + dof, *U = op->buf[2];
+      StencilArgs f = stencil_args(op, u, true);
+      f.out0 = F0;
+      HIPCHK(ctx, stencil(op, f, s));
+      StencilArgs a = stencil_args(op, u, false);
+      a.out0 = g0;
+      HIPCHK(ctx, stencil(op, a, s));
+      HIPCHK(ctx, exp_action(op, 2, F0, false, U, 1, b1, b1 + dof, s, u, kAlphaSL2 * tau, 1.0));
+      StencilArgs c = stencil_args(op, U, false);   // D = g(U) - g0, in place of g0
+      c.sub = g0;
+      c.out0 = g0;
+      HIPCHK(ctx, stencil(op, c, s));
+      HIPCHK(ctx, exp_action(op, 1, F0, false, U, 1, b1, b1 + dof, s, u, tau, 1.0));   // W (over U)
+      HIPCHK(ctx, exp_action(op, 0, g0, false, u, 1, b1, b1 + dof, s, U, 0.5 * tau / kAlphaSL2, 1.0));
     } else {
       // v1 = u + tau g(u), v2 = u + tau/2 g(u); [U, W] = e^{tau A}[v1, v2]; u+ = W + tau/2 g(U)
       StencilArgs a = stencil_args(op, u, false);

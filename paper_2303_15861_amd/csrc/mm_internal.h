@@ -12,6 +12,8 @@
 namespace mm {
 
 constexpr int kMaxGroups = 8;   // quadrature nodes + 1
+// stabilized Lawson2: the alpha of Theorem thm:stablawson2 (stability bound 0.182)
+constexpr double kAlphaSL2 = 0.327;
 
 // One batched/grouped GEMM  C[g][b] = alpha * A[g][b] . B'[g][b] + beta * Cadd[g][b]
 // with row-major operands: A[m][k] at m*lda + k; C[m][n] at m*ldc + n;
