@@ -1238,10 +1238,13 @@ mm_status enqueue_steps(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hip
   return op->family == MM_LAWSON ? enqueue_lawson(ctx, op, u, nsteps, s) : enqueue_erk(ctx, op, u, nsteps, s);
 }
 
-// Record `gs` steps on state u into the op's graph (capture runs nothing).
+// Record `gs` steps on state u into the op's graph (capture runs nothing). A previous
+// graph of the op may still be replaying on the stream it was last launched on: wait for
+// that stream before destroying it.
 mm_status record_graph(mm_ctx* ctx, const mm_op* op, double* u, int gs) {
   if (!ctx->capture) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
   if (op->gexec) {
+    HIPCHK(ctx, hipStreamSynchronize(op->gstream));
     HIPCHK(ctx, hipGraphExecDestroy(op->gexec));
     op->gexec = nullptr;
   }
@@ -1272,6 +1275,7 @@ mm_status run_steps(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hipStre
     if (rc != MM_OK) return rc;
   }
   const int reps = nsteps / gs;
+  op->gstream = s;
   for (int i = 0; i < reps; ++i) HIPCHK(ctx, hipGraphLaunch(op->gexec, s));
   return enqueue_steps(ctx, op, u, nsteps - reps * gs, s);
 }

@@ -179,4 +179,5 @@ struct mm_op {
   mutable hipGraphExec_t gexec = nullptr;
   mutable double* gu = nullptr;
   mutable int gsteps = 0;
+  mutable hipStream_t gstream = nullptr;   // stream of the last replay
 };

@@ -321,6 +321,7 @@ mm_status mm_server_create(int device, int max_active, int64_t hbm_budget, mm_se
   s->budget = hbm_budget;
   for (int i = 0; i < kStreams; ++i)
     if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
+      for (int k = 0; k < i; ++k) hipStreamDestroy(s->streams[k]);
       for (int k = 0; k < kAdmitThreads; ++k) mm_ctx_destroy(s->actx[k]);
       mm_ctx_destroy(s->ctx);
       delete s;
