@@ -190,10 +190,11 @@ mm_status mm_check(mm_ctx* ctx, const mm_op* op, void* stream);
  * enqueues is bracketed by two HIP events recorded on the launch's own stream, and the
  * launch's algorithmic work is recorded with it (mode products: 2*M*N*K flops per
  * batch, padding excluded; stencil: grid points). kind: MM_KIND_STENCIL, MM_KIND_GEMM_K
- * (mode-1 kernel, both operands read along k) or MM_KIND_GEMM_N (modes 2..d, the grid
- * operand read along n). mm_timing_read synchronises the recorded events and returns
+ * (mode-1 kernel, both operands read along k), MM_KIND_GEMM_N (modes 2..d, the grid
+ * operand read along n) or MM_KIND_FUSED (whole small-2D solves, work = mode-product
+ * flops). mm_timing_read synchronises the recorded events and returns
  * the totals since the last enable. */
-enum { MM_KIND_STENCIL = 0, MM_KIND_GEMM_K = 1, MM_KIND_GEMM_N = 2 };
+enum { MM_KIND_STENCIL = 0, MM_KIND_GEMM_K = 1, MM_KIND_GEMM_N = 2, MM_KIND_FUSED = 3 };
 mm_status mm_timing_enable(mm_ctx* ctx, int enable);
 mm_status mm_timing_read(mm_ctx* ctx, int kind, int64_t* launches, double* total_ms, double* work);
 
@@ -203,6 +204,13 @@ mm_status mm_timing_read(mm_ctx* ctx, int kind, int64_t* launches, double* total
  * that agree to rounding (the sum over k runs in the same order in both). Other values:
  * MM_EINVAL. Takes effect for launches enqueued after the call. */
 mm_status mm_set_gemm_tile(mm_ctx* ctx, int tile);
+
+/* Small 2D Lawson solves (n1, n2 <= 64, FP64, Lawson-Euler or Lawson2b) run their whole
+ * time loop in one workgroup: state and stage vectors in LDS, the same stencil
+ * arithmetic and mode products on the FP64 matrix cores, one launch per lawson_step
+ * call. enable = 0 launches them step by step like larger problems (tests, timing).
+ * Default: enabled. Results agree with the launched path to rounding. */
+mm_status mm_set_small_fused(mm_ctx* ctx, int enable);
 
 /* Step replay through HIP graphs (launch-bound small problems). steps = 0 (default):
  * lawson_step / erk_step launch their kernels one by one. steps = G > 0: a call with

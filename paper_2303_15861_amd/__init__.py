@@ -50,8 +50,8 @@ EXPORTS = ("mm_ctx_create", "mm_ctx_destroy", "mm_last_error", "mm_version", "mu
            "mumode_phi1v", "lawson_step", "erk_step", "mm_check", "mm_server_create",
            "mm_server_destroy", "solve_submit", "solve_poll", "mm_server_clock", "mm_timing_enable",
            "mm_timing_read", "mm_synchronize", "mm_set_gemm_tile",
-           "mm_set_graph_steps")
-MM_KIND_STENCIL, MM_KIND_GEMM_K, MM_KIND_GEMM_N = 0, 1, 2
+           "mm_set_graph_steps", "mm_set_small_fused")
+MM_KIND_STENCIL, MM_KIND_GEMM_K, MM_KIND_GEMM_N, MM_KIND_FUSED = 0, 1, 2, 3
 
 
 class MMProblem(Structure):
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_synchronize": (i, [vp]),
         "mm_set_gemm_tile": (i, [vp, i]),
         "mm_set_graph_steps": (i, [vp, i]),
+        "mm_set_small_fused": (i, [vp, i]),
         "mm_timing_read": (i, [vp, i, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
     }
     for name, (res, args) in sig.items():
@@ -176,6 +177,10 @@ class Context:
     def set_gemm_tile(self, tile: int):
         """0: automatic; 64 or 128: force that workgroup tile for mode products."""
         self.check(lib().mm_set_gemm_tile(self._h, int(tile)), "mm_set_gemm_tile")
+
+    def set_small_fused(self, enable: bool):
+        """Whole small 2D Lawson solves in one workgroup (default on)."""
+        self.check(lib().mm_set_small_fused(self._h, int(enable)), "mm_set_small_fused")
 
     def set_graph_steps(self, steps: int):
         """0: launch step kernels one by one; G > 0: replay recorded graphs of G steps."""

@@ -1048,6 +1048,36 @@ mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hi
   double* b0 = op->buf[0];
   double* b1 = op->buf[1];
   const bool mixed = lowp(op);
+  if (ctx->small_fused && op->prec == MM_FP64 && small2d_fits(op->d, op->n[0], op->n[1]) &&
+      (op->scheme == MM_LAWSON_EULER || op->scheme == MM_LAWSON2B)) {
+    // the whole time loop in one workgroup
+    if (nsteps == 0) return MM_OK;
+    const StencilArgs sa = stencil_args(op, u, false);
+    SmallArgs a{};
+    a.u = u;
+    a.a = op->a;
+    a.E1 = factor(op, 0, 0);
+    a.E2 = factor(op, 1, 0);
+    a.n1 = op->n[0];
+    a.n2 = op->n[1];
+    a.nsteps = nsteps;
+    a.tau = tau;
+    for (int mu = 0; mu < 2; ++mu) {
+      a.ih2[mu] = sa.ih2[mu];
+      a.cadv[mu] = sa.cadv[mu];
+    }
+    a.lam_amax = sa.lam_amax;
+    a.r0 = sa.r0;
+    a.r1 = sa.r1;
+    a.r2 = sa.r2;
+    a.r3 = sa.r3;
+    a.flag = op->flag;
+    const double work = (double)nsteps * (op->scheme == MM_LAWSON2B ? 2 : 1) * 2.0 *
+                        (double)op->dof * (op->n[0] + op->n[1]);
+    HIPCHK(ctx, timed_launch(ctx, MM_KIND_FUSED, work, s,
+                             [&] { return launch_lawson_small2d(a, op->scheme == MM_LAWSON2B, s); }));
+    return MM_OK;
+  }
   for (int it = 0; it < nsteps; ++it) {
     if (op->scheme == MM_LAWSON_EULER) {
       // u+ = e^{tau A}(u + tau g(u))
@@ -1310,6 +1340,12 @@ mm_status erk_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* st
     return MM_EINVAL;
   }
   return run_steps(ctx, op, u, nsteps, (hipStream_t)stream);
+}
+
+mm_status mm_set_small_fused(mm_ctx* ctx, int enable) {
+  if (!ctx) return MM_EINVAL;
+  ctx->small_fused = enable != 0;
+  return MM_OK;
 }
 
 mm_status mm_set_graph_steps(mm_ctx* ctx, int steps) {

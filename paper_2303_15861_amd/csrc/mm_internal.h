@@ -73,6 +73,21 @@ struct StencilArgs {
   int* flag;            // nullable: set to 1 if out0 is not finite
 };
 
+// Whole small 2D Lawson solves in one workgroup (n1, n2 <= 64, FP64).
+struct SmallArgs {
+  double* u;            // n2 x n1, advanced in place
+  const double* a;      // (n2+2) x (n1+2)
+  const double* E1;     // n1 x n1 factor exp(tau A_1)
+  const double* E2;     // n2 x n2 factor exp(tau A_2)
+  int n1, n2, nsteps;
+  double tau;
+  double ih2[2], cadv[2], lam_amax;
+  double r0, r1, r2, r3;
+  int* flag;
+};
+bool small2d_fits(int d, int n1, int n2);
+hipError_t launch_lawson_small2d(const SmallArgs& a, bool l2b, hipStream_t s);
+
 hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s);
 // Tile size the launcher takes for g (g.tile if set, else 64 when 128-tiles would not
 // fill the chip once).
@@ -135,6 +150,7 @@ struct mm_ctx {
   bool timing = false;            // per-kernel event timing
   int gemm_tile = 0;              // 0 = automatic, else forced 64 or 128
   int graph_steps = 0;            // >0: step calls replay captured graphs of this many steps
+  bool small_fused = true;        // small 2D Lawson solves as one-workgroup kernels
   hipStream_t capture = nullptr;  // private stream used only to record graphs
   std::vector<mm_timed> timed;
   size_t timed_used = 0;
