@@ -13,108 +13,274 @@
 
 namespace mm {
 
-// Each thread owns one x1 column of a YT (x2) x ZT (x3) patch of grid points and keeps
-// the patch with a one-point halo in registers, so the x2/x3 neighbours of u and a are
-// loaded once per patch instead of once per point; x1 neighbours come from the same
-// cache lines as the neighbouring lanes' centres. A wave covers 64 consecutive x1, so
-// every access is a coalesced row segment. No LDS and no barriers.
-constexpr int SX = 64, SY = 4, YT = 2, ZT = 4;
+// Layout of the work. Each lane owns P consecutive x1 points (P = 1, 2 or 4), so one
+// wave covers a 64 P-point segment of an x1 row with 8 P-byte loads per lane, and the
+// x1 neighbours of its points come from its own registers or, at the lane edges, from
+// the neighbouring lanes by shuffles; only the two ends of the segment need a load
+// (lanes 0 and 63 together, one instruction per row). Each lane also keeps a YT (x2)
+// x ZT (x3) patch of such rows with a one-row halo in registers (no corners), so the
+// x2/x3 neighbours are loaded once per patch. The cost of this kernel is the number
+// of vector memory instructions per point more than its HBM bytes; this layout
+// needs about 3 per point plus the stage operands, against 12 for one point per lane.
+// Blocks are four waves stacked along x2 and are numbered x1 segment fastest, then x2,
+// then x3. Outputs are written with nontemporal stores: the next reader is another
+// kernel, much later than any cache would keep them.
+typedef double dbl2u __attribute__((ext_vector_type(2), aligned(8)));
+typedef float flt2u __attribute__((ext_vector_type(2), aligned(4)));
+typedef float flt4u __attribute__((ext_vector_type(4), aligned(4)));
 
-// Block order: workgroups are dealt round-robin over the eight XCDs (id % 8), each with
-// its own L2. XCD k takes a contiguous band of x2-blocks and walks it x1-fastest, then
-// x2, then x3, so the x2 and x3 halos a block reads were (or are about to be) fetched
-// into the same L2 by its neighbours.
+constexpr int SW = 4;   // waves per block, stacked along x2
+
 struct StencilGrid {
-  int nxb, nyb, nzb, ybx;
+  int nxs, nyb, nzb;    // x1 segments, x2 blocks, x3 blocks
 };
 
-template <int D>
-__global__ __launch_bounds__(SX * SY) void stencil_kernel(StencilArgs p, StencilGrid sg) {
-  constexpr int ZP = (D == 3) ? ZT : 1;   // points per thread along x3
+// P values at base[off..off+P) into v; element k is wanted for k < cnt (cnt may exceed
+// P). One vector access when all P lie inside the row or at least inside the
+// allocation [0, lim); elementwise otherwise (the last row of an array).
+template <int P>
+__device__ __forceinline__ void load_row(double (&v)[P], const double* __restrict__ base, int64_t off, int64_t lim,
+                                         int cnt) {
+  if (cnt >= P || off + P <= lim) {
+    if constexpr (P == 1) {
+      v[0] = base[off];
+    } else {
+#pragma unroll
+      for (int k = 0; k < P; k += 2) {
+        const dbl2u t = *(const dbl2u*)(base + off + k);
+        v[k] = t.x;
+        v[k + 1] = t.y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < P; ++k) v[k] = (k < cnt) ? base[off + k] : 0.0;
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void store_row(double* __restrict__ base, int64_t off, const double (&v)[P], int cnt) {
+  if (cnt >= P) {
+    if constexpr (P == 1) {
+      __builtin_nontemporal_store(v[0], base + off);
+    } else {
+#pragma unroll
+      for (int k = 0; k < P; k += 2) __builtin_nontemporal_store(dbl2u{v[k], v[k + 1]}, (dbl2u*)(base + off + k));
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < P; ++k)
+      if (k < cnt) base[off + k] = v[k];
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void store_row(float* __restrict__ base, int64_t off, const double (&v)[P], int cnt) {
+  if (cnt >= P) {
+    if constexpr (P == 1) {
+      __builtin_nontemporal_store((float)v[0], base + off);
+    } else if constexpr (P == 2) {
+      __builtin_nontemporal_store(flt2u{(float)v[0], (float)v[1]}, (flt2u*)(base + off));
+    } else {
+      __builtin_nontemporal_store(flt4u{(float)v[0], (float)v[1], (float)v[2], (float)v[3]},
+                                  (flt4u*)(base + off));
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < P; ++k)
+      if (k < cnt) base[off + k] = (float)v[k];
+  }
+}
+
+template <int D, int P>
+__global__ __launch_bounds__(64 * SW) void stencil_kernel(StencilArgs p, StencilGrid sg) {
+  constexpr int YT = (D == 3) ? 1 : 2;   // rows per lane along x2
+  constexpr int ZT = (D == 3) ? 2 : 1;   // rows per lane along x3
+  constexpr int YH = YT + 2;             // with the x2 halo
+  constexpr int ZH = (D == 3) ? ZT + 2 : 1;
   const int L = blockIdx.x;
-  const int xcd = L & 7, j = L >> 3;
-  const int bx = j % sg.nxb;
-  const int r = j / sg.nxb;
-  const int by = xcd * sg.ybx + r % sg.ybx;
-  const int bz = r / sg.ybx;
-  if (by >= sg.nyb || bz >= sg.nzb) return;
-  const int tx = threadIdx.x & (SX - 1), ty = threadIdx.x / SX;
-  const int i1 = bx * SX + tx;
-  const int y0 = (by * SY + ty) * YT;
-  const int z0 = (D == 3) ? bz * ZT : 0;
+  const int bx = L % sg.nxs;
+  const int rb = L / sg.nxs;
+  const int by = rb % sg.nyb;
+  const int bz = rb / sg.nyb;
+  const int tx = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int n1 = p.n1, n2 = p.n2, n3 = p.n3;
-  if (i1 >= n1) return;
-  const int s2 = n1, s3 = n1 * n2;                    // strides of u
-  const int t2 = n1 + 2, t3 = (n1 + 2) * (n2 + 2);    // strides of a (padded)
+  const int x0 = bx * 64 * P;            // first x1 of the wave's segment
+  const int x = x0 + P * tx;             // first x1 of this lane
+  const int y0 = (by * SW + w) * YT;
+  const int z0 = (D == 3) ? bz * ZT : 0;
+  const int64_t s2 = n1, s3 = (int64_t)n1 * n2;               // strides of u
+  const int64_t t2 = n1 + 2, t3 = (int64_t)(n1 + 2) * (n2 + 2);   // strides of a (padded)
+  const int64_t nu = s3 * n3, na = t3 * ((D == 3) ? n3 + 2 : 1);
+  const int ucnt = n1 - x;               // u elements of this lane inside the row
+  const int acnt = n1 + 1 - x;           // a elements with x1 <= n1 (the last is a boundary node)
   const double* __restrict__ u = p.u;
   const double* __restrict__ a = p.a;
-  // patch with halo: uu[y][z] holds u at (i1, y0 - 1 + y, z0 - 1 + z); corners unused
-  double uu[YT + 2][ZP + 2], aa[YT + 2][ZP + 2];
+  // uu[y][z][k] = u at (x + k, y0 - 1 + y, z0 - 1 + z) (2D: z0 + z); zero outside the grid
+  double uu[YH][ZH][P], aa[YH][ZH][P];
 #pragma unroll
-  for (int y = 0; y < YT + 2; ++y)
+  for (int y = 0; y < YH; ++y)
 #pragma unroll
-    for (int z = 0; z < ZP + 2; ++z) {
+    for (int z = 0; z < ZH; ++z) {
       const int i2 = y0 - 1 + y;
       const int i3 = (D == 3) ? z0 - 1 + z : 0;
-      const bool need = (D == 3) ? !((y == 0 || y == YT + 1) && (z == 0 || z == ZP + 1)) : (z == 1);
-      const bool uin = need && i2 >= 0 && i2 < n2 && i3 >= 0 && i3 < n3;
-      const bool ain = need && i2 >= -1 && i2 <= n2 && (D == 2 || (i3 >= -1 && i3 <= n3));
-      uu[y][z] = uin ? u[i1 + s2 * i2 + s3 * i3] : 0.0;
-      aa[y][z] = ain ? a[(i1 + 1) + t2 * (i2 + 1) + (D == 3 ? t3 * (i3 + 1) : 0)] : 0.0;
+      const bool need = (D == 3) ? !((y == 0 || y == YH - 1) && (z == 0 || z == ZH - 1)) : true;
+      const bool urow = need && ucnt > 0 && i2 >= 0 && i2 < n2 && i3 >= 0 && i3 < n3;
+      const bool arow = need && acnt > 0 && i2 >= -1 && i2 <= n2 && (D == 2 || (i3 >= -1 && i3 <= n3));
+      if (urow) {
+        load_row<P>(uu[y][z], u, x + s2 * i2 + s3 * i3, nu, ucnt);
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+          if (k >= ucnt) uu[y][z][k] = 0.0;
+      } else {
+#pragma unroll
+        for (int k = 0; k < P; ++k) uu[y][z][k] = 0.0;
+      }
+      if (arow) {
+        load_row<P>(aa[y][z], a, (x + 1) + t2 * (i2 + 1) + ((D == 3) ? t3 * (i3 + 1) : 0), na, acnt);
+      } else {
+#pragma unroll
+        for (int k = 0; k < P; ++k) aa[y][z][k] = 0.0;
+      }
     }
+  const bool edge = (tx == 0) || (tx == 63);
+  const int xe = (tx == 0) ? x0 - 1 : x0 + 64 * P;   // the segment's outside neighbour
+  const bool useg = sg.nxs > 1;                      // u beyond the segment can be nonzero
   const double la = p.lam_amax;
 #pragma unroll
   for (int y = 1; y <= YT; ++y)
 #pragma unroll
-    for (int z = 1; z <= ZP; ++z) {
+    for (int z = (D == 3) ? 1 : 0; z < ((D == 3) ? ZT + 1 : 1); ++z) {
       const int i2 = y0 - 1 + y;
       const int i3 = (D == 3) ? z0 - 1 + z : 0;
-      if (i2 >= n2 || i3 >= n3) continue;
-      const int idx = i1 + s2 * i2 + s3 * i3;
-      const int ia = (i1 + 1) + t2 * (i2 + 1) + (D == 3 ? t3 * (i3 + 1) : 0);
-      const double uc = uu[y][z], ac = aa[y][z];
-      const double uxm = (i1 > 0) ? u[idx - 1] : 0.0;
-      const double uxp = (i1 + 1 < n1) ? u[idx + 1] : 0.0;
-      const double axm = a[ia - 1], axp = a[ia + 1];
-      double g = ((0.5 * (ac + axp) - la) * (uxp - uc) - (0.5 * (ac + axm) - la) * (uc - uxm)) * p.ih2[0] +
-                 p.cadv[0] * (uxp - uxm);
-      g += ((0.5 * (ac + aa[y + 1][z]) - la) * (uu[y + 1][z] - uc) -
-            (0.5 * (ac + aa[y - 1][z]) - la) * (uc - uu[y - 1][z])) * p.ih2[1] +
-           p.cadv[1] * (uu[y + 1][z] - uu[y - 1][z]);
-      if (D == 3)
-        g += ((0.5 * (ac + aa[y][z + 1]) - la) * (uu[y][z + 1] - uc) -
-              (0.5 * (ac + aa[y][z - 1]) - la) * (uc - uu[y][z - 1])) * p.ih2[2] +
-             p.cadv[2] * (uu[y][z + 1] - uu[y][z - 1]);
-      g += p.r0 + uc * (p.r1 + uc * (p.r2 + uc * p.r3));
-      if (p.sub) g -= p.sub[idx];
-      const double o0 = (p.base0 ? p.base0[idx] : 0.0) + p.c0 * g;
-      if (p.out0f)
-        p.out0f[idx] = (float)o0;
-      else
-        p.out0[idx] = o0;
-      if (p.out1 || p.out1f) {
-        const double o1 = (p.base1 ? p.base1[idx] : 0.0) + p.c1 * g;
-        if (p.out1f)
-          p.out1f[idx] = (float)o1;
-        else
-          p.out1[idx] = o1;
+      const bool live_row = i2 < n2 && i3 < n3;
+      const int64_t urow = s2 * i2 + s3 * i3;
+      const int64_t arow = t2 * (i2 + 1) + ((D == 3) ? t3 * (i3 + 1) : 0);
+      const double* uc = uu[y][z];
+      const double* ac = aa[y][z];
+      // x1 neighbours across lanes (every lane takes part), then the segment ends
+      double ul = __shfl_up(uc[P - 1], 1), ur = __shfl_down(uc[0], 1);
+      double al = __shfl_up(ac[P - 1], 1), ar = __shfl_down(ac[0], 1);
+      if (edge) {
+        const double ue = (useg && live_row && xe >= 0 && xe < n1) ? u[urow + xe] : 0.0;
+        const double ae = (live_row && xe >= -1 && xe <= n1) ? a[arow + xe + 1] : 0.0;
+        if (tx == 0) {
+          ul = ue;
+          al = ae;
+        } else {
+          ur = ue;
+          ar = ae;
+        }
       }
-      if (p.flag && !(fabs(o0) <= DBL_MAX)) p.flag[0] = 1;
+      if (!live_row || ucnt <= 0) continue;
+      const int64_t idx = x + urow;
+      double g[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const double u0 = uc[k], a0 = ac[k];
+        const double uxm = (k == 0) ? ul : uc[k - 1], uxp = (k == P - 1) ? ur : uc[k + 1];
+        const double axm = (k == 0) ? al : ac[k - 1], axp = (k == P - 1) ? ar : ac[k + 1];
+        double v = ((0.5 * (a0 + axp) - la) * (uxp - u0) - (0.5 * (a0 + axm) - la) * (u0 - uxm)) * p.ih2[0] +
+                   p.cadv[0] * (uxp - uxm);
+        v += ((0.5 * (a0 + aa[y + 1][z][k]) - la) * (uu[y + 1][z][k] - u0) -
+              (0.5 * (a0 + aa[y - 1][z][k]) - la) * (u0 - uu[y - 1][z][k])) * p.ih2[1] +
+             p.cadv[1] * (uu[y + 1][z][k] - uu[y - 1][z][k]);
+        if constexpr (D == 3)
+          v += ((0.5 * (a0 + aa[y][z + 1][k]) - la) * (uu[y][z + 1][k] - u0) -
+                (0.5 * (a0 + aa[y][z - 1][k]) - la) * (u0 - uu[y][z - 1][k])) * p.ih2[2] +
+               p.cadv[2] * (uu[y][z + 1][k] - uu[y][z - 1][k]);
+        v += p.r0 + u0 * (p.r1 + u0 * (p.r2 + u0 * p.r3));
+        g[k] = v;
+      }
+      if (p.sub) {
+        double sv[P];
+        load_row<P>(sv, p.sub, idx, nu, ucnt);
+#pragma unroll
+        for (int k = 0; k < P; ++k) g[k] -= sv[k];
+      }
+      // out0 = base0 + c0 g (base0 == u: from registers)
+      double o[P];
+      if (p.base0 == nullptr) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) o[k] = p.c0 * g[k];
+      } else if (p.base0 == u) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) o[k] = uc[k] + p.c0 * g[k];
+      } else {
+        load_row<P>(o, p.base0, idx, nu, ucnt);
+#pragma unroll
+        for (int k = 0; k < P; ++k) o[k] += p.c0 * g[k];
+      }
+      if (p.flag) {
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < P; ++k) bad |= (k < ucnt) && !(fabs(o[k]) <= DBL_MAX);
+        if (bad) p.flag[0] = 1;
+      }
+      if (p.out0f)
+        store_row<P>(p.out0f, idx, o, ucnt);
+      else
+        store_row<P>(p.out0, idx, o, ucnt);
+      if (p.out1 || p.out1f) {
+        if (p.base1 == nullptr) {
+#pragma unroll
+          for (int k = 0; k < P; ++k) o[k] = p.c1 * g[k];
+        } else if (p.base1 == u) {
+#pragma unroll
+          for (int k = 0; k < P; ++k) o[k] = uc[k] + p.c1 * g[k];
+        } else {
+          load_row<P>(o, p.base1, idx, nu, ucnt);
+#pragma unroll
+          for (int k = 0; k < P; ++k) o[k] += p.c1 * g[k];
+        }
+        if (p.out1f)
+          store_row<P>(p.out1f, idx, o, ucnt);
+        else
+          store_row<P>(p.out1, idx, o, ucnt);
+      }
     }
 }
 
+// Points per lane: with a segment width W = 64 P ceil(n1 / 64 P), the cost of a row is
+// taken as W / P (load instructions) + W / 4 (bytes); the P in {4, 2, 1} of least cost.
+static int points_per_lane(int n1) {
+  int best = 4;
+  double cost = 1e300;
+  for (int P : {4, 2, 1}) {
+    const double wdt = 64.0 * P * ((n1 + 64 * P - 1) / (64 * P));
+    const double c = wdt / P + wdt / 4;
+    if (c < cost) {
+      cost = c;
+      best = P;
+    }
+  }
+  return best;
+}
+
+template <int D>
+static void launch_d(int P, const StencilArgs& a, StencilGrid sg, unsigned blocks, hipStream_t s) {
+  if (P == 4)
+    stencil_kernel<D, 4><<<dim3(blocks), dim3(64 * SW), 0, s>>>(a, sg);
+  else if (P == 2)
+    stencil_kernel<D, 2><<<dim3(blocks), dim3(64 * SW), 0, s>>>(a, sg);
+  else
+    stencil_kernel<D, 1><<<dim3(blocks), dim3(64 * SW), 0, s>>>(a, sg);
+}
+
 hipError_t launch_stencil(int d, const StencilArgs& a, hipStream_t s) {
+  if (a.n1 < 1 || a.n2 < 1 || a.n3 < 1) return hipErrorInvalidValue;
+  const int P = points_per_lane(a.n1);
   StencilGrid sg;
-  sg.nxb = (a.n1 + SX - 1) / SX;
-  sg.nyb = (a.n2 + SY * YT - 1) / (SY * YT);
-  sg.nzb = (d == 3) ? (a.n3 + ZT - 1) / ZT : 1;
-  sg.ybx = (sg.nyb + 7) / 8;
-  const int64_t blocks = 8LL * sg.nxb * sg.ybx * sg.nzb;
+  sg.nxs = (a.n1 + 64 * P - 1) / (64 * P);
+  const int yt = (d == 3) ? 1 : 2, zt = (d == 3) ? 2 : 1;
+  sg.nyb = (a.n2 + SW * yt - 1) / (SW * yt);
+  sg.nzb = (d == 3) ? (a.n3 + zt - 1) / zt : 1;
+  const int64_t blocks = (int64_t)sg.nxs * sg.nyb * sg.nzb;
   if (blocks >= (1LL << 31)) return hipErrorInvalidValue;
   if (d == 3)
-    stencil_kernel<3><<<dim3((unsigned)blocks), dim3(SX * SY), 0, s>>>(a, sg);
+    launch_d<3>(P, a, sg, (unsigned)blocks, s);
   else
-    stencil_kernel<2><<<dim3((unsigned)blocks), dim3(SX * SY), 0, s>>>(a, sg);
+    launch_d<2>(P, a, sg, (unsigned)blocks, s);
   return hipGetLastError();
 }
 
