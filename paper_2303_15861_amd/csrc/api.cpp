@@ -224,6 +224,10 @@ hipError_t timed_launch(mm_ctx* ctx, int kind, double work, hipStream_t s, F&& l
 hipError_t gemm(const mm_op* op, GemmArgs& g, hipStream_t s) {
   const double work = 2.0 * g.M * (double)g.N * g.K * g.inner * g.groups;
   g.tile = op->ctx ? op->ctx->gemm_tile : 0;
+  g.vdig = op->vdig;
+  g.vexp = op->vexp;
+  g.vdig_cap = op->vdig_len;
+  g.vexp_cap = op->vexp_len;
   return timed_launch(op->ctx, g.b_trans ? MM_KIND_GEMM_N : MM_KIND_GEMM_K, work, s,
                       [&] { return launch_gemm(op->prec, g, s); });
 }
@@ -621,6 +625,8 @@ void mumode_destroy(mm_op* op) {
   dev_free(op, op->f3_phi_exp);
   for (int mu = 0; mu < 3; ++mu) dev_free(op, op->ev[mu]);
   for (int i = 0; i < 6; ++i) dev_free(op, op->buf[i]);
+  dev_free(op, op->vdig);
+  dev_free(op, op->vexp);
   dev_free(op, op->flag);
   if (op->gexec) hipGraphExecDestroy(op->gexec);
   delete op;
@@ -943,6 +949,27 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
       op->buf_len[2] = dof;
       if ((rc = dev_alloc(op, &op->buf[2], dof)) != MM_OK) return fail(rc);
     }
+  }
+  if (prec == MM_SLICED) {
+    // the grid operand of the largest sliced launch: G groups or stacked vectors per
+    // mode product (ERK: the q + 1 stage groups, Lawson: the stacked pair), and the
+    // stacked last mode of the ERK stages (K = G n_last)
+    const int S = op->slices;
+    const int64_t G = std::max(2, op->q + 1);
+    int64_t dig = 0, ex = 0;
+    for (int mu = 0; mu < op->d; ++mu) {
+      const int64_t fib = dof / op->n[mu];
+      dig = std::max(dig, G * fib * S * slice_ld(op->n[mu]));
+      ex = std::max(ex, G * fib);
+    }
+    if (family == MM_ERK) {
+      dig = std::max(dig, (dof / nl) * S * (int64_t)slice_ld((int)G * nl));
+      ex = std::max(ex, dof / nl);
+    }
+    op->vdig_len = dig;
+    op->vexp_len = ex;
+    if ((rc = dev_alloc(op, &op->vdig, dig)) != MM_OK) return fail(rc);
+    if ((rc = dev_alloc(op, &op->vexp, ex)) != MM_OK) return fail(rc);
   }
   if (hipStreamSynchronize(st) != hipSuccess) {
     set_err(ctx, "setup failed on the device");

@@ -42,6 +42,11 @@ struct GemmArgs {
   int slices;
   const int* fexp[kMaxGroups];
   double galpha[kMaxGroups];   // MM_SLICED: extra per-group output scale (0 = none)
+  // MM_SLICED: workspace for the digit planes and fiber exponents of the grid operand
+  // (sliced_workspace() bytes and ints for this launch)
+  signed char* vdig;
+  int* vexp;
+  int64_t vdig_cap, vexp_cap;
   // filled by the launcher
   int tiles_m, tiles_n, total, per_xcd;
 };
@@ -50,7 +55,14 @@ constexpr int kFacPad = 32;   // k padding of pre-converted factors
 inline int fac_ld(int k) { return (k + kFacPad - 1) / kFacPad * kFacPad; }
 // digit planes of MM_SLICED: rows zero-padded to a multiple of 64 in k
 constexpr int kMinSlices = 3, kMaxSlices = 7, kDefaultSlices = 6;
-inline int slice_ld(int k) { return (k + 63) / 64 * 64; }
+__host__ __device__ inline int slice_ld(int k) { return (k + 63) / 64 * 64; }
+// Workspace of a sliced launch: digit bytes and exponent count for the grid operand
+// (groups x fibers x S x slice_ld(K) bytes; groups x fibers exponents). Fibers are the
+// M rows (mode 1) or the inner x N columns (modes 2 and 3).
+__host__ __device__ inline int64_t sliced_fibers(const GemmArgs& g) { return g.b_trans ? (int64_t)g.inner * g.N : (int64_t)g.M; }
+__host__ __device__ inline int64_t sliced_digit_bytes(const GemmArgs& g) {
+  return (int64_t)g.groups * sliced_fibers(g) * g.slices * slice_ld(g.K);
+}
 
 // Stencil launch parameters (remainder g and fused stage updates).
 struct StencilArgs {
@@ -189,6 +201,10 @@ struct mm_op {
   int* f3_phi_exp = nullptr;
   double* buf[6] = {nullptr};          // scratch
   int64_t buf_len[6] = {0};
+  // MM_SLICED: digit planes and fiber exponents of the grid operand of one launch
+  signed char* vdig = nullptr;
+  int* vexp = nullptr;
+  int64_t vdig_len = 0, vexp_len = 0;
   int* flag = nullptr;                 // sticky non-finite flag
   int64_t bytes = 0;                   // device footprint
   // recorded step graph: `gsteps` steps on state `gu` (rebuilt when either changes)

@@ -1,4 +1,4 @@
-// Exact-slice mode products on the int8 matrix cores (v_mfma_i32_16x16x64_i8).
+// Exact-slice mode products on the int8 matrix cores (v_mfma_i32_32x32x32_i8).
 //
 // Every operand row r (along the contracted index k) gets a power-of-two scale: e_r with
 // max_k |x_rk| < 2^e_r. A value becomes Y = round(x 2^(8S-2-e_r)) (|Y| <= 2^(8S-2))
@@ -15,22 +15,25 @@
 //
 // The factor (n x n, or stacked quadrature factors) is split once at setup into S digit
 // planes with per-row exponents (rows zero-padded to a multiple of 64 in k). The grid
-// operand stays FP64 in memory: each workgroup first finds the exponents of its 64 grid
-// rows (mode 1) or columns (modes 2/3) over the whole k range, then splits values into
-// digits while staging them into LDS, four consecutive k at a time (a 4 x 4 byte
-// transpose turns four packed values into one dword per digit plane). Workgroup tile
-// 64 x 64, four waves of 32 x 32, one accumulator per digit level.
+// operand is split once per launch by slice_grid, a streaming pass that finds the
+// exponent of every grid fiber (a row of the operand in mode 1, a column in modes 2/3,
+// over the whole k range) and writes its digit planes with 16 consecutive k of one fiber
+// per 16-byte vector. The product kernel then stages both operands into LDS with
+// 16-byte loads only (splitting inside the product kernel would repeat the work once
+// per 64-row output tile). Workgroup tile 64 x 64, four waves of 32 x 32, one
+// accumulator per digit level.
 #include "mm_internal.h"
 
 namespace mm {
 
 typedef int i4 __attribute__((ext_vector_type(4)));
+typedef int i16 __attribute__((ext_vector_type(16)));
 
 namespace {
 
 constexpr int T8 = 64;      // workgroup tile
-constexpr int KC8 = 64;     // k per chunk (one int8 MFMA)
-constexpr int PI8 = 80;     // LDS row pitch in bytes (16 lanes of 16-byte reads hit all 64 banks once)
+constexpr int KC8 = 64;     // k per chunk (two int8 MFMA k-steps)
+constexpr int PI8 = 80;     // LDS row pitch in bytes (16 lanes of 16-byte reads from consecutive rows hit all 64 banks once)
 constexpr int TH = 256;
 
 // Balanced base-256 digits of x relative to exponent e, packed: byte i of (lo, hi) is
@@ -87,9 +90,111 @@ __device__ __forceinline__ int row_exponent(double mx) {
 
 }  // namespace
 
+// Grid digits of group g, plane s (plane = fibers * slice_ld(K) bytes, group stride
+// S * plane):
+//   mode 1 (rows):     base + fiber * slice_ld(K) + k                 (k contiguous)
+//   modes 2/3 (cols):  base + (k / 16) * (fibers * 16) + fiber * 16 + k % 16
+// (16 consecutive k of one fiber per 16-byte vector, consecutive fibers adjacent, so
+// that the column split writes, and the product stages, whole 1 KB runs).
+template <int BT, int S>
+__global__ __launch_bounds__(TH) void slice_grid(GemmArgs p, int fblocks) {
+  const int g = blockIdx.x / fblocks;
+  const int fb = blockIdx.x - g * fblocks;
+  const int K = p.K, kp = slice_ld(K);
+  const int64_t F = sliced_fibers(p);
+  const int64_t plane = F * kp;
+  signed char* __restrict__ D = p.vdig + g * (S * plane);
+  int* __restrict__ X = p.vexp + g * F;
+  const int tid = threadIdx.x;
+  if (!BT) {
+    // one wave per row, four consecutive k per lane (coalesced row reads and writes)
+    const int row = fb * (TH / 64) + (tid >> 6), lane = tid & 63;
+    if (row >= p.M) return;   // whole waves
+    const double* __restrict__ vr = (const double*)p.A[g] + (int64_t)row * p.lda;
+    double mx = 0.0;
+    for (int k0 = 4 * lane; k0 < K; k0 += 256)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (k0 + i < K) mx = __builtin_fmax(mx, __builtin_fabs(vr[k0 + i]));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mx = __builtin_fmax(mx, __shfl_xor(mx, off));
+    const int e = row_exponent(mx);
+    if (lane == 0) X[row] = e;
+    signed char* __restrict__ dr = D + (int64_t)row * kp;
+    for (int k0 = 4 * lane; k0 < kp; k0 += 256) {
+      double v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = (k0 + i < K) ? vr[k0 + i] : 0.0;
+      unsigned pl[S];
+      slice4<S>(v[0], v[1], v[2], v[3], e, pl);
+#pragma unroll
+      for (int t = 0; t < S; ++t) *reinterpret_cast<unsigned*>(dr + t * plane + k0) = pl[t];
+    }
+  } else {
+    // 64 columns of one batch per workgroup; lane = column, the four waves take every
+    // fourth 16-run of k; for K <= 256 the values stay in registers between the
+    // exponent scan and the split
+    const int nb = (p.N + T8 - 1) / T8;
+    const int b = fb / nb, n = (fb - b * nb) * T8 + (tid & 63), kg = tid >> 6;
+    const bool live = n < p.N;
+    const double* __restrict__ V = (const double*)p.B[g] + b * p.sB + (live ? n : 0);
+    __shared__ double red[4][T8];
+    const int64_t f = (int64_t)b * p.N + n;
+    auto store = [&](int k0, const double (&v)[16], int e) {
+      unsigned pl[4][S];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) slice4<S>(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3], e, pl[q]);
+#pragma unroll
+      for (int t = 0; t < S; ++t)
+        *reinterpret_cast<i4*>(D + t * plane + (int64_t)(k0 >> 4) * (F * 16) + f * 16) =
+            i4{(int)pl[0][t], (int)pl[1][t], (int)pl[2][t], (int)pl[3][t]};
+    };
+    if (K <= 256) {
+      double v[4][16];
+      double mx = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int k = 16 * kg + 64 * j + i;
+          v[j][i] = (k < K) ? V[(int64_t)k * p.ldb] : 0.0;
+          mx = __builtin_fmax(mx, __builtin_fabs(v[j][i]));
+        }
+      red[kg][tid & 63] = mx;
+      __syncthreads();
+      const int c = tid & 63;
+      const int e =
+          row_exponent(__builtin_fmax(__builtin_fmax(red[0][c], red[1][c]), __builtin_fmax(red[2][c], red[3][c])));
+      if (!live) return;
+      if (kg == 0) X[f] = e;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (16 * kg + 64 * j < kp) store(16 * kg + 64 * j, v[j], e);
+    } else {
+      double mx = 0.0;
+      for (int k0 = 16 * kg; k0 < K; k0 += 64)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (k0 + i < K) mx = __builtin_fmax(mx, __builtin_fabs(V[(int64_t)(k0 + i) * p.ldb]));
+      red[kg][tid & 63] = mx;
+      __syncthreads();
+      const int c = tid & 63;
+      const int e =
+          row_exponent(__builtin_fmax(__builtin_fmax(red[0][c], red[1][c]), __builtin_fmax(red[2][c], red[3][c])));
+      if (!live) return;
+      if (kg == 0) X[f] = e;
+      for (int k0 = 16 * kg; k0 < kp; k0 += 64) {
+        double v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = (k0 + i < K) ? V[(int64_t)(k0 + i) * p.ldb] : 0.0;
+        store(k0, v, e);
+      }
+    }
+  }
+}
+
 template <int BT, int S>
 __global__ __launch_bounds__(TH, 2) void gemm_i8(GemmArgs p) {
-  constexpr int FI = 2;                      // 16 x 16 fragments per wave and dimension
   const int L = blockIdx.x;
   const int P = (L & 7) * p.per_xcd + (L >> 3);
   if (P >= p.total) return;
@@ -113,173 +218,107 @@ __global__ __launch_bounds__(TH, 2) void gemm_i8(GemmArgs p) {
   }
   const signed char* __restrict__ F =
       BT ? (const signed char*)p.A[g] + b * p.sA : (const signed char*)p.B[g] + b * p.sB;
-  const double* __restrict__ V = BT ? (const double*)p.B[g] + b * p.sB : (const double*)p.A[g] + b * p.sA;
   const int* __restrict__ Fexp = p.fexp[g];
   double* __restrict__ C = (double*)p.C[g] + b * p.sC;
   const double* __restrict__ Cadd = p.Cadd[g] ? p.Cadd[g] + b * p.sC : nullptr;
   const int M = p.M, N = p.N, K = p.K;
   const int ldf = BT ? p.lda : p.ldb;        // digit-plane row stride (multiple of 64)
-  const int ldv = BT ? p.ldb : p.lda;
   const int fr0 = BT ? m0 : n0, frows = BT ? M : N;
   const int vr0 = BT ? n0 : m0, vrows = BT ? N : M;
   const int64_t fsl = p.fac_slice;
+  // grid digits of this group and the fiber of this thread's staging column
+  const int64_t nfib = sliced_fibers(p);
+  const int64_t vplane = nfib * slice_ld(K);
+  const signed char* __restrict__ Vd = p.vdig + g * (S * vplane);
+  const int* __restrict__ Vx = p.vexp + g * nfib;
+  const int64_t vfib0 = BT ? (int64_t)b * N : 0;
 
   __shared__ __attribute__((aligned(16))) signed char Fs[S][T8 * PI8];
   __shared__ __attribute__((aligned(16))) signed char Vs[S][T8 * PI8];
   __shared__ int Fe[T8], Ve[T8];
-  __shared__ double red[4][T8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int lg = lane >> 4, lr = lane & 15;
   const int nch = (K + KC8 - 1) / KC8;
 
-  // grid staging map. !BT: k quad kq = tid & 15 (k = 4kq..4kq+3), rows r16 + 16j.
-  //                    BT: column n = tid & 63, k run 16 kg..16 kg+15.
-  const int kq = tid & 15, r16 = tid >> 4;
-  const int cn = tid & 63, kg = tid >> 6;
-
-  // ---- exponents: factor rows from setup, grid rows/columns over the whole k range
-  if (tid < T8) Fe[tid] = Fexp[min(fr0 + tid, frows - 1)];
-  if (!BT) {
-    double mx[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c = 0; c < nch; ++c) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const unsigned row = (unsigned)min(vr0 + r16 + 16 * j, vrows - 1);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const unsigned k = (unsigned)min(c * KC8 + 4 * kq + q, K - 1);
-          mx[j] = __builtin_fmax(mx[j], __builtin_fabs(V[row * (unsigned)ldv + k]));
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-#pragma unroll
-      for (int off = 8; off >= 1; off >>= 1) mx[j] = __builtin_fmax(mx[j], __shfl_xor(mx[j], off, 16));
-      if (kq == 0) Ve[r16 + 16 * j] = row_exponent(mx[j]);
-    }
-  } else {
-    double mx = 0.0;
-    const unsigned col = (unsigned)min(vr0 + cn, vrows - 1);
-    for (int c = 0; c < nch; ++c) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const unsigned k = (unsigned)min(c * KC8 + 16 * kg + i, K - 1);
-        mx = __builtin_fmax(mx, __builtin_fabs(V[k * (unsigned)ldv + col]));
-      }
-    }
-    red[kg][cn] = mx;
-    __syncthreads();
-    if (tid < T8)
-      Ve[tid] = row_exponent(__builtin_fmax(__builtin_fmax(red[0][tid], red[1][tid]),
-                                            __builtin_fmax(red[2][tid], red[3][tid])));
+  // exponents of the factor rows and the grid fibers of this tile (fibers past the end
+  // repeat the last one; their outputs are not stored)
+  if (tid < T8) {
+    Fe[tid] = Fexp[min(fr0 + tid, frows - 1)];
+    Ve[tid] = Vx[vfib0 + min(vr0 + tid, vrows - 1)];
   }
-  __syncthreads();
 
-  i4 acc[S][FI][FI];
+  // one 32 x 32 accumulator per digit level (v_mfma_i32_32x32x32_i8: the 32x32x32 form
+  // runs at about twice the int8 rate of the 16x16x64 form on this chip)
+  i16 acc[S];
 #pragma unroll
   for (int l = 0; l < S; ++l)
 #pragma unroll
-    for (int i = 0; i < FI; ++i)
-#pragma unroll
-      for (int j = 0; j < FI; ++j) acc[l][i][j] = i4{0, 0, 0, 0};
+    for (int j = 0; j < 16; ++j) acc[l][j] = 0;
 
   // factor digits: 64 rows x 64 bytes per plane, one 16-byte vector per thread
   const int frow = tid >> 2, fk = (tid & 3) * 16;
   const int64_t foff = (int64_t)min(fr0 + frow, frows - 1) * ldf + fk;
+  // grid digits, one 16-byte vector per thread: modes 2/3 fiber cn = tid & 63, k run
+  // kg = tid >> 6 of the chunk; mode 1 like the factor (fiber tid >> 2, k 16 (tid & 3))
+  const int cn = BT ? (tid & 63) : (tid >> 2);
+  const int vk = BT ? 16 * (tid >> 6) : 16 * (tid & 3);
+  const int64_t vfib = vfib0 + min(vr0 + cn, vrows - 1);
+  const int64_t voff = BT ? vfib * 16 + (int64_t)(vk >> 4) * (nfib * 16) : vfib * slice_ld(K) + vk;
+  const int64_t vstep = BT ? 4 * (nfib * 16) : KC8;   // per chunk
 
+  // chunk c's digits into registers (the next chunk's loads overlap this chunk's products)
+  i4 rf[S], rv[S];
+  auto load = [&](int c) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) rf[s] = *reinterpret_cast<const i4*>(F + s * fsl + foff + c * KC8);
+#pragma unroll
+    for (int s = 0; s < S; ++s) rv[s] = *reinterpret_cast<const i4*>(Vd + s * vplane + voff + c * vstep);
+  };
+  load(0);
   for (int c = 0; c < nch; ++c) {
-    const int k0 = c * KC8;
-    i4 rf[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) rf[s] = *reinterpret_cast<const i4*>(F + s * fsl + foff + k0);
-    double rv[16];
-    if (!BT) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const unsigned row = (unsigned)min(vr0 + r16 + 16 * j, vrows - 1);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const unsigned k = (unsigned)min(k0 + 4 * kq + q, K - 1);
-          rv[4 * j + q] = V[row * (unsigned)ldv + k];
-        }
-      }
-    } else {
-      const unsigned col = (unsigned)min(vr0 + cn, vrows - 1);
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const unsigned k = (unsigned)min(k0 + 16 * kg + i, K - 1);
-        rv[i] = V[k * (unsigned)ldv + col];
-      }
-    }
 #pragma unroll
     for (int s = 0; s < S; ++s) *reinterpret_cast<i4*>(&Fs[s][frow * PI8 + fk]) = rf[s];
-    // k >= K: clamped grid values meet zero factor digits, so no masking is needed
-    if (!BT) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int rloc = r16 + 16 * j;
-        unsigned pl[S];
-        slice4<S>(rv[4 * j + 0], rv[4 * j + 1], rv[4 * j + 2], rv[4 * j + 3], Ve[rloc], pl);
-#pragma unroll
-        for (int s = 0; s < S; ++s) *reinterpret_cast<unsigned*>(&Vs[s][rloc * PI8 + 4 * kq]) = pl[s];
-      }
-    } else {
-      const int e = Ve[cn];
-#pragma unroll
-      for (int qd = 0; qd < 4; ++qd) {
-        unsigned pl[S];
-        slice4<S>(rv[4 * qd + 0], rv[4 * qd + 1], rv[4 * qd + 2], rv[4 * qd + 3], e, pl);
-#pragma unroll
-        for (int s = 0; s < S; ++s) *reinterpret_cast<unsigned*>(&Vs[s][cn * PI8 + 16 * kg + 4 * qd]) = pl[s];
-      }
-    }
+    for (int s = 0; s < S; ++s) *reinterpret_cast<i4*>(&Vs[s][cn * PI8 + vk]) = rv[s];
     __syncthreads();
-    // A rows: grid (!BT) or factor (BT); B' rows: factor (!BT) or grid (BT)
-    i4 af[S][FI];
+    if (c + 1 < nch) load(c + 1);
+    // A rows: grid (!BT) or factor (BT); B' rows: factor (!BT) or grid (BT). Lane l
+    // supplies row l % 32 of its operand, k bytes 16 (l / 32) .. +15 of each 32-k step.
+    const int rl = lane & 31, kh = 16 * (lane >> 5);
 #pragma unroll
-    for (int s = 0; s < S; ++s)
+    for (int ks = 0; ks < KC8 / 32; ++ks) {
+      i4 af[S];
 #pragma unroll
-      for (int i = 0; i < FI; ++i)
-        af[s][i] = *reinterpret_cast<const i4*>(&(BT ? Fs : Vs)[s][(wm + 16 * i + lr) * PI8 + 16 * lg]);
+      for (int s = 0; s < S; ++s)
+        af[s] = *reinterpret_cast<const i4*>(&(BT ? Fs : Vs)[s][(wm + rl) * PI8 + 32 * ks + kh]);
 #pragma unroll
-    for (int sb = 0; sb < S; ++sb) {
-      i4 bfr[FI];
+      for (int sb = 0; sb < S; ++sb) {
+        const i4 bfr = *reinterpret_cast<const i4*>(&(BT ? Vs : Fs)[sb][(wn + rl) * PI8 + 32 * ks + kh]);
 #pragma unroll
-      for (int j = 0; j < FI; ++j)
-        bfr[j] = *reinterpret_cast<const i4*>(&(BT ? Vs : Fs)[sb][(wn + 16 * j + lr) * PI8 + 16 * lg]);
-#pragma unroll
-      for (int sa = 0; sa + sb < S; ++sa)
-#pragma unroll
-        for (int i = 0; i < FI; ++i)
-#pragma unroll
-          for (int j = 0; j < FI; ++j)
-            acc[sa + sb][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[sa][i], bfr[j], acc[sa + sb][i][j], 0, 0, 0);
+        for (int sa = 0; sa + sb < S; ++sa)
+          acc[sa + sb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[sa], bfr, acc[sa + sb], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
 
-  // 16x16 integer accumulator layout: lane l, element t holds row 4(l/16) + t, column l%16
+  // 32x32 integer accumulator layout: lane l, element j holds row 8(j/4) + 4(l/32) + j%4,
+  // column l%32
   const double alpha = p.alpha * (p.galpha[g] != 0.0 ? p.galpha[g] : 1.0), beta = p.beta;
 #pragma unroll
-  for (int i = 0; i < FI; ++i)
+  for (int j = 0; j < 16; ++j) {
+    const int ml = wm + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3), nl = wn + (lane & 31);
+    const int m = m0 + ml, n = n0 + nl;
+    if (m < M && n < N) {
+      double v = (double)acc[S - 1][j];
 #pragma unroll
-    for (int j = 0; j < FI; ++j)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int ml = wm + 16 * i + 4 * lg + t, nl = wn + 16 * j + lr;
-        const int m = m0 + ml, n = n0 + nl;
-        if (m < M && n < N) {
-          double v = (double)acc[S - 1][i][j][t];
-#pragma unroll
-          for (int l = S - 2; l >= 0; --l) v = __builtin_fma(v, 0x1p-8, (double)acc[l][i][j][t]);
-          const int e = (BT ? Fe[ml] + Ve[nl] : Ve[ml] + Fe[nl]) - 12;
-          double o = alpha * __builtin_ldexp(v, e);
-          if (Cadd) o += beta * Cadd[m * p.ldc + n];
-          C[m * p.ldc + n] = o;
-        }
-      }
+      for (int l = S - 2; l >= 0; --l) v = __builtin_fma(v, 0x1p-8, (double)acc[l][j]);
+      const int e = (BT ? Fe[ml] + Ve[nl] : Ve[ml] + Fe[nl]) - 12;
+      double o = alpha * __builtin_ldexp(v, e);
+      if (Cadd) o += beta * Cadd[m * p.ldc + n];
+      C[m * p.ldc + n] = o;
+    }
+  }
 }
 
 // Split `rows` rows of an FP64 matrix (row stride lds, k columns) into S digit planes of
@@ -327,17 +366,30 @@ hipError_t launch_slice_rows(signed char* dst, int* exps, const double* src, int
 hipError_t launch_gemm_sliced(GemmArgs& g, hipStream_t s) {
   // every level sum must stay an exact int32: S products of at most 2^14 per k
   if ((int64_t)g.K * g.slices * 16384 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  if (g.M < 1 || g.N < 1 || g.K < 1 || g.inner < 1 || g.groups < 1 || g.groups > kMaxGroups)
+    return hipErrorInvalidValue;
+  // the grid operand's digits and fiber exponents go to the caller's workspace
+  if (!g.vdig || !g.vexp || sliced_digit_bytes(g) > g.vdig_cap ||
+      (int64_t)g.groups * sliced_fibers(g) > g.vexp_cap)
+    return hipErrorInvalidValue;
   g.tiles_m = (g.M + T8 - 1) / T8;
   g.tiles_n = (g.N + T8 - 1) / T8;
   const int64_t total = (int64_t)g.tiles_m * g.tiles_n * g.inner * g.groups;
   if (total >= ((int64_t)1 << 28)) return hipErrorInvalidValue;
   g.total = (int)total;
   g.per_xcd = (g.total + 7) / 8;
-  const dim3 grid(8 * g.per_xcd), block(TH);
-#define MM_SLICED_CASE(SS)                                  \
-  case SS:                                                  \
-    if (g.b_trans) gemm_i8<1, SS><<<grid, block, 0, s>>>(g); \
-    else gemm_i8<0, SS><<<grid, block, 0, s>>>(g);           \
+  const int64_t fblocks = g.b_trans ? (int64_t)g.inner * ((g.N + T8 - 1) / T8) : ((int64_t)g.M + 3) / 4;
+  if (fblocks * g.groups >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const dim3 sgrid((unsigned)(fblocks * g.groups)), grid(8 * g.per_xcd), block(TH);
+#define MM_SLICED_CASE(SS)                                                \
+  case SS:                                                                \
+    if (g.b_trans) {                                                      \
+      slice_grid<1, SS><<<sgrid, block, 0, s>>>(g, (int)fblocks);         \
+      gemm_i8<1, SS><<<grid, block, 0, s>>>(g);                           \
+    } else {                                                              \
+      slice_grid<0, SS><<<sgrid, block, 0, s>>>(g, (int)fblocks);         \
+      gemm_i8<0, SS><<<grid, block, 0, s>>>(g);                           \
+    }                                                                     \
     break;
   switch (g.slices) {
     MM_SLICED_CASE(3)
