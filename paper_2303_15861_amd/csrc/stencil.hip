@@ -241,16 +241,17 @@ __global__ __launch_bounds__(64 * SW) void stencil_kernel(StencilArgs p, Stencil
     }
 }
 
-// Points per lane: with a segment width W = 64 P ceil(n1 / 64 P), the cost of a row is
-// taken as W / P (load instructions) + W / 4 (bytes); the P in {4, 2, 1} of least cost.
+// Points per lane: the P in {4, 2, 1} that pads n1 least to whole 64 P-point segments,
+// the larger P on ties. Measured per pass at n^3 (us, P = 1 / 2 / 4): n = 63: 5 / 7 / 8;
+// 191: 54 / 71 / 59; 255: 129-149 / 141-146 / 132-134; 383: 510 / 481 / 591 -- idle lanes
+// cost more than the extra instructions of narrower lanes.
 static int points_per_lane(int n1) {
   int best = 4;
-  double cost = 1e300;
-  for (int P : {4, 2, 1}) {
-    const double wdt = 64.0 * P * ((n1 + 64 * P - 1) / (64 * P));
-    const double c = wdt / P + wdt / 4;
-    if (c < cost) {
-      cost = c;
+  int64_t width = 256LL * ((n1 + 255) / 256);
+  for (int P : {2, 1}) {
+    const int64_t wdt = 64LL * P * ((n1 + 64 * P - 1) / (64 * P));
+    if (wdt < width) {
+      width = wdt;
       best = P;
     }
   }

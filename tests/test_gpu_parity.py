@@ -78,7 +78,15 @@ def test_factors_match_closed_form(mm, ctx, n, scheme, tau):
 
 
 # ------------------------------------------------------------------ stencil
-@pytest.mark.parametrize("n", [(1, 1), (5, 7), (63, 63), (1, 1, 1), (5, 6, 7), (70, 9, 33), (127, 127, 127)])
+# The kernel gives each lane P = 1, 2 or 4 consecutive x1 points (the P that pads n1 least
+# to 64 P-point segments) and splits longer rows into segments whose ends are loaded
+# separately: the cases cover every P, partly and exactly filled segments, and rows of
+# several segments for each P (129, 257, 300: P = 1; 383: P = 2; 511: P = 4).
+STENCIL_CASES = [(1, 1), (5, 7), (63, 63), (65, 9), (300, 7), (511, 5), (1, 1, 1), (5, 6, 7), (70, 9, 33),
+                 (127, 127, 127), (129, 5, 6), (256, 4, 3), (257, 3, 4), (383, 6, 5)]
+
+
+@pytest.mark.parametrize("n", STENCIL_CASES)
 def test_remainder_and_full_rhs(mm, ctx, n):
     p = synth.smooth_problem(n, 2, beta=(3.0, -2.0, 1.5)[: len(n)], lam=0.8,
                              beta_bar=(1.0, 0.5, -0.25)[: len(n)], r=(0.1, 0.7, -0.4, 0.2))
@@ -151,6 +159,8 @@ CASES = [
     ("erk2p1f", (19, 22, 17), 6, 2e-3),
     ("etd2rk", (40, 35), 10, 2e-3),
     ("l2b", (129, 130, 131), 3, 5e-4),
+    ("l2b", (300, 40), 5, 1e-4),        # two-segment stencil rows
+    ("etd2rk", (260, 9, 11), 3, 1e-4),
 ]
 
 
