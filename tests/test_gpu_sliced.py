@@ -59,8 +59,11 @@ def oracle_op(p):
     return expo.KronOperator(p.n, adr.extracted_amax(p.a), p.lam, p.beta_bar, p.tau)
 
 
-CASES = [((9, 13), 3), ((9, 13), 7), ((200, 130), 5), ((1, 1, 1), 4), ((5, 6, 7), 6), ((70, 65, 66), 3),
-         ((70, 65, 66), 4), ((70, 65, 66), 5), ((70, 65, 66), 6), ((70, 65, 66), 7), ((130, 129, 127), 6)]
+# (300, 270) and (20, 9, 290): contractions longer than 256 (the grid split's looped row
+# path and its two-pass column path)
+CASES = [((9, 13), 3), ((9, 13), 7), ((200, 130), 5), ((300, 270), 6), ((1, 1, 1), 4), ((5, 6, 7), 6),
+         ((70, 65, 66), 3), ((70, 65, 66), 4), ((70, 65, 66), 5), ((70, 65, 66), 6), ((70, 65, 66), 7),
+         ((130, 129, 127), 6), ((20, 9, 290), 7)]
 
 
 def flip_bar(S, emax):
@@ -103,10 +106,11 @@ def test_lawson_solve_matches_sliced_oracle(mm, ctx, scheme, n, steps, S):
     assert np.max(np.abs(got - ref)) <= flip_bar(S, emax) * amplification(p) * scale
 
 
-@pytest.mark.parametrize("scheme", ["etd2rk", "erk2p1f"])
-def test_erk_solve_within_slicing_bound(mm, ctx, scheme):
+# (22, 19, 70): the stacked last mode contracts (q + 1) 70 = 350 > 256 values per fiber
+@pytest.mark.parametrize("scheme,n", [("etd2rk", (22, 19, 17)), ("erk2p1f", (22, 19, 17)), ("etd2rk", (22, 19, 70))])
+def test_erk_solve_within_slicing_bound(mm, ctx, scheme, n):
     S = 6
-    p = synth.smooth_problem((22, 19, 17), 14, tau=1e-3, steps=8, scheme=scheme, beta=(2.0, 1.0, -1.0))
+    p = synth.smooth_problem(n, 14, tau=1e-3, steps=8, scheme=scheme, beta=(2.0, 1.0, -1.0))
     op = mm.setup_problem(ctx, p, prec=f"sliced{S}")
     u = dev(p.u0)
     mm.step(op, u, p.steps)
