@@ -62,10 +62,18 @@ class Problem:
     lam: float = 1.0
     beta_bar: Tuple[float, ...] = ()
     name: str = ""
+    # per axis: 0 = Dirichlet data at both ends, 1 = Dirichlet at x = 0 and homogeneous
+    # Neumann at x = 1 (then the n unknowns sit at i/n, i = 1..n, and the padded node
+    # n + 1 of ``a`` holds the mirror value a(x_{n-1}))
+    bc: Tuple[int, ...] = ()
+    # diffusion term: "flux" = div(a grad u), "nondiv" = a Lap u
+    form: str = "flux"
 
     def __post_init__(self):
         if not self.beta_bar:
             self.beta_bar = tuple(0.0 for _ in range(self.d))
+        if not self.bc:
+            self.bc = tuple(0 for _ in range(self.d))
 
     @property
     def dof(self) -> int:
@@ -203,6 +211,26 @@ def workload(name: str, seed: int = 0) -> Problem:
     if name == "3d_n383_etd2rk_exact":
         return anisotropic_problem(383, seed, tau=2e-3, steps=50, scheme="etd2rk", q=0, name=name)
     raise KeyError(name)
+
+
+def paper3d_problem(N: int, b: float, lam: float, *, scheme: str = "l2b", steps: int = 256, T: float = 0.25,
+                    name: str = "") -> Problem:
+    """The three-dimensional problem of Sec. 5.3, eq. (eq:adr3d), split as eq. (eq:adr3dstab):
+    u_t = a Lap u + b (d_1 + d_2 + d_3) u + u(1 + u^2) on (0,1)^3, Dirichlet data on the faces
+    x_mu = 0, homogeneous Neumann data on x_mu = 1, a = exp(-|x - 1/2|^2)/10,
+    u0 = (27/4)^3 prod x_mu (1 - x_mu)^2, N points per direction (x_i = i/N), the whole
+    advection in the extracted operator (beta_bar = beta)."""
+    h = 1.0 / N
+    x = h * np.arange(1, N + 1)
+    xa = h * np.arange(0, N + 2)
+    xa[N + 1] = xa[N - 1] if N >= 2 else 0.0        # mirror node beyond the Neumann face
+    g1 = np.exp(-(xa - 0.5) ** 2)
+    a = 0.1 * g1[:, None, None] * g1[None, :, None] * g1[None, None, :]
+    f = x * (1.0 - x) ** 2
+    u0 = (27.0 / 4.0) ** 3 * f[:, None, None] * f[None, :, None] * f[None, None, :]
+    return Problem(d=3, n=(N, N, N), a=a, u0=u0, beta=(b, b, b), r=(0.0, 1.0, 0.0, 1.0), tau=T / steps,
+                   steps=steps, scheme=scheme, lam=lam, beta_bar=(b, b, b), bc=(1, 1, 1), form="nondiv",
+                   name=name or f"paper3d_N{N}")
 
 
 WORKLOADS = ("2d_n63_le", "3d_n127_l2b", "3d_n127_etd2rk", "3d_n255_l2b", "3d_n383_etd2rk",
