@@ -39,6 +39,8 @@ DESCRIPTION = {
                             "200 steps",
     "3d_n383_etd2rk_exact": "3D Dirichlet ADR 383^3 interior, anisotropic a in (0.01, 2), ETD2RK with exact "
                             "phi1 (eigenbasis), tau=2e-3, 50 steps",
+    "3d_paper_n60_sl2": "the 3D ADR problem of Sec. 5.3 (a Lap u, Dirichlet at 0, Neumann at 1), N = 60, b = -0.01, "
+                        "SL2 with lambda = 0.53, 256 steps to T = 1/4",
 }
 HBM_PEAK = 8.0e12
 WORKLOAD = "3d_n255_l2b"
@@ -198,14 +200,17 @@ def serve_stream(mm, prec, count, max_active):
 
 
 def cpu_baseline(p, steps):
-    """The oracle, untuned, on the host cores: `steps` Lawson2b steps of the workload."""
+    """The oracle, untuned, on the host cores: `steps` steps of the workload's scheme."""
     cores = len(os.sched_getaffinity(0))
     try:
         from threadpoolctl import threadpool_limits
         ctxm = threadpool_limits(limits=cores)
     except Exception:  # pragma: no cover
         ctxm = None
-    from oracle import schemes as S
+    if any(getattr(p, "bc", ())) or getattr(p, "form", "flux") != "flux":
+        from oracle import adr3d as S          # Neumann axes or the non-divergence form
+    else:
+        from oracle import schemes as S
     t0 = time.perf_counter()
     S.solve(p, steps=steps)
     dt = time.perf_counter() - t0

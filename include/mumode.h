@@ -102,14 +102,29 @@ enum { MM_LAWSON = 0, MM_ERK = 1 };
 enum { MM_LAWSON_EULER = 0, MM_LAWSON2B = 1, MM_SLE = 2, MM_LAWSON2A = 3, MM_SL2 = 4 };
 enum { MM_ETD2RK = 0, MM_ERK2P1 = 1, MM_EE = 2, MM_ERK2P2 = 3 };
 
+/* Boundary data per axis (Sec. 5.3, eq. (eq:adr3d)): MM_BC_DIRICHLET is zero data at
+ * x = 0 and x = 1 (n unknowns at i/(n+1)); MM_BC_NEUMANN is zero data at x = 0 and a zero
+ * normal derivative at x = 1 (n unknowns at i/n, i = 1..n, the value beyond x = 1 taken as
+ * the mirror u_{n+1} = u_{n-1}, so the 1D operator's last row reads [.., 2, -2]/h^2 and
+ * its centred advection vanishes there). Diffusion form: MM_FORM_FLUX is div(a grad u)
+ * with face means of the nodal a (eq. (eq:nonlin)); MM_FORM_NONDIV is a Lap u, the form
+ * of eq. (eq:adr3d), which reads a at the unknowns only.                              */
+enum { MM_BC_DIRICHLET = 0, MM_BC_NEUMANN = 1 };
+enum { MM_FORM_FLUX = 0, MM_FORM_NONDIV = 1 };
+
 typedef struct {
   int d;                 /* 2 or 3                                                    */
-  int n[3];              /* interior points per axis, x1 first (n[2] ignored if d=2)  */
-  const double* a;       /* device, nodal diffusion coefficient incl. boundary        */
+  int n[3];              /* unknowns per axis, x1 first (n[2] ignored if d=2)         */
+  const double* a;       /* device, nodal diffusion coefficient on the padded nodes
+                            (n3+2)(n2+2)(n1+2): the unknowns plus one node per side;
+                            beyond a Neumann face the flux form reads the extra node,
+                            which should hold the mirror value a(x_{n-1})             */
   double beta[3];        /* constant velocity                                         */
   double r[4];           /* reaction coefficients r0..r3                              */
   double lambda;         /* extraction factor, eq. (eq:linop)                         */
   double beta_bar[3];    /* advection moved into A, eq. (eq:linop)                    */
+  int bc[3];             /* MM_BC_* per axis (zero: Dirichlet)                        */
+  int form;              /* MM_FORM_* (zero: flux form)                               */
 } mm_problem;
 
 typedef struct mm_ctx mm_ctx;
@@ -135,7 +150,8 @@ const char* mm_version(void);
  * the op then also stores R_mu and L_mu. slices: digit count of MM_SLICED (0 = 6,
  * else 3..7), ignored by the other precisions. `a` must be complete when the call is
  * made (the copy runs on the context's own stream, which does not wait for others).
- * Errors: MM_EINVAL (d, n < 1, tau <= 0 or not finite, unknown family/scheme/prec,
+ * Errors: MM_EINVAL (d, n < 1, tau <= 0 or not finite, unknown family/scheme/prec/bc/form,
+ * exact phi1 with a Neumann axis,
  * slices out of range, exact phi1 with another precision or complex eigenvalues,
  * a == NULL), MM_ENOMEM, MM_EDEVICE. */
 mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int family, int scheme,

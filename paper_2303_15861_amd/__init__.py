@@ -56,7 +56,14 @@ MM_KIND_STENCIL, MM_KIND_GEMM_K, MM_KIND_GEMM_N, MM_KIND_FUSED = 0, 1, 2, 3
 
 class MMProblem(Structure):
     _fields_ = [("d", c_int), ("n", c_int * 3), ("a", c_void_p), ("beta", c_double * 3),
-                ("r", c_double * 4), ("lam", c_double), ("beta_bar", c_double * 3)]
+                ("r", c_double * 4), ("lam", c_double), ("beta_bar", c_double * 3), ("bc", c_int * 3),
+                ("form", c_int)]
+
+
+# boundary data per axis and diffusion form (mumode.h)
+MM_BC_DIRICHLET, MM_BC_NEUMANN = 0, 1
+MM_FORM_FLUX, MM_FORM_NONDIV = 0, 1
+FORMS = {"flux": MM_FORM_FLUX, "nondiv": MM_FORM_NONDIV}
 
 
 class MMRequest(Structure):
@@ -251,7 +258,8 @@ class Operator:
 
 def mumode_setup(ctx: Context, d: int, n: Sequence[int], a, beta: Sequence[float], r: Sequence[float],
                  tau: float, scheme: str = "l2b", prec: str = "fp64", q: int = 4, lam: float = 1.0,
-                 beta_bar: Optional[Sequence[float]] = None) -> Operator:
+                 beta_bar: Optional[Sequence[float]] = None, bc: Optional[Sequence[int]] = None,
+                 form: str = "flux") -> Operator:
     """Build the extracted operator and its factors on the device (see mumode.h)."""
     prob = MMProblem()
     prob.d = d
@@ -259,6 +267,8 @@ def mumode_setup(ctx: Context, d: int, n: Sequence[int], a, beta: Sequence[float
         prob.n[i] = int(n[i]) if i < d else 1
         prob.beta[i] = float(beta[i]) if i < d else 0.0
         prob.beta_bar[i] = float(beta_bar[i]) if (beta_bar is not None and i < d) else 0.0
+        prob.bc[i] = int(bc[i]) if (bc is not None and i < d) else MM_BC_DIRICHLET
+    prob.form = FORMS[form]
     for i in range(4):
         prob.r[i] = float(r[i])
     prob.lam = float(lam)
@@ -319,7 +329,7 @@ def setup_problem(ctx: Context, prob, prec: str = "fp64", scheme: Optional[str] 
     torch = _torch()
     a = torch.from_numpy(prob.a).to(device=f"cuda:{ctx.device}")
     op = mumode_setup(ctx, prob.d, prob.n, a, prob.beta, prob.r, prob.tau, scheme or prob.scheme, prec,
-                      prob.q, prob.lam, prob.beta_bar)
+                      prob.q, prob.lam, prob.beta_bar, getattr(prob, "bc", None), getattr(prob, "form", "flux"))
     return op
 
 

@@ -123,12 +123,15 @@ mm_status newton_schulz_solve(mm_ctx* ctx, int n, const double* Q, double* P, do
 // Pade approximant with scaling and squaring (Higham, SIAM J. Matrix Anal. Appl. 26(4),
 // 2005): s = max(0, ceil(log2(||T||_1 / theta_13))), X = r_13(T/2^s), then s squarings.
 // The Pade numerator coefficients are b_j = (26 - j)! / (j! (13 - j)!).
-mm_status pade_expm(mm_ctx* ctx, int n, double sub, double diag, double sup, double* out, int* s_out,
+// neumann: the last row is [.., sub + sup, diag] (the mirror ghost of a zero normal
+// derivative at x = 1), which adds at most |sub + sup| to a column sum.
+mm_status pade_expm(mm_ctx* ctx, int n, double sub, double diag, double sup, bool neumann, double* out, int* s_out,
                     double* ws) {
   hipStream_t st = ctx->stream;
+  const double last_sub = (neumann && n >= 2) ? sub + sup : sub;
   double nrm = std::fabs(diag);
-  if (n == 2) nrm += std::fmax(std::fabs(sub), std::fabs(sup));
-  if (n >= 3) nrm += std::fabs(sub) + std::fabs(sup);
+  if (n == 2) nrm += std::fmax(std::fabs(last_sub), std::fabs(sup));
+  if (n >= 3) nrm += std::fabs(sub) + std::fabs(sup) + (neumann ? std::fabs(last_sub) : 0.0);
   const double theta13 = 5.371920351148152;
   int s = 0;
   if (nrm > theta13) s = (int)std::ceil(std::log2(nrm / theta13));
@@ -144,7 +147,7 @@ mm_status pade_expm(mm_ctx* ctx, int n, double sub, double diag, double sup, dou
   const int64_t nn = (int64_t)n * n;
   double *A = ws, *A2 = ws + nn, *A4 = ws + 2 * nn, *A6 = ws + 3 * nn, *T1 = ws + 4 * nn, *U = ws + 5 * nn,
          *V = ws + 6 * nn;
-  HIPCHK(ctx, launch_build_tridiag(A, n, sub * sc, diag * sc, sup * sc, st));
+  HIPCHK(ctx, launch_build_tridiag(A, n, sub * sc, diag * sc, sup * sc, last_sub * sc, st));
   HIPCHK(ctx, gemm_sq(n, A, A, A2, st));
   HIPCHK(ctx, gemm_sq(n, A2, A2, A4, st));
   HIPCHK(ctx, gemm_sq(n, A4, A2, A6, st));
@@ -475,6 +478,12 @@ hipError_t eig_scale(const mm_op* op, double* out, const double* a, double ca, i
                           op->n[0], op->n[1], op->d == 3 ? op->n[2] : 1, op->tau, s);
 }
 
+// mesh width of axis mu: n unknowns at i/(n+1) (Dirichlet data at both ends) or at i/n
+// (zero normal derivative at x = 1)
+double mesh_h(const mm_op* op, int mu) {
+  return op->bc[mu] == MM_BC_NEUMANN ? 1.0 / op->n[mu] : 1.0 / (op->n[mu] + 1);
+}
+
 StencilArgs stencil_args(const mm_op* op, const double* u, bool full) {
   StencilArgs a{};
   a.u = u;
@@ -483,8 +492,9 @@ StencilArgs stencil_args(const mm_op* op, const double* u, bool full) {
   a.n2 = op->n[1];
   a.n3 = (op->d == 3) ? op->n[2] : 1;
   for (int mu = 0; mu < 3; ++mu) {
-    const double h = 1.0 / (op->n[mu] + 1);
+    const double h = mesh_h(op, mu);
     a.ih2[mu] = 1.0 / (h * h);
+    a.neu[mu] = (mu < op->d) && op->bc[mu] == MM_BC_NEUMANN;
     const double b = full ? op->beta[mu] : op->beta[mu] - op->beta_bar[mu];
     a.cadv[mu] = (mu < op->d) ? b / (2.0 * h) : 0.0;
   }
@@ -496,6 +506,7 @@ StencilArgs stencil_args(const mm_op* op, const double* u, bool full) {
   a.c0 = 1.0;
   a.c1 = 1.0;
   a.flag = op->flag;
+  a.nondiv = op->form == MM_FORM_NONDIV;
   return a;
 }
 
@@ -657,6 +668,15 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     set_err(ctx, "null diffusion coefficient");
     return MM_EINVAL;
   }
+  for (int mu = 0; mu < prob->d; ++mu)
+    if (prob->bc[mu] != MM_BC_DIRICHLET && prob->bc[mu] != MM_BC_NEUMANN) {
+      set_err(ctx, "bc[%d] = %d is not a boundary type", mu, prob->bc[mu]);
+      return MM_EINVAL;
+    }
+  if (prob->form != MM_FORM_FLUX && prob->form != MM_FORM_NONDIV) {
+    set_err(ctx, "form = %d is not a diffusion form", prob->form);
+    return MM_EINVAL;
+  }
   if (family != MM_LAWSON && family != MM_ERK) {
     set_err(ctx, "unknown family %d", family);
     return MM_EINVAL;
@@ -681,6 +701,12 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     set_err(ctx, "exact phi1 (quad_nodes = 0) is FP64 only");
     return MM_EINVAL;
   }
+  if (family == MM_ERK && quad_nodes == 0)
+    for (int mu = 0; mu < prob->d; ++mu)
+      if (prob->bc[mu] != MM_BC_DIRICHLET) {
+        set_err(ctx, "exact phi1 (quad_nodes = 0) needs Dirichlet data on every axis (closed-form eigenbasis)");
+        return MM_EINVAL;
+      }
   if (prec < MM_FP64 || prec > MM_SLICED) {
     set_err(ctx, "unknown precision %d", prec);
     return MM_EINVAL;
@@ -714,7 +740,9 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     op->n[mu] = (mu < prob->d) ? prob->n[mu] : 1;
     op->beta[mu] = (mu < prob->d) ? prob->beta[mu] : 0.0;
     op->beta_bar[mu] = (mu < prob->d) ? prob->beta_bar[mu] : 0.0;
+    op->bc[mu] = (mu < prob->d) ? prob->bc[mu] : MM_BC_DIRICHLET;
   }
+  op->form = prob->form;
   for (int i = 0; i < 4; ++i) op->r[i] = prob->r[i];
   op->lam = prob->lambda;
   op->tau = tau;
@@ -789,7 +817,7 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
   for (int mu = 0; mu < op->d; ++mu) {
     int same = -1;
     for (int nu = 0; nu < mu; ++nu)
-      if (op->n[nu] == op->n[mu] && op->beta_bar[nu] == op->beta_bar[mu]) same = nu;
+      if (op->n[nu] == op->n[mu] && op->beta_bar[nu] == op->beta_bar[mu] && op->bc[nu] == op->bc[mu]) same = nu;
     if (same >= 0) {
       op->fac[mu] = op->fac[same];
       op->squarings[mu] = op->squarings[same];
@@ -801,13 +829,13 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
       return fail(rc);
     }
     op->fac_owned[mu] = true;
-    const double h = 1.0 / (n + 1);
+    const double h = mesh_h(op, mu);
     const double diff = op->lam * op->a_max / (h * h);
     const double adv = op->beta_bar[mu] / (2.0 * h);
     for (int j = 0; j < nf; ++j) {
       const double ct = cs[j] * tau;
       int sq = 0;
-      rc = pade_expm(ctx, n, ct * (diff - adv), ct * (-2.0 * diff), ct * (diff + adv),
+      rc = pade_expm(ctx, n, ct * (diff - adv), ct * (-2.0 * diff), ct * (diff + adv), op->bc[mu] == MM_BC_NEUMANN,
                      op->fac[mu] + (int64_t)j * n * n, &sq, ws);
       if (rc != MM_OK) {
         hipFreeAsync(ws, st);
@@ -1075,7 +1103,9 @@ mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hi
   double* b0 = op->buf[0];
   double* b1 = op->buf[1];
   const bool mixed = lowp(op);
+  // (the one-workgroup solver implements the flux form with Dirichlet data only)
   if (ctx->small_fused && op->prec == MM_FP64 && small2d_fits(op->d, op->n[0], op->n[1]) &&
+      op->form == MM_FORM_FLUX && op->bc[0] == MM_BC_DIRICHLET && op->bc[1] == MM_BC_DIRICHLET &&
       (op->scheme == MM_LAWSON_EULER || op->scheme == MM_LAWSON2B)) {
     // the whole time loop in one workgroup
     if (nsteps == 0) return MM_OK;

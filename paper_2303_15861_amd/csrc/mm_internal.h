@@ -83,6 +83,8 @@ struct StencilArgs {
   double* out1;         // nullable: out1 = base1 + c1 * s
   float* out1f;         // if set, out1 is written here as float instead
   int* flag;            // nullable: set to 1 if out0 is not finite
+  int neu[3];           // per axis: zero normal derivative at x = 1 (mirror ghost)
+  int nondiv;           // diffusion a Lap u instead of div(a grad u)
 };
 
 // Whole small 2D Lawson solves in one workgroup (n1, n2 <= 64, FP64).
@@ -113,7 +115,9 @@ hipError_t launch_slice_rows(signed char* dst, int* exps, const double* src, int
 hipError_t launch_stencil(int d, const StencilArgs& a, hipStream_t s);
 hipError_t launch_max_reduce(const double* x, int64_t n, double* partial, int nparts, double* out,
                              hipStream_t s);
-hipError_t launch_build_tridiag(double* M, int n, double sub, double diag, double sup, hipStream_t s);
+// last_sub: the entry (n-1, n-2) (sub for a Toeplitz matrix)
+hipError_t launch_build_tridiag(double* M, int n, double sub, double diag, double sup, double last_sub,
+                                hipStream_t s);
 // out = c0*X0 + c1*X1 + c2*X2 + c3*X3 + cI*I (any X may be null); n x n
 hipError_t launch_combo(double* out, int n, double c0, const double* X0, double c1, const double* X1,
                         double c2, const double* X2, double c3, const double* X3, double cI,
@@ -177,6 +181,8 @@ struct mm_op {
   double beta[3] = {0, 0, 0}, beta_bar[3] = {0, 0, 0}, r[4] = {0, 0, 0, 0};
   int family = 0, scheme = 0, q = 0, prec = 0;
   int slices = 0;                      // MM_SLICED digit count
+  int bc[3] = {0, 0, 0};               // MM_BC_* per axis
+  int form = 0;                        // MM_FORM_*
   bool exact = false;                  // MM_ERK with exact phi1 through the eigenbasis
   int nfac = 1;                        // factors stored per axis
   double* ev[3] = {nullptr, nullptr, nullptr};   // exact: 1D eigenvalues per axis

@@ -5,6 +5,10 @@
 //     + sum_mu (beta_mu - beta_bar_mu)(u+ - u-)/(2 h_mu) + r0 + r1 u + r2 u^2 + r3 u^3,
 // abar = mean of the two nodal coefficients at a face, zero Dirichlet ghosts. With
 // lam_amax = 0 and the full velocity the same kernel yields F(u) (Appendix, u' = F(u)).
+// Sec. 5.3, eq. (eq:adr3d): the diffusion may instead be in non-divergence form,
+// (a - lam a_max) Lap_h u, and an axis may carry a zero normal derivative at x = 1,
+// whose ghost beyond the last unknown is the mirror value: at that unknown the + and -
+// neighbours along the axis are equal (u_{n+1} = u_{n-1}), so no extra loads.
 // The stage updates of the schemes are fused as out0 = base0 + c0 (g - sub) and
 // out1 = base1 + c1 (g - sub), so each remainder evaluation is one pass over HBM.
 #include <cfloat>
@@ -174,21 +178,39 @@ __global__ __launch_bounds__(64 * SW) void stencil_kernel(StencilArgs p, Stencil
       }
       if (!live_row || ucnt <= 0) continue;
       const int64_t idx = x + urow;
+      // last unknown of an axis with a zero normal derivative at x = 1: mirror ghost
+      const bool my = p.neu[1] && i2 == n2 - 1;
+      const bool mz = (D == 3) && p.neu[2] && i3 == n3 - 1;
       double g[P];
 #pragma unroll
       for (int k = 0; k < P; ++k) {
         const double u0 = uc[k], a0 = ac[k];
-        const double uxm = (k == 0) ? ul : uc[k - 1], uxp = (k == P - 1) ? ur : uc[k + 1];
-        const double axm = (k == 0) ? al : ac[k - 1], axp = (k == P - 1) ? ar : ac[k + 1];
-        double v = ((0.5 * (a0 + axp) - la) * (uxp - u0) - (0.5 * (a0 + axm) - la) * (u0 - uxm)) * p.ih2[0] +
-                   p.cadv[0] * (uxp - uxm);
-        v += ((0.5 * (a0 + aa[y + 1][z][k]) - la) * (uu[y + 1][z][k] - u0) -
-              (0.5 * (a0 + aa[y - 1][z][k]) - la) * (u0 - uu[y - 1][z][k])) * p.ih2[1] +
-             p.cadv[1] * (uu[y + 1][z][k] - uu[y - 1][z][k]);
-        if constexpr (D == 3)
-          v += ((0.5 * (a0 + aa[y][z + 1][k]) - la) * (uu[y][z + 1][k] - u0) -
-                (0.5 * (a0 + aa[y][z - 1][k]) - la) * (u0 - uu[y][z - 1][k])) * p.ih2[2] +
-               p.cadv[2] * (uu[y][z + 1][k] - uu[y][z - 1][k]);
+        const double uxm = (k == 0) ? ul : uc[k - 1];
+        const double uxp = (p.neu[0] && x + k == n1 - 1) ? uxm : (k == P - 1) ? ur : uc[k + 1];
+        const double uym = uu[y - 1][z][k], uyp = my ? uym : uu[y + 1][z][k];
+        double v;
+        if (p.nondiv) {
+          const double c = a0 - la;
+          v = c * (uxp - 2.0 * u0 + uxm) * p.ih2[0] + p.cadv[0] * (uxp - uxm);
+          v += c * (uyp - 2.0 * u0 + uym) * p.ih2[1] + p.cadv[1] * (uyp - uym);
+          if constexpr (D == 3) {
+            const double uzm = uu[y][z - 1][k], uzp = mz ? uzm : uu[y][z + 1][k];
+            v += c * (uzp - 2.0 * u0 + uzm) * p.ih2[2] + p.cadv[2] * (uzp - uzm);
+          }
+        } else {
+          const double axm = (k == 0) ? al : ac[k - 1], axp = (k == P - 1) ? ar : ac[k + 1];
+          v = ((0.5 * (a0 + axp) - la) * (uxp - u0) - (0.5 * (a0 + axm) - la) * (u0 - uxm)) * p.ih2[0] +
+              p.cadv[0] * (uxp - uxm);
+          v += ((0.5 * (a0 + aa[y + 1][z][k]) - la) * (uyp - u0) - (0.5 * (a0 + aa[y - 1][z][k]) - la) * (u0 - uym)) *
+                   p.ih2[1] +
+               p.cadv[1] * (uyp - uym);
+          if constexpr (D == 3) {
+            const double uzm = uu[y][z - 1][k], uzp = mz ? uzm : uu[y][z + 1][k];
+            v += ((0.5 * (a0 + aa[y][z + 1][k]) - la) * (uzp - u0) - (0.5 * (a0 + aa[y][z - 1][k]) - la) * (u0 - uzm)) *
+                     p.ih2[2] +
+                 p.cadv[2] * (uzp - uzm);
+          }
+        }
         v += p.r0 + u0 * (p.r1 + u0 * (p.r2 + u0 * p.r3));
         g[k] = v;
       }
@@ -309,16 +331,17 @@ hipError_t launch_max_reduce(const double* x, int64_t n, double* partial, int np
 }
 
 // ---------------------------------------------------------------- dense helpers
-__global__ void build_tridiag(double* M, int n, double sub, double diag, double sup) {
+__global__ void build_tridiag(double* M, int n, double sub, double diag, double sup, double last_sub) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)n * n) return;
   const int r = (int)(e / n), c = (int)(e % n);
-  M[e] = (c == r) ? diag : (c == r - 1) ? sub : (c == r + 1) ? sup : 0.0;
+  M[e] = (c == r) ? diag : (c == r - 1) ? (r == n - 1 ? last_sub : sub) : (c == r + 1) ? sup : 0.0;
 }
 
-hipError_t launch_build_tridiag(double* M, int n, double sub, double diag, double sup, hipStream_t s) {
+hipError_t launch_build_tridiag(double* M, int n, double sub, double diag, double sup, double last_sub,
+                                hipStream_t s) {
   const int64_t cnt = (int64_t)n * n;
-  build_tridiag<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(M, n, sub, diag, sup);
+  build_tridiag<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(M, n, sub, diag, sup, last_sub);
   return hipGetLastError();
 }
 

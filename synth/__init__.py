@@ -210,6 +210,10 @@ def workload(name: str, seed: int = 0) -> Problem:
                               tau=5e-4, steps=200, scheme="etd2rk", q=0, name=name)
     if name == "3d_n383_etd2rk_exact":
         return anisotropic_problem(383, seed, tau=2e-3, steps=50, scheme="etd2rk", q=0, name=name)
+    # the paper's own 3D problem at the size of its timing runs (Sec. 5.3: N = 60, b = -0.01,
+    # SL2 with the lambda of Table tab:adr3d_lambdaopt, m = 2^8 steps to T = 1/4)
+    if name == "3d_paper_n60_sl2":
+        return paper3d_problem(60, -0.01, 0.53, scheme="sl2", steps=256, name=name)
     raise KeyError(name)
 
 
@@ -234,7 +238,7 @@ def paper3d_problem(N: int, b: float, lam: float, *, scheme: str = "l2b", steps:
 
 
 WORKLOADS = ("2d_n63_le", "3d_n127_l2b", "3d_n127_etd2rk", "3d_n255_l2b", "3d_n383_etd2rk",
-             "3d_n127_etd2rk_exact", "3d_n383_etd2rk_exact")
+             "3d_n127_etd2rk_exact", "3d_n383_etd2rk_exact", "3d_paper_n60_sl2")
 
 
 # --------------------------------------------------------------------------
