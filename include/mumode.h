@@ -258,6 +258,8 @@ typedef struct {
   int steps;
   int prec;              /* mm_prec                                                   */
   int slices;            /* digit count for MM_SLICED (0 = 6)                          */
+  int bc[3];             /* MM_BC_* per axis (zero: Dirichlet), as in mm_problem      */
+  int form;              /* MM_FORM_* (zero: flux form)                               */
 } mm_request;
 
 typedef struct {

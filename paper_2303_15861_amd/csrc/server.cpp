@@ -162,6 +162,8 @@ struct mm_server {
       p.beta_bar[i] = r.beta_bar[i];
     }
     for (int i = 0; i < 4; ++i) p.r[i] = r.r[i];
+    for (int i = 0; i < 3; ++i) p.bc[i] = r.bc[i];
+    p.form = r.form;
     p.lambda = r.lambda;
     p.a = da;
     // mumode_setup ends with a synchronisation of actx's stream: a, u and the op are
@@ -365,15 +367,20 @@ mm_status solve_submit(mm_server* s, const mm_request* r, uint64_t* id) {
       r->prec < MM_FP64 || r->prec > MM_SLICED ||
       (r->prec == MM_SLICED && r->slices != 0 && (r->slices < mm::kMinSlices || r->slices > mm::kMaxSlices)))
     return MM_EINVAL;
+  if (r->form != MM_FORM_FLUX && r->form != MM_FORM_NONDIV) return MM_EINVAL;
   int64_t dof = 1, na = 1;
   for (int mu = 0; mu < r->d; ++mu) {
     if (r->n[mu] < 1 || r->n[mu] > 4096) return MM_EINVAL;
+    if (r->bc[mu] != MM_BC_DIRICHLET && r->bc[mu] != MM_BC_NEUMANN) return MM_EINVAL;
     dof *= r->n[mu];
     na *= r->n[mu] + 2;
   }
   auto j = std::make_unique<Job>();
   j->req = *r;
-  for (int mu = r->d; mu < 3; ++mu) j->req.n[mu] = 1;
+  for (int mu = r->d; mu < 3; ++mu) {
+    j->req.n[mu] = 1;
+    j->req.bc[mu] = MM_BC_DIRICHLET;
+  }
   j->a.assign(r->a, r->a + na);
   j->u0.assign(r->u0, r->u0 + dof);
   j->req.a = nullptr;

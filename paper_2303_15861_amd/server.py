@@ -37,7 +37,7 @@ class Server:
 
 def solve_submit(srv: Server, prob, prec: str = "fp64") -> Tuple[int, int]:
     """Queue a Lawson2b solve of a ``synth.Problem``; returns (status, id)."""
-    from . import MMRequest, prec_code
+    from . import FORMS, MMRequest, prec_code
     req = MMRequest()
     req.d = prob.d
     a = np.ascontiguousarray(prob.a, dtype=np.float64)
@@ -46,6 +46,8 @@ def solve_submit(srv: Server, prob, prec: str = "fp64") -> Tuple[int, int]:
         req.n[i] = int(prob.n[i]) if i < prob.d else 1
         req.beta[i] = float(prob.beta[i]) if i < prob.d else 0.0
         req.beta_bar[i] = float(prob.beta_bar[i]) if i < prob.d else 0.0
+        req.bc[i] = int(prob.bc[i]) if (i < prob.d and getattr(prob, "bc", ())) else 0
+    req.form = FORMS[getattr(prob, "form", "flux")]
     for i in range(4):
         req.r[i] = float(prob.r[i])
     req.lam = float(prob.lam)

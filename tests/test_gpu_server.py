@@ -123,3 +123,26 @@ def test_mixed_precision_requests(mm, prec):
         srv.close()
     assert st == mm.MM_OK
     assert relerr(u, S.solve(p)) <= (1e-4 if prec == "fp32" else 1e-3)
+
+
+def test_neumann_requests_next_to_dirichlet_ones(mm):
+    """Requests carry the boundary type and diffusion form: the problem of Sec. 5.3
+    (Lawson2b, lambda = 1) served next to an all-Dirichlet flux-form request, each
+    against its oracle."""
+    from oracle import adr3d
+    paper = synth.paper3d_problem(16, -1.0, 1.0, scheme="l2b", steps=64)
+    plain = synth.smooth_problem((20, 18, 16), 51, tau=1e-3, steps=15)
+    srv = mm.Server(0, max_active=4)
+    try:
+        ia = mm.solve_submit(srv, paper)[1]
+        ib = mm.solve_submit(srv, plain)[1]
+        sa, ua, _ = wait(mm, srv, ia, paper.shape)
+        sb, ub, _ = wait(mm, srv, ib, plain.shape)
+        bad = synth.paper3d_problem(8, -1.0, 1.0, scheme="l2b", steps=4)
+        bad.bc = (1, 2, 1)
+        assert mm.solve_submit(srv, bad)[0] == mm.MM_EINVAL
+    finally:
+        srv.close()
+    assert sa == mm.MM_OK and sb == mm.MM_OK
+    assert relerr(ua, adr3d.solve(paper)) <= 1e-12
+    assert relerr(ub, S.solve(plain)) <= 1e-12
