@@ -17,8 +17,9 @@
 // planes with per-row exponents (rows zero-padded to a multiple of 64 in k). The grid
 // operand is split once per launch by slice_grid, a streaming pass that finds the
 // exponent of every grid fiber (a row of the operand in mode 1, a column in modes 2/3,
-// over the whole k range) and writes its digit planes with 16 consecutive k of one fiber
-// per 16-byte vector. The product kernel then stages both operands into LDS with
+// over the whole k range) and writes its digit planes (k-contiguous rows in mode 1, runs
+// of 16 k of adjacent fibers in modes 2/3). The product kernel then stages both operands
+// into LDS with
 // 16-byte loads only (splitting inside the product kernel would repeat the work once
 // per 64-row output tile). Workgroup tile 64 x 64, four waves of 32 x 32, one
 // accumulator per digit level.
@@ -284,20 +285,29 @@ __global__ __launch_bounds__(TH, 2) void gemm_i8(GemmArgs p) {
     if (c + 1 < nch) load(c + 1);
     // A rows: grid (!BT) or factor (BT); B' rows: factor (!BT) or grid (BT). Lane l
     // supplies row l % 32 of its operand, k bytes 16 (l / 32) .. +15 of each 32-k step.
+    // All 2S fragments of a 32-k step are read before its products, so one LDS wait
+    // covers the step; the S(S+1)/2 products then go round-robin over the levels (round r
+    // takes digit sa = r of A against sb = l - r for every level l >= r), so consecutive
+    // MFMAs update different accumulators; odd steps run the levels upwards so that the
+    // step boundary does not chain two updates of one level. Integer sums: the order does
+    // not change the result.
     const int rl = lane & 31, kh = 16 * (lane >> 5);
 #pragma unroll
     for (int ks = 0; ks < KC8 / 32; ++ks) {
-      i4 af[S];
+      i4 af[S], bf[S];
 #pragma unroll
       for (int s = 0; s < S; ++s)
         af[s] = *reinterpret_cast<const i4*>(&(BT ? Fs : Vs)[s][(wm + rl) * PI8 + 32 * ks + kh]);
 #pragma unroll
-      for (int sb = 0; sb < S; ++sb) {
-        const i4 bfr = *reinterpret_cast<const i4*>(&(BT ? Vs : Fs)[sb][(wn + rl) * PI8 + 32 * ks + kh]);
+      for (int s = 0; s < S; ++s)
+        bf[s] = *reinterpret_cast<const i4*>(&(BT ? Vs : Fs)[s][(wn + rl) * PI8 + 32 * ks + kh]);
 #pragma unroll
-        for (int sa = 0; sa + sb < S; ++sa)
-          acc[sa + sb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[sa], bfr, acc[sa + sb], 0, 0, 0);
-      }
+      for (int r = 0; r < S; ++r)
+#pragma unroll
+        for (int i = 0; i < S - r; ++i) {
+          const int l = (ks & 1) ? r + i : S - 1 - i;   // level of this product
+          acc[l] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[r], bf[l - r], acc[l], 0, 0, 0);
+        }
     }
     __syncthreads();
   }
