@@ -248,3 +248,25 @@ def test_lambda_scan_defaults(mm, ctx):
                                    ref_steps=512)
     assert lams[0] == STABILITY_BOUND["sle"] and lams[-1] == 1.0 and len(errs) == 5
     assert np.all(np.isfinite(errs)) and best in lams and np.min(errs) < 1e-2
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "sliced6"])
+def test_mixed_precision_actions_with_neumann_factors(mm, ctx, prec):
+    """The low-precision copies of the Neumann factors (N = 60 paper problem, b = -1):
+    the action of u0 within the bars of the Dirichlet case (tests/test_gpu_mixed.py and
+    tests/test_gpu_sliced.py; the factors are entrywise nonnegative with row sums <= 1)."""
+    p = synth.paper3d_problem(60, -1.0, 0.57, scheme="sl2", steps=256)
+    op = mm.setup_problem(ctx, p, prec=prec)
+    out = dev(np.zeros(p.shape))
+    mm.mumode_expv(op, dev(p.u0), out)
+    got = host(out)
+    op.close()
+    be = adr3d.Backend(p)
+    ref = be.expv(1.0, p.u0)
+    u24 = 2.0 ** -24
+    if prec == "sliced6":
+        emax = max(float(np.max(np.abs(E))) for E in be.factors(1.0))
+        bar = 3 * 2.0 ** (-48) * 16 * 6 * 60 * emax + 1e-13
+    else:
+        bar = 3 * (2 * (u24 if prec == "fp32" else 2.0 ** -16) + 16 * u24)
+    assert relerr(got, ref) <= bar
