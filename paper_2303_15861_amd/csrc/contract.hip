@@ -79,12 +79,22 @@ constexpr int P64 = KC4 + 2;   // [row][k] pitch in doubles (144 B: 16-byte alig
 template <int T>
 constexpr int occupancy() { return T == 128 ? 2 : 4; }
 
+// FP64 workgroups: 128-tiles run eight waves (4 x 2 waves of 32 x 64), so that two
+// workgroups per compute unit put four waves on every SIMD (more waves to cover the
+// per-chunk barrier and load waits than four waves of 64 x 64 at two per SIMD; the
+// accumulation order per output is the same); 64-tiles run four waves of 32 x 32.
+template <int T>
+constexpr int f64_waves() { return T == 128 ? 8 : 4; }
+
 template <int BT, int T>
-__global__ __launch_bounds__(THREADS, occupancy<T>()) void gemm_f64(GemmArgs p) {
-  constexpr int FI = T / 32;          // 16 x 16 fragments per wave and dimension
-  constexpr int NL = T / 16;          // tile elements per thread and operand per chunk
+__global__ __launch_bounds__(64 * f64_waves<T>(), 4) void gemm_f64(GemmArgs p) {
+  constexpr int NT = 64 * f64_waves<T>();       // threads
+  constexpr int WM = T / (f64_waves<T>() / 2);  // wave tile: WM x T/2
+  constexpr int FIM = WM / 16, FIN = T / 32;    // 16 x 16 fragments per wave
+  constexpr int NL = T * KC4 / NT;    // tile elements per thread and operand per chunk
+  constexpr int RS = NT / 16;         // rows of a [row][k] tile covered by one pass
   constexpr int PKN = T + 4;
-  constexpr int KR = THREADS / T;     // k rows of the [k][n] tile covered by one pass
+  constexpr int KR = NT / T;          // k rows of the [k][n] tile covered by one pass
   const int L = blockIdx.x;
   const int P = (L & 7) * p.per_xcd + (L >> 3);
   if (P >= p.total) return;
@@ -99,17 +109,17 @@ __global__ __launch_bounds__(THREADS, occupancy<T>()) void gemm_f64(GemmArgs p) 
   __shared__ __attribute__((aligned(16))) double As[2][T * P64];
   __shared__ __attribute__((aligned(16))) double Bs[2][BSZ];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * (T / 2), wn = (wave & 1) * (T / 2);
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * (T / 2);
   const int lg = lane >> 4, lr = lane & 15;
   const int M = p.M, N = p.N, K = p.K, lda = p.lda, ldb = p.ldb;
 
-  d4 acc[FI][FI];
+  d4 acc[FIM][FIN];
 #pragma unroll
-  for (int i = 0; i < FI; ++i)
+  for (int i = 0; i < FIM; ++i)
 #pragma unroll
-    for (int j = 0; j < FI; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FIN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  // element e = i*256 + tid of a tile: A and B' read along k: row = e/16 = 16i + tid/16,
+  // element e = i*NT + tid of a tile: A and B' read along k: row = e/16 = RS*i + tid/16,
   // k = tid%16;  B' read along n: k = e/T = KR*i + tid/T, n = tid%T
   const int r16 = tid >> 4, k16 = tid & 15;
   const int nB = min(n0 + (tid % T), N - 1), kB = tid / T;
@@ -120,9 +130,9 @@ __global__ __launch_bounds__(THREADS, occupancy<T>()) void gemm_f64(GemmArgs p) 
   auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-      const unsigned arow = (unsigned)min(m0 + 16 * i + r16, M - 1);
+      const unsigned arow = (unsigned)min(m0 + RS * i + r16, M - 1);
       const int kb = BT ? KR * i + kB : k16;
-      const unsigned brow = (unsigned)(BT ? nB : min(n0 + 16 * i + r16, N - 1));
+      const unsigned brow = (unsigned)(BT ? nB : min(n0 + RS * i + r16, N - 1));
       const unsigned ka = (unsigned)min(k0 + k16, K - 1), kbb = (unsigned)min(k0 + kb, K - 1);
       ra[i] = A[arow * (unsigned)lda + ka];
       rb[i] = BT ? B[kbb * (unsigned)ldb + brow] : B[brow * (unsigned)ldb + kbb];
@@ -131,7 +141,7 @@ __global__ __launch_bounds__(THREADS, occupancy<T>()) void gemm_f64(GemmArgs p) 
   auto store = [&](double* as, double* bs, int k0) {
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
-      const int e = i * THREADS + tid;
+      const int e = i * NT + tid;
       const int kb = BT ? KR * i + kB : k16;
       as[(e >> 4) * P64 + (e & 15)] = (k0 + k16 < K) ? ra[i] : 0.0;
       const double y = (k0 + kb < K) ? rb[i] : 0.0;
@@ -152,10 +162,12 @@ __global__ __launch_bounds__(THREADS, occupancy<T>()) void gemm_f64(GemmArgs p) 
     const double* bs = Bs[cur];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {   // k = 4g + 2h + {0, 1}
-      d2 af[FI], bf[FI];
+      d2 af[FIM], bf[FIN];
 #pragma unroll
-      for (int i = 0; i < FI; ++i) {
+      for (int i = 0; i < FIM; ++i)
         af[i] = *reinterpret_cast<const d2*>(as + (wm + 16 * i + lr) * P64 + 4 * lg + 2 * h);
+#pragma unroll
+      for (int i = 0; i < FIN; ++i) {
         if (BT) {
           const double* q = bs + (4 * lg + 2 * h) * PKN + wn + 16 * i + lr;
           bf[i] = d2{q[0], q[PKN]};
@@ -166,9 +178,9 @@ __global__ __launch_bounds__(THREADS, occupancy<T>()) void gemm_f64(GemmArgs p) 
 #pragma unroll
       for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int i = 0; i < FI; ++i)
+        for (int i = 0; i < FIM; ++i)
 #pragma unroll
-          for (int j = 0; j < FI; ++j)
+          for (int j = 0; j < FIN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
     }
     if (c + 1 < nch) store(As[cur ^ 1], Bs[cur ^ 1], (c + 1) * KC4);
@@ -177,9 +189,9 @@ __global__ __launch_bounds__(THREADS, occupancy<T>()) void gemm_f64(GemmArgs p) 
   // f64 16x16 layout: lane l, element t holds row 4t + l/16, column l%16
   const double alpha = p.alpha, beta = p.beta;
 #pragma unroll
-  for (int i = 0; i < FI; ++i)
+  for (int i = 0; i < FIM; ++i)
 #pragma unroll
-    for (int j = 0; j < FI; ++j)
+    for (int j = 0; j < FIN; ++j)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int m = m0 + wm + 16 * i + 4 * t + lg;
@@ -550,8 +562,9 @@ hipError_t launch_tile(int prec, GemmArgs& g, hipStream_t s) {
   const dim3 grid(8 * g.per_xcd), block(THREADS);
   if (prec == MM_FP64) {
     if (g.in_f32 || g.out_f32) return hipErrorInvalidValue;
-    if (g.b_trans) gemm_f64<1, T><<<grid, block, 0, s>>>(g);
-    else gemm_f64<0, T><<<grid, block, 0, s>>>(g);
+    const dim3 fblock(64 * f64_waves<T>());
+    if (g.b_trans) gemm_f64<1, T><<<grid, fblock, 0, s>>>(g);
+    else gemm_f64<0, T><<<grid, fblock, 0, s>>>(g);
     return hipGetLastError();
   }
   return g.b_trans ? launch_mixed<1, T>(prec, g, grid, block, s) : launch_mixed<0, T>(prec, g, grid, block, s);
