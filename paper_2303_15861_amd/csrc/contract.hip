@@ -8,8 +8,8 @@
 //   mode 3 (2D: mode 2):   A = E3,  B'[n][k] = V[k][n] with V viewed n3 x (n1 n2)
 // so A is always read along k (row-major) and B' either along k (factor, mode 1) or
 // along n (grid operand, modes 2/3, "b_trans"). Square workgroup tiles of T = 128 or 64
-// (four waves of T/2 x T/2; the launcher takes 64 when 128-tiles would not fill the
-// chip once), K staged through LDS in chunks; ragged edges are zero-filled on load and
+// (four waves of T/2 x T/2, or for FP64 128-tiles eight waves of 32 x 64; the launcher
+// takes 64 when 128-tiles would not fill the chip once), K staged through LDS in chunks; ragged edges are zero-filled on load and
 // masked on store. The linear workgroup id is remapped so that tiles sharing the large
 // operand are dispatched to the same XCD (workgroups are dealt round-robin over the
 // eight XCDs, each with its own L2).
@@ -25,6 +25,8 @@
 // In the mixed modes the grid operand may be FP32 or FP64 in memory and C may be
 // written as FP32 (intermediate passes) or FP64 (last pass of an action).
 #include "mm_internal.h"
+
+#include <type_traits>
 
 namespace mm {
 
@@ -125,39 +127,54 @@ __global__ __launch_bounds__(64 * f64_waves<T>(), 4) void gemm_f64(GemmArgs p) {
   const int nB = min(n0 + (tid % T), N - 1), kB = tid / T;
   double ra[NL], rb[NL];
   // loads are unconditional (clamped indices, unsigned 32-bit offsets from the uniform
-  // base) so that the loads of a chunk stay in flight through the MFMA phase;
-  // k >= K (last chunk only) is zeroed when the registers are written to LDS
-  auto load = [&](int k0) {
+  // base) so that the loads of a chunk stay in flight through the MFMA phase. Only the
+  // last K-chunk can reach past K: it alone clamps k into the matrix and zeroes k >= K
+  // when the registers are written to LDS (tail = true_type); the other chunks skip
+  // both, which takes about a third of the loop's vector-ALU instructions off the
+  // MFMA issue slots.
+  auto load = [&](int k0, auto tail) {
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
       const unsigned arow = (unsigned)min(m0 + RS * i + r16, M - 1);
       const int kb = BT ? KR * i + kB : k16;
       const unsigned brow = (unsigned)(BT ? nB : min(n0 + RS * i + r16, N - 1));
-      const unsigned ka = (unsigned)min(k0 + k16, K - 1), kbb = (unsigned)min(k0 + kb, K - 1);
+      const unsigned ka = (unsigned)(tail ? min(k0 + k16, K - 1) : k0 + k16);
+      const unsigned kbb = (unsigned)(tail ? min(k0 + kb, K - 1) : k0 + kb);
       ra[i] = A[arow * (unsigned)lda + ka];
       rb[i] = BT ? B[kbb * (unsigned)ldb + brow] : B[brow * (unsigned)ldb + kbb];
     }
   };
-  auto store = [&](double* as, double* bs, int k0) {
+  auto store = [&](double* as, double* bs, int k0, auto tail) {
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
       const int e = i * NT + tid;
       const int kb = BT ? KR * i + kB : k16;
-      as[(e >> 4) * P64 + (e & 15)] = (k0 + k16 < K) ? ra[i] : 0.0;
-      const double y = (k0 + kb < K) ? rb[i] : 0.0;
+      as[(e >> 4) * P64 + (e & 15)] = (!tail || k0 + k16 < K) ? ra[i] : 0.0;
+      const double y = (!tail || k0 + kb < K) ? rb[i] : 0.0;
       if (BT)
         bs[(e / T) * PKN + (e % T)] = y;
       else
         bs[(e >> 4) * P64 + (e & 15)] = y;
     }
   };
-  load(0);
-  store(As[0], Bs[0], 0);
-  __syncthreads();
+  using Tail = std::true_type;
+  using Body = std::false_type;
   const int nch = (K + KC4 - 1) / KC4;
+  if (nch > 1) {
+    load(0, Body());
+    store(As[0], Bs[0], 0, Body());
+  } else {
+    load(0, Tail());
+    store(As[0], Bs[0], 0, Tail());
+  }
+  __syncthreads();
   for (int c = 0; c < nch; ++c) {
     const int cur = c & 1;
-    if (c + 1 < nch) load((c + 1) * KC4);
+    const bool last = c + 2 == nch;   // the chunk staged in this iteration is the last
+    if (c + 1 < nch) {
+      if (last) load((c + 1) * KC4, Tail());
+      else load((c + 1) * KC4, Body());
+    }
     const double* as = As[cur];
     const double* bs = Bs[cur];
 #pragma unroll
@@ -183,7 +200,10 @@ __global__ __launch_bounds__(64 * f64_waves<T>(), 4) void gemm_f64(GemmArgs p) {
           for (int j = 0; j < FIN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
     }
-    if (c + 1 < nch) store(As[cur ^ 1], Bs[cur ^ 1], (c + 1) * KC4);
+    if (c + 1 < nch) {
+      if (last) store(As[cur ^ 1], Bs[cur ^ 1], (c + 1) * KC4, Tail());
+      else store(As[cur ^ 1], Bs[cur ^ 1], (c + 1) * KC4, Body());
+    }
     __syncthreads();
   }
   // f64 16x16 layout: lane l, element t holds row 4t + l/16, column l%16
