@@ -68,6 +68,11 @@ class Problem:
     bc: Tuple[int, ...] = ()
     # diffusion term: "flux" = div(a grad u), "nondiv" = a Lap u
     form: str = "flux"
+    # periodic problems (every bc = 2): the period of each axis; ``a`` then holds the
+    # diagonal diffusion tensor on the periodic grid, shape (d, *grid), and ``velocity``
+    # (None or the same shape) a velocity field entering as div(velocity u)
+    length: Tuple[float, ...] = ()
+    velocity: Optional[np.ndarray] = None
 
     def __post_init__(self):
         if not self.beta_bar:
@@ -235,6 +240,47 @@ def paper3d_problem(N: int, b: float, lam: float, *, scheme: str = "l2b", steps:
     return Problem(d=3, n=(N, N, N), a=a, u0=u0, beta=(b, b, b), r=(0.0, 1.0, 0.0, 1.0), tau=T / steps,
                    steps=steps, scheme=scheme, lam=lam, beta_bar=(b, b, b), bc=(1, 1, 1), form="nondiv",
                    name=name or f"paper3d_N{N}")
+
+
+PERIODIC = 2
+
+
+def paper2d_problem(N: int, lam: float, *, scheme: str = "l2b", steps: int = 256, T: float = 4.0,
+                    name: str = "") -> Problem:
+    """The two-dimensional problem of Sec. 5.2, eq. (eq:ad2d): periodic on (-3 pi, 3 pi)^2,
+    diffusion tensor diag(1/2 + sin^2 x1 sin^2 x2 / 6, 1/2 + cos^2 x1 cos^2 x2 / 6), velocity
+    b = (sin^2 x1, sin^2 x2)/5 in div(b u), r(u) = u(1 - u)/4, u0 = exp(-(x1^2 + x2^2)),
+    N points per direction. The extracted velocity of eq. (eq:amaxbeta) is the mean of
+    b_mu + d_mu a_mumu over the box, 1/10 on both axes (the derivative term has mean zero)."""
+    L = 6.0 * np.pi
+    x = -3.0 * np.pi + L / N * np.arange(N)
+    X2, X1 = np.meshgrid(x, x, indexing="ij")           # arrays [x2][x1]
+    a = np.stack([0.5 + np.sin(X1) ** 2 * np.sin(X2) ** 2 / 6.0, 0.5 + np.cos(X1) ** 2 * np.cos(X2) ** 2 / 6.0])
+    vel = np.stack([np.sin(X1) ** 2 / 5.0, np.sin(X2) ** 2 / 5.0])
+    u0 = np.exp(-(X1 ** 2 + X2 ** 2))
+    return Problem(d=2, n=(N, N), a=a, u0=u0, beta=(0.1, 0.1), r=(0.0, 0.25, -0.25, 0.0), tau=T / steps,
+                   steps=steps, scheme=scheme, lam=lam, beta_bar=(0.1, 0.1), bc=(PERIODIC, PERIODIC), form="flux",
+                   length=(L, L), velocity=vel, name=name or f"paper2d_N{N}")
+
+
+def paper1d_problem(N: int, lam: float, *, nonlinear: bool, scheme: str = "l2b", steps: int = 256,
+                    T: Optional[float] = None, name: str = "") -> Problem:
+    """The one-dimensional periodic problems of Sec. 4 on (-pi, pi) with
+    a = 1 + 10 sin^2 x (a_max over the grid = 11 for N divisible by 4), u0 = sin x:
+    eq. (eq:adlinearzero) u_t = a u_xx (nonlinear = False, T = 1/40) or eq. (eq:adnonlinear)
+    u_t = (a u_x)_x + u(1 - u) (nonlinear = True, T = 1/10). Stored as a 2D periodic
+    problem with one point along x2 (whose derivatives vanish)."""
+    if T is None:
+        T = 0.1 if nonlinear else 1.0 / 40.0
+    L = 2.0 * np.pi
+    x = -np.pi + L / N * np.arange(N)
+    a1 = 1.0 + 10.0 * np.sin(x) ** 2
+    a = np.stack([a1[None, :], np.ones((1, N))])
+    u0 = np.sin(x)[None, :]
+    r = (0.0, 1.0, -1.0, 0.0) if nonlinear else (0.0, 0.0, 0.0, 0.0)
+    return Problem(d=2, n=(N, 1), a=a, u0=u0, beta=(0.0, 0.0), r=r, tau=T / steps, steps=steps, scheme=scheme,
+                   lam=lam, beta_bar=(0.0, 0.0), bc=(PERIODIC, PERIODIC), form="flux" if nonlinear else "nondiv",
+                   length=(L, L), velocity=None, name=name or f"paper1d_N{N}")
 
 
 WORKLOADS = ("2d_n63_le", "3d_n127_l2b", "3d_n127_etd2rk", "3d_n255_l2b", "3d_n383_etd2rk",
