@@ -108,8 +108,22 @@ enum { MM_ETD2RK = 0, MM_ERK2P1 = 1, MM_EE = 2, MM_ERK2P2 = 3 };
  * the mirror u_{n+1} = u_{n-1}, so the 1D operator's last row reads [.., 2, -2]/h^2 and
  * its centred advection vanishes there). Diffusion form: MM_FORM_FLUX is div(a grad u)
  * with face means of the nodal a (eq. (eq:nonlin)); MM_FORM_NONDIV is a Lap u, the form
- * of eq. (eq:adr3d), which reads a at the unknowns only.                              */
-enum { MM_BC_DIRICHLET = 0, MM_BC_NEUMANN = 1 };
+ * of eq. (eq:adr3d), which reads a at the unknowns only.
+ *
+ * MM_BC_PERIODIC (every axis at once; Sec. 4.1, 4.2 and 5.2) selects the Fourier
+ * pseudo-spectral discretization on n equispaced points per period length[mu]: a is then
+ * the diagonal diffusion tensor, d fields of n1 n2 (n3) values (a_11 first) on those
+ * points, and `velocity` (nullable) holds d fields b_mu entering as div(b u) (without it
+ * the constant beta enters as beta . grad u). The derivatives along an axis multiply the
+ * discrete Fourier coefficients by i kappa (zero at the Nyquist wavenumber of even n) and
+ * by -kappa^2, kappa = 2 pi m / length; the library applies them, and the exponentials
+ * of A = sum_mu lam a_mumu^max d_mumu + beta_bar_mu d_mu (a^max the grid maximum of each
+ * a_mumu), as mode products with dense circulant n x n matrices whose first columns it
+ * sums from their Fourier symbols in FP64 at setup (no FFT on the step path). g follows
+ * eq. (eq:nonlin): sum_mu d_mu((a_mumu - lam a^max_mumu) d_mu u) (MM_FORM_NONDIV:
+ * (a_mumu - lam a^max_mumu) d_mumu u) + sum_mu d_mu((b_mu - beta_bar_mu) u) + r(u), and
+ * F = A u + g. Exact phi (q = 0) is not offered for periodic problems.              */
+enum { MM_BC_DIRICHLET = 0, MM_BC_NEUMANN = 1, MM_BC_PERIODIC = 2 };
 enum { MM_FORM_FLUX = 0, MM_FORM_NONDIV = 1 };
 
 typedef struct {
@@ -125,6 +139,9 @@ typedef struct {
   double beta_bar[3];    /* advection moved into A, eq. (eq:linop)                    */
   int bc[3];             /* MM_BC_* per axis (zero: Dirichlet)                        */
   int form;              /* MM_FORM_* (zero: flux form)                               */
+  double length[3];      /* MM_BC_PERIODIC: period of each axis (ignored otherwise)   */
+  const double* velocity;/* MM_BC_PERIODIC: nullable device pointer, d velocity fields
+                            of n1 n2 (n3) values (ignored otherwise)                  */
 } mm_problem;
 
 typedef struct mm_ctx mm_ctx;

@@ -57,11 +57,11 @@ MM_KIND_STENCIL, MM_KIND_GEMM_K, MM_KIND_GEMM_N, MM_KIND_FUSED = 0, 1, 2, 3
 class MMProblem(Structure):
     _fields_ = [("d", c_int), ("n", c_int * 3), ("a", c_void_p), ("beta", c_double * 3),
                 ("r", c_double * 4), ("lam", c_double), ("beta_bar", c_double * 3), ("bc", c_int * 3),
-                ("form", c_int)]
+                ("form", c_int), ("length", c_double * 3), ("velocity", c_void_p)]
 
 
 # boundary data per axis and diffusion form (mumode.h)
-MM_BC_DIRICHLET, MM_BC_NEUMANN = 0, 1
+MM_BC_DIRICHLET, MM_BC_NEUMANN, MM_BC_PERIODIC = 0, 1, 2
 MM_FORM_FLUX, MM_FORM_NONDIV = 0, 1
 FORMS = {"flux": MM_FORM_FLUX, "nondiv": MM_FORM_NONDIV}
 
@@ -161,8 +161,10 @@ class Context:
     """An mm_ctx on one device."""
 
     def __init__(self, device: int = 0):
+        import weakref
         self._h = c_void_p()
         self.device = device
+        self._ops = weakref.WeakSet()     # live operators: released before the context
         st = lib().mm_ctx_create(device, byref(self._h))
         if st != MM_OK:
             raise MumodeError(st, f"mm_ctx_create(device={device}) failed")
@@ -201,6 +203,8 @@ class Context:
 
     def close(self):
         if self._h:
+            for op in list(self._ops):
+                op.close()
             lib().mm_ctx_destroy(self._h)
             self._h = c_void_p()
 
@@ -216,6 +220,7 @@ class Operator:
 
     def __init__(self, ctx: Context, handle: c_void_p, prob, scheme: str, prec: str, q: int):
         self.ctx, self._h = ctx, handle
+        ctx._ops.add(self)
         self.d, self.n = prob.d, tuple(prob.n)
         self.scheme, self.prec, self.q = scheme, prec, q
         self.family = SCHEMES[scheme][0]
@@ -243,11 +248,13 @@ class Operator:
         return out
 
     def close(self):
-        if self._h:
+        # a closed context has released its operators first (Context.close), so an op
+        # whose context is gone has nothing left to free
+        if self._h and self.ctx.handle:
             # through the library, so that this is safe from a finaliser
             lib().mm_synchronize(self.ctx.handle)
             lib().mumode_destroy(self._h)
-            self._h = c_void_p()
+        self._h = c_void_p()
 
     def __del__(self):
         try:
@@ -259,8 +266,10 @@ class Operator:
 def mumode_setup(ctx: Context, d: int, n: Sequence[int], a, beta: Sequence[float], r: Sequence[float],
                  tau: float, scheme: str = "l2b", prec: str = "fp64", q: int = 4, lam: float = 1.0,
                  beta_bar: Optional[Sequence[float]] = None, bc: Optional[Sequence[int]] = None,
-                 form: str = "flux") -> Operator:
-    """Build the extracted operator and its factors on the device (see mumode.h)."""
+                 form: str = "flux", length: Optional[Sequence[float]] = None, velocity=None) -> Operator:
+    """Build the extracted operator and its factors on the device (see mumode.h). For
+    periodic problems ``a`` holds the d diagonal diffusion fields and ``velocity`` (a
+    device tensor or None) the d velocity fields; ``length`` gives the periods."""
     prob = MMProblem()
     prob.d = d
     for i in range(3):
@@ -273,6 +282,9 @@ def mumode_setup(ctx: Context, d: int, n: Sequence[int], a, beta: Sequence[float
         prob.r[i] = float(r[i])
     prob.lam = float(lam)
     prob.a = _ptr(a)
+    for i in range(3):
+        prob.length[i] = float(length[i]) if (length is not None and i < d) else 0.0
+    prob.velocity = _ptr(velocity) if velocity is not None else None
     _torch().cuda.current_stream(a.device).synchronize()   # a must be complete
     fam, sch = SCHEMES[scheme]
     h = c_void_p()
@@ -327,9 +339,14 @@ def mm_check(op: Operator, stream=None) -> int:
 def setup_problem(ctx: Context, prob, prec: str = "fp64", scheme: Optional[str] = None) -> Operator:
     """mumode_setup for a ``synth.Problem`` (copies its coefficient to the device)."""
     torch = _torch()
-    a = torch.from_numpy(prob.a).to(device=f"cuda:{ctx.device}")
+    import numpy as np
+    dev = f"cuda:{ctx.device}"
+    a = torch.from_numpy(np.ascontiguousarray(prob.a)).to(device=dev)
+    vel = getattr(prob, "velocity", None)
+    vel = torch.from_numpy(np.ascontiguousarray(vel)).to(device=dev) if vel is not None else None
     op = mumode_setup(ctx, prob.d, prob.n, a, prob.beta, prob.r, prob.tau, scheme or prob.scheme, prec,
-                      prob.q, prob.lam, prob.beta_bar, getattr(prob, "bc", None), getattr(prob, "form", "flux"))
+                      prob.q, prob.lam, prob.beta_bar, getattr(prob, "bc", None), getattr(prob, "form", "flux"),
+                      getattr(prob, "length", None) or None, vel)
     return op
 
 

@@ -1,8 +1,11 @@
 // Host side of the C ABI: operator setup (extraction, on-device Pade factors),
 // the remainder evaluation, exp / phi1 actions and the Lawson / ERK step sequences.
-// Everything that computes on grid data runs in the kernels of contract.hip and
-// stencil.hip; this file only validates arguments, allocates, and enqueues.
+// Everything that computes on grid data runs in the kernels of contract.hip,
+// stencil.hip and spectral.hip; this file only validates arguments, allocates, and
+// enqueues (and, for periodic problems, sums the first columns of the circulant
+// factors from their Fourier symbols at setup).
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
@@ -235,7 +238,93 @@ hipError_t gemm(const mm_op* op, GemmArgs& g, hipStream_t s) {
                       [&] { return launch_gemm(op->prec, g, s); });
 }
 
+// FP64 mode product along axis mu with a dense n_mu x n_mu matrix M (out_i = sum_j M_ij
+// in_j along the axis), out = M x_mu in (+ add): the layouts of the three mode passes.
+hipError_t mode_product64(const mm_op* op, int mu, const double* M, const double* in, double* out,
+                          const double* add, hipStream_t s) {
+  const int n = op->n[mu];
+  const int64_t dof = op->dof;
+  GemmArgs g{};
+  g.groups = 1;
+  g.alpha = 1.0;
+  g.beta = add ? 1.0 : 0.0;
+  g.Cadd[0] = add;
+  g.C[0] = out;
+  g.inner = 1;
+  if (mu == 0) {
+    g.A[0] = in;
+    g.B[0] = M;
+    g.M = (int)(dof / n);
+    g.N = g.K = n;
+    g.lda = g.ldb = g.ldc = n;
+    g.b_trans = 0;
+  } else if (mu == op->d - 1) {
+    const int P = (int)(dof / n);
+    g.A[0] = M;
+    g.B[0] = in;
+    g.M = g.K = n;
+    g.N = P;
+    g.lda = n;
+    g.ldb = g.ldc = P;
+    g.b_trans = 1;
+  } else {   // x2 of a 3D grid: per x3 slab
+    g.A[0] = M;
+    g.B[0] = in;
+    g.M = g.K = n;
+    g.N = op->n[0];
+    g.lda = n;
+    g.ldb = g.ldc = op->n[0];
+    g.inner = op->n[2];
+    g.sA = 0;
+    g.sB = g.sC = (int64_t)op->n[0] * op->n[1];
+    g.b_trans = 1;
+  }
+  g.tile = op->ctx ? op->ctx->gemm_tile : 0;
+  const double work = 2.0 * g.M * (double)g.N * g.K * g.inner;
+  return timed_launch(op->ctx, g.b_trans ? MM_KIND_GEMM_N : MM_KIND_GEMM_K, work, s,
+                      [&] { return launch_gemm(MM_FP64, g, s); });
+}
+
+// Remainder of a periodic problem (pseudo-spectral, FP64 whatever the op's precision):
+// G = r(u); per axis T1 = D x_mu u, the pointwise pass, G += D1 x_mu T2; for F also
+// G += A_mu x_mu u; then the stage outputs of `a` from G (the stencil's contract).
+hipError_t spectral_remainder(const mm_op* op, const StencilArgs& a, hipStream_t s) {
+  const int64_t dof = op->dof;
+  double* G = op->spec_ws;
+  double* T1 = G + dof;
+  double* T2 = T1 + dof;
+  const bool nondiv = op->form == MM_FORM_NONDIV;
+  hipError_t e = launch_spec_react(G, a.u, dof, op->r, s);
+  for (int mu = 0; mu < op->d && e == hipSuccess; ++mu) {
+    const int64_t nn = (int64_t)op->n[mu] * op->n[mu];
+    const double* D1 = op->dmat[mu];
+    const double* D2 = D1 + nn;
+    if ((e = mode_product64(op, mu, nondiv ? D2 : D1, a.u, T1, nullptr, s)) != hipSuccess) break;
+    SpecMidArgs m{};
+    m.G = G;
+    m.T2 = T2;
+    m.T1 = T1;
+    m.u = a.u;
+    m.a = op->a + mu * dof;
+    m.vel = op->vel ? op->vel + mu * dof : nullptr;
+    m.lam_amax = op->lam * op->amax_mu[mu];
+    m.beta = op->beta[mu];
+    m.beta_bar = op->beta_bar[mu];
+    m.n = dof;
+    m.nondiv = nondiv;
+    if ((e = launch_spec_mid(m, s)) != hipSuccess) break;
+    // the outer derivative: of the flux, or (non-divergence form) of the advected u only
+    if (!nondiv || op->vel || op->beta[mu] != op->beta_bar[mu]) e = mode_product64(op, mu, D1, T2, G, G, s);
+  }
+  if (a.full)
+    for (int mu = 0; mu < op->d && e == hipSuccess; ++mu)
+      e = mode_product64(op, mu, op->dmat[mu] + 2 * (int64_t)op->n[mu] * op->n[mu], a.u, G, G, s);
+  if (e != hipSuccess) return e;
+  return launch_spec_combine(G, a, dof, s);
+}
+
 hipError_t stencil(const mm_op* op, const StencilArgs& a, hipStream_t s) {
+  if (op->periodic) return spectral_remainder(op, a, s);
   return timed_launch(op->ctx, MM_KIND_STENCIL, (double)op->dof, s,
                       [&] { return launch_stencil(op->d, a, s); });
 }
@@ -481,7 +570,34 @@ hipError_t eig_scale(const mm_op* op, double* out, const double* a, double ca, i
 // mesh width of axis mu: n unknowns at i/(n+1) (Dirichlet data at both ends) or at i/n
 // (zero normal derivative at x = 1)
 double mesh_h(const mm_op* op, int mu) {
+  if (op->bc[mu] == MM_BC_PERIODIC) return op->length[mu] / op->n[mu];
   return op->bc[mu] == MM_BC_NEUMANN ? 1.0 / op->n[mu] : 1.0 / (op->n[mu] + 1);
+}
+
+// First column of the real circulant n x n matrix whose eigenvalue on the Fourier mode
+// e^{2 pi i m j / n} is sym(m, nyquist): c_j = (1/n) sum_m sym(m) e^{2 pi i m j / n}, m the
+// signed wavenumber (|m| <= n/2; nyquist marks m = n/2 of even n). Summed in long double
+// with an exact twiddle index (m j mod n).
+template <typename F>
+std::vector<double> circulant_column(int n, F sym) {
+  typedef std::complex<long double> cl;
+  std::vector<cl> tw(n), f(n);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int k = 0; k < n; ++k) {
+    const long double t = 2.0L * pi * (long double)k / (long double)n;
+    tw[k] = cl(std::cos(t), std::sin(t));
+  }
+  for (int m = 0; m < n; ++m) {
+    const int ms = (m <= (n - 1) / 2) ? m : m - n;
+    f[m] = sym(ms, n % 2 == 0 && m == n / 2);
+  }
+  std::vector<double> col(n);
+  for (int j = 0; j < n; ++j) {
+    cl acc = 0;
+    for (int m = 0; m < n; ++m) acc += f[m] * tw[(int64_t)m * j % n];
+    col[j] = (double)(acc.real() / (long double)n);
+  }
+  return col;
 }
 
 StencilArgs stencil_args(const mm_op* op, const double* u, bool full) {
@@ -507,6 +623,7 @@ StencilArgs stencil_args(const mm_op* op, const double* u, bool full) {
   a.c1 = 1.0;
   a.flag = op->flag;
   a.nondiv = op->form == MM_FORM_NONDIV;
+  a.full = full;
   return a;
 }
 
@@ -635,6 +752,10 @@ void mumode_destroy(mm_op* op) {
   dev_free(op, op->f3_stage2_exp);
   dev_free(op, op->f3_phi_exp);
   for (int mu = 0; mu < 3; ++mu) dev_free(op, op->ev[mu]);
+  for (int mu = 0; mu < 3; ++mu)
+    if (op->dmat_owned[mu]) dev_free(op, op->dmat[mu]);
+  dev_free(op, op->vel);
+  dev_free(op, op->spec_ws);
   for (int i = 0; i < 6; ++i) dev_free(op, op->buf[i]);
   dev_free(op, op->vdig);
   dev_free(op, op->vexp);
@@ -669,10 +790,25 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     return MM_EINVAL;
   }
   for (int mu = 0; mu < prob->d; ++mu)
-    if (prob->bc[mu] != MM_BC_DIRICHLET && prob->bc[mu] != MM_BC_NEUMANN) {
+    if (prob->bc[mu] != MM_BC_DIRICHLET && prob->bc[mu] != MM_BC_NEUMANN && prob->bc[mu] != MM_BC_PERIODIC) {
       set_err(ctx, "bc[%d] = %d is not a boundary type", mu, prob->bc[mu]);
       return MM_EINVAL;
     }
+  const bool periodic = prob->bc[0] == MM_BC_PERIODIC;
+  for (int mu = 0; mu < prob->d; ++mu) {
+    if ((prob->bc[mu] == MM_BC_PERIODIC) != periodic) {
+      set_err(ctx, "periodic axes cannot be mixed with Dirichlet or Neumann axes");
+      return MM_EINVAL;
+    }
+    if (periodic && !(prob->length[mu] > 0.0 && std::isfinite(prob->length[mu]))) {
+      set_err(ctx, "length[%d] must be finite and positive for a periodic axis", mu);
+      return MM_EINVAL;
+    }
+  }
+  if (periodic && family == MM_ERK && quad_nodes == 0) {
+    set_err(ctx, "exact phi (quad_nodes = 0) is not offered for periodic problems");
+    return MM_EINVAL;
+  }
   if (prob->form != MM_FORM_FLUX && prob->form != MM_FORM_NONDIV) {
     set_err(ctx, "form = %d is not a diffusion form", prob->form);
     return MM_EINVAL;
@@ -743,6 +879,8 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     op->bc[mu] = (mu < prob->d) ? prob->bc[mu] : MM_BC_DIRICHLET;
   }
   op->form = prob->form;
+  op->periodic = periodic;
+  for (int mu = 0; mu < 3; ++mu) op->length[mu] = (periodic && mu < prob->d) ? prob->length[mu] : 0.0;
   for (int i = 0; i < 4; ++i) op->r[i] = prob->r[i];
   op->lam = prob->lambda;
   op->tau = tau;
@@ -755,6 +893,7 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
   op->dof = (int64_t)op->n[0] * op->n[1] * op->n[2];
   int64_t na = 1;
   for (int mu = 0; mu < op->d; ++mu) na *= op->n[mu] + 2;
+  if (periodic) na = op->d * op->dof;   // the d diagonal diffusion fields
 
   auto fail = [&](mm_status s) {
     mumode_destroy(op);
@@ -768,21 +907,39 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
   }
   if ((rc = dev_alloc(op, &op->flag, 1)) != MM_OK) return fail(rc);
   if (hipMemsetAsync(op->flag, 0, sizeof(int), st) != hipSuccess) return fail(MM_EDEVICE);
+  if (periodic && prob->velocity) {
+    if ((rc = dev_alloc(op, &op->vel, op->d * op->dof)) != MM_OK) return fail(rc);
+    if (hipMemcpyAsync(op->vel, prob->velocity, op->d * op->dof * sizeof(double), hipMemcpyDeviceToDevice, st) !=
+        hipSuccess) {
+      set_err(ctx, "copy of the velocity field failed (device pointer expected)");
+      return fail(MM_EINVAL);
+    }
+  }
 
-  // a_max = max over all nodes (eq. (eq:amaxbeta))
+  // a_max = max over all nodes (eq. (eq:amaxbeta)); periodic problems: the maximum of each
+  // diagonal entry a_mumu of the diffusion tensor
+  const int nred = periodic ? op->d : 1;
+  const int64_t lred = periodic ? op->dof : na;
   double amax = 0.0;
-  if (launch_max_reduce(op->a, na, ctx->reduce_buf, ctx->reduce_parts, ctx->reduce_buf + ctx->reduce_parts,
-                        st) != hipSuccess ||
-      hipMemcpyAsync(&amax, ctx->reduce_buf + ctx->reduce_parts, sizeof(double), hipMemcpyDeviceToHost, st) !=
-          hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess) {
-    set_err(ctx, "a_max reduction failed");
-    return fail(MM_EDEVICE);
+  for (int i = 0; i < nred; ++i) {
+    double m = 0.0;
+    if (launch_max_reduce(op->a + i * lred, lred, ctx->reduce_buf, ctx->reduce_parts,
+                          ctx->reduce_buf + ctx->reduce_parts, st) != hipSuccess ||
+        hipMemcpyAsync(&m, ctx->reduce_buf + ctx->reduce_parts, sizeof(double), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      set_err(ctx, "a_max reduction failed");
+      return fail(MM_EDEVICE);
+    }
+    if (!std::isfinite(m)) {
+      set_err(ctx, "diffusion coefficient is not finite");
+      return fail(MM_EINVAL);
+    }
+    op->amax_mu[i] = m;
+    amax = (i == 0) ? m : std::max(amax, m);
   }
-  if (!std::isfinite(amax)) {
-    set_err(ctx, "diffusion coefficient is not finite");
-    return fail(MM_EINVAL);
-  }
+  if (!periodic)
+    for (int mu = 0; mu < 3; ++mu) op->amax_mu[mu] = amax;
   op->a_max = amax;
 
   // coefficients c of the factors exp(c tau A_mu): c_0 = 1, c_j = theta_j
@@ -817,7 +974,9 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
   for (int mu = 0; mu < op->d; ++mu) {
     int same = -1;
     for (int nu = 0; nu < mu; ++nu)
-      if (op->n[nu] == op->n[mu] && op->beta_bar[nu] == op->beta_bar[mu] && op->bc[nu] == op->bc[mu]) same = nu;
+      if (op->n[nu] == op->n[mu] && op->beta_bar[nu] == op->beta_bar[mu] && op->bc[nu] == op->bc[mu] &&
+          op->length[nu] == op->length[mu] && op->amax_mu[nu] == op->amax_mu[mu])
+        same = nu;
     if (same >= 0) {
       op->fac[mu] = op->fac[same];
       op->squarings[mu] = op->squarings[same];
@@ -829,6 +988,28 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
       return fail(rc);
     }
     op->fac_owned[mu] = true;
+    if (periodic) {
+      // exp(c tau A_mu) is circulant: its first column from the symbol of A_mu
+      const double kap = 2.0 * M_PI / op->length[mu];
+      const long double la = (long double)op->lam * op->amax_mu[mu], bb = op->beta_bar[mu];
+      for (int j = 0; j < nf; ++j) {
+        const long double ct = (long double)cs[j] * tau;
+        std::vector<double> col = circulant_column(n, [&](int m, bool nyq) {
+          const long double k = (long double)kap * m;
+          const long double re = -la * k * k, im = nyq ? 0.0L : bb * k;
+          const long double mag = std::exp(ct * re);
+          return std::complex<long double>(mag * std::cos(ct * im), mag * std::sin(ct * im));
+        });
+        if (hipMemcpyAsync(ws, col.data(), n * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+            launch_build_circulant(op->fac[mu] + (int64_t)j * n * n, n, ws, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+          hipFreeAsync(ws, st);
+          set_err(ctx, "circulant factor setup failed");
+          return fail(MM_EDEVICE);
+        }
+      }
+      continue;
+    }
     const double h = mesh_h(op, mu);
     const double diff = op->lam * op->a_max / (h * h);
     const double adv = op->beta_bar[mu] / (2.0 * h);
@@ -842,6 +1023,46 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
         return fail(rc);
       }
       if (j == 0) op->squarings[mu] = sq;
+    }
+  }
+  if (periodic) {
+    // per axis [D1 | D2 | A_mu]: the Fourier derivatives and the extracted operator
+    for (int mu = 0; mu < op->d; ++mu) {
+      int same = -1;
+      for (int nu = 0; nu < mu; ++nu)
+        if (op->n[nu] == op->n[mu] && op->beta_bar[nu] == op->beta_bar[mu] && op->length[nu] == op->length[mu] &&
+            op->amax_mu[nu] == op->amax_mu[mu])
+          same = nu;
+      if (same >= 0) {
+        op->dmat[mu] = op->dmat[same];
+        continue;
+      }
+      const int n = op->n[mu];
+      const int64_t nn = (int64_t)n * n;
+      if ((rc = dev_alloc(op, &op->dmat[mu], 3 * nn)) != MM_OK) {
+        hipFreeAsync(ws, st);
+        return fail(rc);
+      }
+      op->dmat_owned[mu] = true;
+      const long double kap = 2.0L * (long double)M_PI / op->length[mu];
+      const long double la = (long double)op->lam * op->amax_mu[mu], bb = op->beta_bar[mu];
+      typedef std::complex<long double> cl;
+      const std::vector<double> cols[3] = {
+          circulant_column(n, [&](int m, bool nyq) { return cl(0.0L, nyq ? 0.0L : kap * m); }),
+          circulant_column(n, [&](int m, bool) { return cl(-(kap * m) * (kap * m), 0.0L); }),
+          circulant_column(n, [&](int m, bool nyq) { return cl(-la * (kap * m) * (kap * m), nyq ? 0.0L : bb * kap * m); })};
+      for (int k = 0; k < 3; ++k)
+        if (hipMemcpyAsync(ws, cols[k].data(), n * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+            launch_build_circulant(op->dmat[mu] + k * nn, n, ws, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+          hipFreeAsync(ws, st);
+          set_err(ctx, "circulant derivative setup failed");
+          return fail(MM_EDEVICE);
+        }
+    }
+    if ((rc = dev_alloc(op, &op->spec_ws, 3 * op->dof)) != MM_OK) {
+      hipFreeAsync(ws, st);
+      return fail(rc);
     }
   }
   hipFreeAsync(ws, st);

@@ -85,6 +85,21 @@ struct StencilArgs {
   int* flag;            // nullable: set to 1 if out0 is not finite
   int neu[3];           // per axis: zero normal derivative at x = 1 (mirror ghost)
   int nondiv;           // diffusion a Lap u instead of div(a grad u)
+  int full;             // F(u) requested instead of g(u) (periodic problems read this;
+                        // the stencil gets F through lam_amax = 0 and cadv)
+};
+
+// One axis of the pointwise pass of the spectral remainder (spectral.hip).
+struct SpecMidArgs {
+  double* G;            // remainder accumulator (nondiv: += (a - lam a_max) T1)
+  double* T2;           // operand of the outer derivative
+  const double* T1;     // inner derivative of u along the axis
+  const double* u;
+  const double* a;      // a_mumu on the grid
+  const double* vel;    // nullable: velocity b_mu on the grid (else the constant beta)
+  double lam_amax, beta, beta_bar;
+  int64_t n;
+  int nondiv;
 };
 
 // Whole small 2D Lawson solves in one workgroup (n1, n2 <= 64, FP64).
@@ -113,6 +128,10 @@ hipError_t launch_gemm_sliced(GemmArgs& g, hipStream_t s);
 hipError_t launch_slice_rows(signed char* dst, int* exps, const double* src, int rows, int k, int lds, int ldd,
                              int S, hipStream_t s);
 hipError_t launch_stencil(int d, const StencilArgs& a, hipStream_t s);
+hipError_t launch_build_circulant(double* M, int n, const double* col, hipStream_t s);
+hipError_t launch_spec_react(double* G, const double* u, int64_t n, const double* r, hipStream_t s);
+hipError_t launch_spec_mid(const SpecMidArgs& a, hipStream_t s);
+hipError_t launch_spec_combine(const double* G, const StencilArgs& a, int64_t n, hipStream_t s);
 hipError_t launch_max_reduce(const double* x, int64_t n, double* partial, int nparts, double* out,
                              hipStream_t s);
 // last_sub: the entry (n-1, n-2) (sub for a Toeplitz matrix)
@@ -183,6 +202,14 @@ struct mm_op {
   int slices = 0;                      // MM_SLICED digit count
   int bc[3] = {0, 0, 0};               // MM_BC_* per axis
   int form = 0;                        // MM_FORM_*
+  // periodic (pseudo-spectral) problems: every axis MM_BC_PERIODIC
+  bool periodic = false;
+  double length[3] = {0, 0, 0};        // periods
+  double amax_mu[3] = {0, 0, 0};       // max of each diagonal diffusion entry
+  double* vel = nullptr;               // nullable: d velocity fields (dof each)
+  double* dmat[3] = {nullptr, nullptr, nullptr};   // per axis [D1 | D2 | A], n x n each
+  bool dmat_owned[3] = {false, false, false};
+  double* spec_ws = nullptr;           // G, T1, T2 (dof each)
   bool exact = false;                  // MM_ERK with exact phi1 through the eigenbasis
   int nfac = 1;                        // factors stored per axis
   double* ev[3] = {nullptr, nullptr, nullptr};   // exact: 1D eigenvalues per axis
