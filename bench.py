@@ -41,6 +41,8 @@ DESCRIPTION = {
                             "phi1 (eigenbasis), tau=2e-3, 50 steps",
     "3d_paper_n60_sl2": "the 3D ADR problem of Sec. 5.3 (a Lap u, Dirichlet at 0, Neumann at 1), N = 60, b = -0.01, "
                         "SL2 with lambda = 0.53, 256 steps to T = 1/4",
+    "2d_paper_n256_sl2": "the periodic 2D ADR problem of Sec. 5.2 (pseudo-spectral, circulant factors), N = 256, "
+                         "SL2 with lambda = 0.57, 256 steps to T = 4",
 }
 HBM_PEAK = 8.0e12
 WORKLOAD = "3d_n255_l2b"
@@ -201,13 +203,16 @@ def serve_stream(mm, prec, count, max_active):
 
 def cpu_baseline(p, steps):
     """The oracle, untuned, on the host cores: `steps` steps of the workload's scheme."""
+    import synth
     cores = len(os.sched_getaffinity(0))
     try:
         from threadpoolctl import threadpool_limits
         ctxm = threadpool_limits(limits=cores)
     except Exception:  # pragma: no cover
         ctxm = None
-    if any(getattr(p, "bc", ())) or getattr(p, "form", "flux") != "flux":
+    if any(b == synth.PERIODIC for b in getattr(p, "bc", ())):
+        from oracle import spectral as S       # periodic pseudo-spectral problems
+    elif any(getattr(p, "bc", ())) or getattr(p, "form", "flux") != "flux":
         from oracle import adr3d as S          # Neumann axes or the non-divergence form
     else:
         from oracle import schemes as S

@@ -219,6 +219,8 @@ def workload(name: str, seed: int = 0) -> Problem:
     # SL2 with the lambda of Table tab:adr3d_lambdaopt, m = 2^8 steps to T = 1/4)
     if name == "3d_paper_n60_sl2":
         return paper3d_problem(60, -0.01, 0.53, scheme="sl2", steps=256, name=name)
+    if name == "2d_paper_n256_sl2":
+        return paper2d_problem(256, 0.57, scheme="sl2", steps=256, name=name)
     raise KeyError(name)
 
 
@@ -284,7 +286,7 @@ def paper1d_problem(N: int, lam: float, *, nonlinear: bool, scheme: str = "l2b",
 
 
 WORKLOADS = ("2d_n63_le", "3d_n127_l2b", "3d_n127_etd2rk", "3d_n255_l2b", "3d_n383_etd2rk",
-             "3d_n127_etd2rk_exact", "3d_n383_etd2rk_exact", "3d_paper_n60_sl2")
+             "3d_n127_etd2rk_exact", "3d_n383_etd2rk_exact", "3d_paper_n60_sl2", "2d_paper_n256_sl2")
 
 
 # --------------------------------------------------------------------------

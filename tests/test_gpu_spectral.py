@@ -222,3 +222,46 @@ def test_fig_adr2d_printed_errors_and_lambda_table(mm, ctx):
         if lam_opt is not None:
             best = pts[int(np.argmin(errs))][0]
             assert abs(best - lam_opt) < 0.01, (sch, best, lam_opt)
+
+
+def test_fig_px91_printed_errors_with_gpu_solves(mm, ctx):
+    """Figure fig:ad1dpx91_diffdelta (Sec. 4.2, N = 2^10, T = 1/10, m = 2^12) with the
+    solutions computed on the GPU and the oracle's unsplit reference (ERK2 with phi2, the
+    linear part exact; tests/test_oracle_spectral.py): the printed errors of the Lawson
+    family within 1e-3 relative."""
+    import test_oracle_spectral as T
+    N, T_end = 1024, 0.1
+    p = synth.paper1d_problem(N, 1.0, nonlinear=True, scheme="l2b", steps=4096)
+    be = spectral.Spectral(p)
+    eye = np.eye(N)
+    D1 = np.stack([be.d1(eye[j][None, :], 0)[0] for j in range(N)], axis=1)
+    Afull = D1 @ np.diag(p.a[0][0]) @ D1
+    w, V = np.linalg.eigh(0.5 * (Afull + Afull.T))
+
+    class Unsplit:
+        def __init__(self, tau):
+            self.tau = tau
+
+        def _f(self, f, v):
+            return (V @ (f * (V.T @ v[0])))[None, :]
+
+        def phi1v(self, v):
+            return self._f(spectral.phi_complex(1, self.tau * w).real, v)
+
+        def phi2v(self, v):
+            return self._f(spectral.phi_complex(2, self.tau * w).real, v)
+
+        def g(self, v):
+            return v * (1.0 - v)
+
+        def F(self, v):
+            return (Afull @ v[0])[None, :] + self.g(v)
+
+    m = 2 ** 13
+    ref = Sch.integrate(p.u0, Unsplit(T_end / m), T_end / m, m, "erk2p2")
+    for sch, lam, err in T.FIG_PX91:
+        if sch in ("ee", "erk2p2"):
+            continue          # exact phi is not offered for periodic problems on the GPU
+        u = _gpu_solve(mm, ctx, synth.paper1d_problem(N, lam, nonlinear=True, scheme=sch, steps=4096))
+        e = Sch.rel_inf_error(u, ref)
+        assert abs(e - err) <= 1e-3 * err, (sch, lam, e, err)
