@@ -180,7 +180,8 @@ void mumode_destroy(mm_op* op);
 mm_status mm_synchronize(mm_ctx* ctx);
 
 /* The extracted maximum a_max and the scaling exponent s used for factor c = 1 along
- * axis mu (diagnostics). */
+ * axis mu (diagnostics). Periodic problems: a_max is the largest of the per-axis maxima
+ * a_mumu^max, and s = 0 (their factors come from the Fourier symbol, not from Pade). */
 mm_status mumode_info(const mm_op* op, double* a_max, int* squarings);
 
 /* Copy the FP64 factor of index j of axis mu into host memory (n_mu*n_mu values,
