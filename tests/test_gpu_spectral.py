@@ -265,3 +265,17 @@ def test_fig_px91_printed_errors_with_gpu_solves(mm, ctx):
         u = _gpu_solve(mm, ctx, synth.paper1d_problem(N, lam, nonlinear=True, scheme=sch, steps=4096))
         e = Sch.rel_inf_error(u, ref)
         assert abs(e - err) <= 1e-3 * err, (sch, lam, e, err)
+
+
+def test_periodic_steps_replayed_from_graphs_are_bitwise_equal(mm, ctx):
+    """Step graphs (recorded mode products and pointwise passes of the spectral remainder)
+    replay the same arithmetic as direct launches: 10 Lawson2b steps, graphs of 4 steps
+    plus 2 direct ones, bit for bit."""
+    p = dataclasses.replace(synth.paper2d_problem(64, 0.5, scheme="l2b", steps=256), steps=10)
+    ref = _gpu_solve(mm, ctx, p)
+    ctx.set_graph_steps(4)
+    try:
+        got = _gpu_solve(mm, ctx, p)
+    finally:
+        ctx.set_graph_steps(0)
+    assert np.array_equal(got, ref)
