@@ -279,3 +279,30 @@ def test_periodic_steps_replayed_from_graphs_are_bitwise_equal(mm, ctx):
     finally:
         ctx.set_graph_steps(0)
     assert np.array_equal(got, ref)
+
+
+def test_fig1_printed_errors_with_gpu_solves(mm, ctx):
+    """Figure fig:ad1dex0_diffdeltaa (Sec. 4.1: u_t = a u_xx, N = 2^12 Fourier points,
+    T = 1/40) with the solutions computed on the GPU (4096 x 4096 circulant factors) and
+    the exact semi-discrete reference of oracle/fourier1d.py: the printed errors of the
+    Lawson family at lambda = 1 and 1/2, m = 16 and 64, within 1e-6 relative + 5e-12 (the
+    bar of the oracle's own pin)."""
+    import os
+    from oracle import fourier1d as F1
+    gold = os.path.join(os.path.dirname(__file__), "golden", "fig1_linear_diffusion_errors.txt")
+    lams = {"1": 1.0, "1/2": 0.5}
+    N, T_end = 4096, 1.0 / 40.0
+    x = -np.pi + 2.0 * np.pi * np.arange(N) / N
+    ref = F1.exact_solution(x, T_end)[None, :]
+    checked = 0
+    for ln in open(gold):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        lam, sch, m, err = ln.split()
+        if lam not in lams or sch not in ("le", "sle", "l2a", "l2b", "sl2") or int(m) > 64:
+            continue
+        u = _gpu_solve(mm, ctx, synth.paper1d_problem(N, lams[lam], nonlinear=False, scheme=sch, steps=int(m)))
+        e = Sch.rel_inf_error(u, ref)
+        assert abs(e - float(err)) <= 1e-6 * float(err) + 5e-12, (lam, sch, m, e, err)
+        checked += 1
+    assert checked == 20
