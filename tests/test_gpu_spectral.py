@@ -306,3 +306,23 @@ def test_fig1_printed_errors_with_gpu_solves(mm, ctx):
         assert abs(e - float(err)) <= 1e-6 * float(err) + 5e-12, (lam, sch, m, e, err)
         checked += 1
     assert checked == 20
+
+
+@pytest.mark.parametrize("tile", [64, 128])
+def test_periodic_with_forced_tiles(mm, ctx, tile):
+    """Both workgroup tiles of the mode products (ragged 40 x 36 x 30 grid, the 128-tile
+    kernels otherwise reserved for large grids) on the spectral remainder's in-place
+    accumulation and on Lawson2b steps."""
+    p = random_periodic((40, 36, 30), 11, scheme="l2b", steps=3, tau=4e-3)
+    ctx.set_gemm_tile(tile)
+    try:
+        op = mm.setup_problem(ctx, p)
+        u = dev(p.u0)
+        g = dev(np.zeros(p.u0.shape))
+        mm.remainder_eval(op, u, g)
+        assert relerr(host(g), spectral.Spectral(p).g(p.u0)) <= FP64_TOL
+        mm.step(op, u, p.steps)
+        assert relerr(host(u), spectral.solve(p)) <= FP64_TOL
+        op.close()
+    finally:
+        ctx.set_gemm_tile(0)
