@@ -280,6 +280,10 @@ typedef struct {
   int slices;            /* digit count for MM_SLICED (0 = 6)                          */
   int bc[3];             /* MM_BC_* per axis (zero: Dirichlet), as in mm_problem      */
   int form;              /* MM_FORM_* (zero: flux form)                               */
+  double length[3];      /* MM_BC_PERIODIC: periods, as in mm_problem                 */
+  const double* velocity;/* MM_BC_PERIODIC: nullable HOST pointer, d velocity fields
+                            (copied); for periodic requests `a` holds the d diagonal
+                            diffusion fields of n1 n2 (n3) values each                */
 } mm_request;
 
 typedef struct {

@@ -70,7 +70,8 @@ class MMRequest(Structure):
     _fields_ = [("d", c_int), ("n", c_int * 3), ("a", c_void_p), ("u0", c_void_p),
                 ("beta", c_double * 3), ("r", c_double * 4), ("lam", c_double),
                 ("beta_bar", c_double * 3), ("tau", c_double), ("steps", c_int), ("prec", c_int),
-                ("slices", c_int), ("bc", c_int * 3), ("form", c_int)]
+                ("slices", c_int), ("bc", c_int * 3), ("form", c_int), ("length", c_double * 3),
+                ("velocity", c_void_p)]
 
 
 class MMStats(Structure):

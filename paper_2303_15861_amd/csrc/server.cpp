@@ -23,6 +23,8 @@
 #include <mutex>
 #include <thread>
 
+#include <cmath>
+
 #include "mm_internal.h"
 
 namespace {
@@ -33,7 +35,7 @@ constexpr int kAdmitThreads = 4;
 struct Job {
   uint64_t id = 0;
   mm_request req{};
-  std::vector<double> a, u0;
+  std::vector<double> a, u0, vel;
   int64_t est_bytes = 0;
   double work = 0;   // flop estimate for stream balancing
   double t_submit = 0, t_admit = 0, t_done = 0;
@@ -58,6 +60,10 @@ int64_t footprint(const mm_request& r) {
     fac += (int64_t)r.n[mu] * r.n[mu];
     nmax = std::max<int64_t>(nmax, r.n[mu]);
   }
+  // periodic: d diffusion fields (and the velocity copy), [D1 | D2 | A] per axis and the
+  // remainder's three scratch grid functions
+  const bool periodic = r.bc[0] == MM_BC_PERIODIC;
+  if (periodic) na = r.d * dof * (r.velocity ? 2 : 1) + 3 * dof + 3 * fac;
   // a, u, 4 scratch grid functions, factors (+ mixed copies), Pade workspace (7 n^2)
   return 8 * (na + 5 * dof + 2 * fac + 7 * nmax * nmax) + 4096;
 }
@@ -141,17 +147,28 @@ struct mm_server {
     const mm_request& r = j.req;
     hipStream_t cs = actx->stream;
     double* da = nullptr;
+    double* dv = nullptr;
     const size_t abytes = j.a.size() * sizeof(double);
     const size_t ubytes = j.u0.size() * sizeof(double);
+    const size_t vbytes = j.vel.size() * sizeof(double);
     if (hipMallocAsync((void**)&da, abytes, cs) != hipSuccess) return MM_ENOMEM;
-    if (hipMallocAsync((void**)&j.u, ubytes, cs) != hipSuccess) {
-      j.u = nullptr;
+    if (vbytes && hipMallocAsync((void**)&dv, vbytes, cs) != hipSuccess) {
       hipFreeAsync(da, cs);
       return MM_ENOMEM;
     }
-    if (hipMemcpyAsync(da, j.a.data(), abytes, hipMemcpyHostToDevice, cs) != hipSuccess ||
-        hipMemcpyAsync(j.u, j.u0.data(), ubytes, hipMemcpyHostToDevice, cs) != hipSuccess) {
+    auto free_inputs = [&] {
       hipFreeAsync(da, cs);
+      if (dv) hipFreeAsync(dv, cs);
+    };
+    if (hipMallocAsync((void**)&j.u, ubytes, cs) != hipSuccess) {
+      j.u = nullptr;
+      free_inputs();
+      return MM_ENOMEM;
+    }
+    if (hipMemcpyAsync(da, j.a.data(), abytes, hipMemcpyHostToDevice, cs) != hipSuccess ||
+        (vbytes && hipMemcpyAsync(dv, j.vel.data(), vbytes, hipMemcpyHostToDevice, cs) != hipSuccess) ||
+        hipMemcpyAsync(j.u, j.u0.data(), ubytes, hipMemcpyHostToDevice, cs) != hipSuccess) {
+      free_inputs();
       return MM_EDEVICE;
     }
     mm_problem p{};
@@ -166,10 +183,12 @@ struct mm_server {
     p.form = r.form;
     p.lambda = r.lambda;
     p.a = da;
+    for (int i = 0; i < 3; ++i) p.length[i] = r.length[i];
+    p.velocity = dv;
     // mumode_setup ends with a synchronisation of actx's stream: a, u and the op are
     // ready for any stream afterwards
     const int st = mumode_setup(actx, &p, r.tau, MM_LAWSON, MM_LAWSON2B, 0, r.prec, r.slices, &j.op);
-    hipFreeAsync(da, cs);
+    free_inputs();
     if (st != MM_OK) {
       j.op = nullptr;
       return st;
@@ -369,12 +388,16 @@ mm_status solve_submit(mm_server* s, const mm_request* r, uint64_t* id) {
     return MM_EINVAL;
   if (r->form != MM_FORM_FLUX && r->form != MM_FORM_NONDIV) return MM_EINVAL;
   int64_t dof = 1, na = 1;
+  const bool periodic = r->bc[0] == MM_BC_PERIODIC;
   for (int mu = 0; mu < r->d; ++mu) {
     if (r->n[mu] < 1 || r->n[mu] > 4096) return MM_EINVAL;
-    if (r->bc[mu] != MM_BC_DIRICHLET && r->bc[mu] != MM_BC_NEUMANN) return MM_EINVAL;
+    if (r->bc[mu] != MM_BC_DIRICHLET && r->bc[mu] != MM_BC_NEUMANN && r->bc[mu] != MM_BC_PERIODIC) return MM_EINVAL;
+    if ((r->bc[mu] == MM_BC_PERIODIC) != periodic) return MM_EINVAL;
+    if (periodic && !(r->length[mu] > 0.0 && std::isfinite(r->length[mu]))) return MM_EINVAL;
     dof *= r->n[mu];
     na *= r->n[mu] + 2;
   }
+  if (periodic) na = r->d * dof;
   auto j = std::make_unique<Job>();
   j->req = *r;
   for (int mu = r->d; mu < 3; ++mu) {
@@ -383,10 +406,12 @@ mm_status solve_submit(mm_server* s, const mm_request* r, uint64_t* id) {
   }
   j->a.assign(r->a, r->a + na);
   j->u0.assign(r->u0, r->u0 + dof);
+  if (periodic && r->velocity) j->vel.assign(r->velocity, r->velocity + r->d * dof);
   j->req.a = nullptr;
   j->req.u0 = nullptr;
   j->est_bytes = footprint(j->req);
   j->work = work_estimate(j->req);
+  j->req.velocity = nullptr;   // copied into j->vel
   if (j->est_bytes > s->budget) return MM_ENOMEM;
   j->t_submit = s->now();
   {

@@ -56,6 +56,13 @@ def solve_submit(srv: Server, prob, prec: str = "fp64") -> Tuple[int, int]:
     req.prec, req.slices = prec_code(prec)
     req.a = a.ctypes.data
     req.u0 = u0.ctypes.data
+    length = getattr(prob, "length", ()) or ()
+    for i in range(3):
+        req.length[i] = float(length[i]) if i < len(length) else 0.0
+    vel = getattr(prob, "velocity", None)
+    if vel is not None:
+        vel = np.ascontiguousarray(vel, dtype=np.float64)
+        req.velocity = vel.ctypes.data   # copied by solve_submit before it returns
     rid = c_uint64()
     st = srv._lib.solve_submit(srv._h, byref(req), byref(rid))
     return st, rid.value

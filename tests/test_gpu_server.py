@@ -5,6 +5,7 @@ Checks: a request's result is bit-for-bit the same alone and among other request
 it matches the FP64 oracle, admission respects the HBM budget, a request larger than
 the budget is refused, a non-finite request fails alone, and unknown ids are reported.
 """
+import dataclasses
 import time
 
 import numpy as np
@@ -146,3 +147,26 @@ def test_neumann_requests_next_to_dirichlet_ones(mm):
     assert sa == mm.MM_OK and sb == mm.MM_OK
     assert relerr(ua, adr3d.solve(paper)) <= 1e-12
     assert relerr(ub, S.solve(plain)) <= 1e-12
+
+
+def test_periodic_requests_next_to_dirichlet_ones(mm):
+    """Periodic (pseudo-spectral) requests: the problem of Sec. 5.2 with its velocity field
+    and the problem of Sec. 4.2 without one, served next to an all-Dirichlet request, each
+    Lawson2b solve against its oracle; a request mixing periodic and Dirichlet axes is
+    refused."""
+    from oracle import spectral
+    p2 = dataclasses.replace(synth.paper2d_problem(64, 0.5, scheme="l2b", steps=256), steps=24)
+    p1 = synth.paper1d_problem(256, 0.5, nonlinear=True, scheme="l2b", steps=32)
+    plain = synth.smooth_problem((20, 18, 16), 52, tau=1e-3, steps=12)
+    srv = mm.Server(0, max_active=4)
+    try:
+        ids = [mm.solve_submit(srv, q)[1] for q in (p2, p1, plain)]
+        outs = [wait(mm, srv, i, q.u0.shape) for i, q in zip(ids, (p2, p1, plain))]
+        bad = dataclasses.replace(p2, bc=(synth.PERIODIC, 0))
+        assert mm.solve_submit(srv, bad)[0] == mm.MM_EINVAL
+    finally:
+        srv.close()
+    assert all(o[0] == mm.MM_OK for o in outs)
+    assert relerr(outs[0][1], spectral.solve(p2)) <= 1e-12
+    assert relerr(outs[1][1], spectral.solve(p1)) <= 1e-12
+    assert relerr(outs[2][1], S.solve(plain)) <= 1e-12
