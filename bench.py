@@ -11,7 +11,7 @@ parity tests).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes fp64,fp32,...]
 
-Prints one JSON line. --gpus N > 1 exits: this build runs on one GPU.
+Prints one JSON line. --gpus N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -229,7 +229,7 @@ def cpu_baseline(p, steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
     import paper_2303_15861_amd as mm
