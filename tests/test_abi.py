@@ -43,3 +43,44 @@ def test_binding_fails_loudly_without_library(tmp_path):
     import paper_2303_15861_amd as mm
     with pytest.raises(ImportError):
         mm.load_library(str(tmp_path / "libmumode.so"))
+
+
+def _c_layout(struct, fields):
+    """sizeof and field offsets of a header struct, from a C program built with gcc."""
+    import subprocess
+    import tempfile
+    body = "\n".join(f'  printf("%s %zu\\n", "{f}", offsetof({struct}, {f}));' for f in fields)
+    src = f"""#include <stddef.h>
+#include <stdio.h>
+#include "mumode.h"
+int main(void) {{
+  printf("sizeof %zu\\n", sizeof({struct}));
+{body}
+  return 0;
+}}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "l.c")
+        exe = os.path.join(d, "l")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    return {k: int(v) for k, v in (ln.split() for ln in out.splitlines())}
+
+
+@pytest.mark.parametrize("cls,struct", [("MMProblem", "mm_problem"), ("MMRequest", "mm_request"),
+                                        ("MMStats", "mm_stats")])
+def test_binding_structs_match_the_header(cls, struct):
+    """The ctypes mirrors of the ABI structs have the header's size and field offsets (the
+    binding's field names map to the header's: lam -> lambda)."""
+    import shutil
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    import paper_2303_15861_amd as mm
+    S = getattr(mm, cls)
+    cnames = {"lam": "lambda"}
+    fields = [f for f, _ in S._fields_]
+    lay = _c_layout(struct, [cnames.get(f, f) for f in fields])
+    assert lay["sizeof"] == ctypes.sizeof(S)
+    for f in fields:
+        assert lay[cnames.get(f, f)] == getattr(S, f).offset, f
