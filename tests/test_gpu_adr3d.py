@@ -270,3 +270,28 @@ def test_mixed_precision_actions_with_neumann_factors(mm, ctx, prec):
     else:
         bar = 3 * (2 * (u24 if prec == "fp32" else 2.0 ** -16) + 16 * u24)
     assert relerr(got, ref) <= bar
+
+
+def test_fig_cpudiagadr3d_printed_errors_at_n60(mm, ctx):
+    """Figure fig:cpudiagadr3d, the paper's timing size (N = 60, b = -0.01, T = 1/4): the
+    errors of its mu-mode runs (SLE, LE at m = 2^9..2^12; SL2, L2a at m = 2^5..2^8, each at
+    its lambda of Table tab:adr3d_lambdaopt) reproduced with GPU solves alone against a
+    GPU Lawson2b reference at lambda = 1 with 2^15 steps (2^14 and 2^15 agree to 1.2e-10):
+    every point within 5e-5 relative + 2e-10."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "fig_cpudiagadr3d_mumode_errors.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 16
+
+    def run(p):
+        op = mm.setup_problem(ctx, p)
+        u = dev(p.u0)
+        mm.step(op, u, p.steps)
+        assert mm.mm_check(op) == mm.MM_OK
+        out = host(u)
+        op.close()
+        return out
+
+    ref = run(synth.paper3d_problem(60, -0.01, 1.0, scheme="l2b", steps=2 ** 15))
+    for sch, lam, m, err in rows:
+        e = Sch.rel_inf_error(run(synth.paper3d_problem(60, -0.01, float(lam), scheme=sch, steps=int(m))), ref)
+        assert abs(e - float(err)) <= 5e-5 * float(err) + 2e-10, (sch, lam, m, e, err)
