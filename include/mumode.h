@@ -150,12 +150,14 @@ typedef struct mm_ctx mm_ctx;
 typedef struct mm_op mm_op;
 typedef struct mm_server mm_server;
 
-/* Create a context on HIP device `device` (it becomes current on the calling thread). */
+/* Create a context on HIP device `device` (it becomes current on the calling thread).
+ * *out is set to NULL first, so it is NULL after any failure. MM_EINVAL for out ==
+ * NULL, MM_EDEVICE for a device that does not exist, MM_ENOMEM. */
 mm_status mm_ctx_create(int device, mm_ctx** out);
 void mm_ctx_destroy(mm_ctx* ctx);
 /* Message of the last failure on this context (static storage, never NULL). */
 const char* mm_last_error(const mm_ctx* ctx);
-/* Library version string and the number of exported entry points. */
+/* Library version string (static storage). */
 const char* mm_version(void);
 
 /* Build the operator for one problem and time step (Sec. 3 extraction, Sec. 5.2
@@ -296,8 +298,11 @@ typedef struct {
 } mm_stats;
 
 /* max_active: concurrent solves on the device; hbm_budget: bytes the active solves may
- * hold (0 = 90% of free device memory at creation). */
+ * hold (0 = 90% of free device memory at creation). *out is set to NULL first (when out
+ * is not NULL). MM_EINVAL for out == NULL or max_active < 1. */
 mm_status mm_server_create(int device, int max_active, int64_t hbm_budget, mm_server** out);
+/* Stop taking requests, run every queued and running request to its end, then release
+ * the server; results that were not polled are discarded. */
 void mm_server_destroy(mm_server* srv);
 /* Copy the request in and queue it; returns its id. MM_ENOMEM if the request alone
  * exceeds the budget, MM_EINVAL for a malformed request. */

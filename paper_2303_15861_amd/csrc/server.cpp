@@ -316,8 +316,9 @@ struct mm_server {
 extern "C" {
 
 mm_status mm_server_create(int device, int max_active, int64_t hbm_budget, mm_server** out) {
-  if (!out || max_active < 1) return MM_EINVAL;
+  if (!out) return MM_EINVAL;
   *out = nullptr;
+  if (max_active < 1) return MM_EINVAL;
   auto* s = new mm_server();
   s->device = device;
   s->max_active = max_active;

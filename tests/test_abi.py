@@ -84,3 +84,43 @@ def test_binding_structs_match_the_header(cls, struct):
     assert lay["sizeof"] == ctypes.sizeof(S)
     for f in fields:
         assert lay[cnames.get(f, f)] == getattr(S, f).offset, f
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_entry_points_reject_null_handles_before_any_device_call():
+    """Every entry point checks its handles and pointers first and returns MM_EINVAL (or
+    the documented neutral value) without touching the device, so these calls are safe on
+    a machine with no GPU."""
+    import paper_2303_15861_amd as mm
+    lib = mm.load_library()
+    EINVAL = mm.MM_EINVAL
+    out = ctypes.c_void_p(123)
+    assert lib.mm_ctx_create(0, None) == EINVAL
+    assert lib.mm_last_error(None).decode() == "null context"
+    prob = mm.MMProblem()
+    assert lib.mumode_setup(None, ctypes.byref(prob), 0.1, 0, 0, 0, 0, 0, ctypes.byref(out)) == EINVAL
+    assert lib.mumode_info(None, None, None) == EINVAL
+    assert lib.mumode_get_factor(None, 0, 0, None) == EINVAL
+    assert lib.remainder_eval(None, None, None, None, None, None) == EINVAL
+    assert lib.mumode_expv(None, None, 0, None, None, None) == EINVAL
+    assert lib.mumode_phi1v(None, None, None, None, None) == EINVAL
+    assert lib.lawson_step(None, None, None, 1, None) == EINVAL
+    assert lib.erk_step(None, None, None, 1, None) == EINVAL
+    assert lib.mm_check(None, None, None) == EINVAL
+    assert lib.mm_synchronize(None) == EINVAL
+    assert lib.mm_timing_enable(None, 1) == EINVAL
+    assert lib.mm_set_gemm_tile(None, 64) == EINVAL
+    assert lib.mm_set_graph_steps(None, 1) == EINVAL
+    assert lib.mm_set_small_fused(None, 1) == EINVAL
+    assert lib.mm_timing_read(None, 0, None, None, None) == EINVAL
+    lib.mumode_destroy(None)
+    srv = ctypes.c_void_p(123)
+    assert lib.mm_server_create(0, 0, 0, ctypes.byref(srv)) == EINVAL   # max_active < 1
+    assert srv.value is None                                             # cleared on failure
+    assert lib.mm_server_create(0, 4, 0, None) == EINVAL
+    rid = ctypes.c_uint64(0)
+    req = mm.MMRequest()
+    assert lib.solve_submit(None, ctypes.byref(req), ctypes.byref(rid)) == EINVAL
+    assert lib.solve_poll(None, 1, None, None) == EINVAL
+    assert lib.mm_server_clock(None) == 0.0
+    lib.mm_server_destroy(None)
