@@ -123,8 +123,11 @@ enum { MM_ETD2RK = 0, MM_ERK2P1 = 1, MM_EE = 2, MM_ERK2P2 = 3 };
  * eq. (eq:nonlin): sum_mu d_mu((a_mumu - lam a^max_mumu) d_mu u) (MM_FORM_NONDIV:
  * (a_mumu - lam a^max_mumu) d_mumu u) + sum_mu d_mu((b_mu - beta_bar_mu) u) + r(u), and
  * F = A u + g. Exact phi (q = 0) is not offered for periodic problems. Their remainder
- * works in scratch held by the op, so calls on one periodic op must not overlap (on
- * different streams), as for the step calls of every op.                            */
+ * works in scratch held by the op (three grid functions per axis) and runs the chain of
+ * every axis after the first on a side stream of the op, forked from and joined back to
+ * the call's stream with events (so it stays stream-ordered and can be captured); calls
+ * on one periodic op must not overlap (on different streams), as for the step calls of
+ * every op.                                                                          */
 enum { MM_BC_DIRICHLET = 0, MM_BC_NEUMANN = 1, MM_BC_PERIODIC = 2 };
 enum { MM_FORM_FLUX = 0, MM_FORM_NONDIV = 1 };
 

@@ -288,18 +288,31 @@ hipError_t mode_product64(const mm_op* op, int mu, const double* M, const double
 // Remainder of a periodic problem (pseudo-spectral, FP64 whatever the op's precision):
 // G = r(u); per axis T1 = D x_mu u, the pointwise pass, G += D1 x_mu T2; for F also
 // G += A_mu x_mu u; then the stage outputs of `a` from G (the stencil's contract).
+// The chains of the axes are independent up to the stage outputs: axis 0 runs on s, every
+// further axis on a side stream of its own (forked from and joined back to s with events,
+// so the calls stay stream-ordered and capturable) into its own accumulator. A mode
+// product of a 256-point axis has only sixteen workgroups, so running the chains side by
+// side fills more of the chip than running them one after another.
 hipError_t spectral_remainder(const mm_op* op, const StencilArgs& a, hipStream_t s) {
   const int64_t dof = op->dof;
-  double* G = op->spec_ws;
-  double* T1 = G + dof;
-  double* T2 = T1 + dof;
   const bool nondiv = op->form == MM_FORM_NONDIV;
-  hipError_t e = launch_spec_react(G, a.u, dof, op->r, s);
+  hipError_t e = hipSuccess;
+  if (op->d > 1) {
+    e = hipEventRecord(op->spec_fork, s);
+    for (int mu = 1; mu < op->d && e == hipSuccess; ++mu) e = hipStreamWaitEvent(op->spec_side[mu - 1], op->spec_fork, 0);
+  }
+  const double* Gs[3] = {nullptr, nullptr, nullptr};
   for (int mu = 0; mu < op->d && e == hipSuccess; ++mu) {
+    const hipStream_t sm = mu == 0 ? s : op->spec_side[mu - 1];
+    double* G = op->spec_ws + 3 * mu * dof;
+    double* T1 = G + dof;
+    double* T2 = T1 + dof;
+    Gs[mu] = G;
     const int64_t nn = (int64_t)op->n[mu] * op->n[mu];
     const double* D1 = op->dmat[mu];
     const double* D2 = D1 + nn;
-    if ((e = mode_product64(op, mu, nondiv ? D2 : D1, a.u, T1, nullptr, s)) != hipSuccess) break;
+    if ((e = mu == 0 ? launch_spec_react(G, a.u, dof, op->r, sm) : launch_fill(G, 0.0, dof, sm)) != hipSuccess) break;
+    if ((e = mode_product64(op, mu, nondiv ? D2 : D1, a.u, T1, nullptr, sm)) != hipSuccess) break;
     SpecMidArgs m{};
     m.G = G;
     m.T2 = T2;
@@ -312,15 +325,16 @@ hipError_t spectral_remainder(const mm_op* op, const StencilArgs& a, hipStream_t
     m.beta_bar = op->beta_bar[mu];
     m.n = dof;
     m.nondiv = nondiv;
-    if ((e = launch_spec_mid(m, s)) != hipSuccess) break;
+    if ((e = launch_spec_mid(m, sm)) != hipSuccess) break;
     // the outer derivative: of the flux, or (non-divergence form) of the advected u only
-    if (!nondiv || op->vel || op->beta[mu] != op->beta_bar[mu]) e = mode_product64(op, mu, D1, T2, G, G, s);
+    if (!nondiv || op->vel || op->beta[mu] != op->beta_bar[mu])
+      if ((e = mode_product64(op, mu, D1, T2, G, G, sm)) != hipSuccess) break;
+    if (a.full && (e = mode_product64(op, mu, D1 + 2 * nn, a.u, G, G, sm)) != hipSuccess) break;
+    if (mu > 0 && (e = hipEventRecord(op->spec_join[mu - 1], sm)) == hipSuccess)
+      e = hipStreamWaitEvent(s, op->spec_join[mu - 1], 0);
   }
-  if (a.full)
-    for (int mu = 0; mu < op->d && e == hipSuccess; ++mu)
-      e = mode_product64(op, mu, op->dmat[mu] + 2 * (int64_t)op->n[mu] * op->n[mu], a.u, G, G, s);
   if (e != hipSuccess) return e;
-  return launch_spec_combine(G, a, dof, s);
+  return launch_spec_combine(Gs, a, dof, s);
 }
 
 hipError_t stencil(const mm_op* op, const StencilArgs& a, hipStream_t s) {
@@ -756,6 +770,11 @@ void mumode_destroy(mm_op* op) {
     if (op->dmat_owned[mu]) dev_free(op, op->dmat[mu]);
   dev_free(op, op->vel);
   dev_free(op, op->spec_ws);
+  for (int i = 0; i < 2; ++i) {
+    if (op->spec_side[i]) hipStreamDestroy(op->spec_side[i]);
+    if (op->spec_join[i]) hipEventDestroy(op->spec_join[i]);
+  }
+  if (op->spec_fork) hipEventDestroy(op->spec_fork);
   for (int i = 0; i < 6; ++i) dev_free(op, op->buf[i]);
   dev_free(op, op->vdig);
   dev_free(op, op->vexp);
@@ -1060,9 +1079,21 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
           return fail(MM_EDEVICE);
         }
     }
-    if ((rc = dev_alloc(op, &op->spec_ws, 3 * op->dof)) != MM_OK) {
+    if ((rc = dev_alloc(op, &op->spec_ws, 3 * (int64_t)op->d * op->dof)) != MM_OK) {
       hipFreeAsync(ws, st);
       return fail(rc);
+    }
+    for (int mu = 1; mu < op->d; ++mu)
+      if (hipStreamCreateWithFlags(&op->spec_side[mu - 1], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&op->spec_join[mu - 1], hipEventDisableTiming) != hipSuccess) {
+        hipFreeAsync(ws, st);
+        set_err(ctx, "stream or event creation failed");
+        return fail(MM_EDEVICE);
+      }
+    if (op->d > 1 && hipEventCreateWithFlags(&op->spec_fork, hipEventDisableTiming) != hipSuccess) {
+      hipFreeAsync(ws, st);
+      set_err(ctx, "event creation failed");
+      return fail(MM_EDEVICE);
     }
   }
   hipFreeAsync(ws, st);

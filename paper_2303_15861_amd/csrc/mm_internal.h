@@ -131,7 +131,7 @@ hipError_t launch_stencil(int d, const StencilArgs& a, hipStream_t s);
 hipError_t launch_build_circulant(double* M, int n, const double* col, hipStream_t s);
 hipError_t launch_spec_react(double* G, const double* u, int64_t n, const double* r, hipStream_t s);
 hipError_t launch_spec_mid(const SpecMidArgs& a, hipStream_t s);
-hipError_t launch_spec_combine(const double* G, const StencilArgs& a, int64_t n, hipStream_t s);
+hipError_t launch_spec_combine(const double* const (&G)[3], const StencilArgs& a, int64_t n, hipStream_t s);
 hipError_t launch_max_reduce(const double* x, int64_t n, double* partial, int nparts, double* out,
                              hipStream_t s);
 // last_sub: the entry (n-1, n-2) (sub for a Toeplitz matrix)
@@ -209,7 +209,9 @@ struct mm_op {
   double* vel = nullptr;               // nullable: d velocity fields (dof each)
   double* dmat[3] = {nullptr, nullptr, nullptr};   // per axis [D1 | D2 | A], n x n each
   bool dmat_owned[3] = {false, false, false};
-  double* spec_ws = nullptr;           // G, T1, T2 (dof each)
+  double* spec_ws = nullptr;           // per axis G, T1, T2 (dof each)
+  hipStream_t spec_side[2] = {nullptr, nullptr};   // streams of the x2 and x3 chains
+  hipEvent_t spec_fork = nullptr, spec_join[2] = {nullptr, nullptr};
   bool exact = false;                  // MM_ERK with exact phi1 through the eigenbasis
   int nfac = 1;                        // factors stored per axis
   double* ev[3] = {nullptr, nullptr, nullptr};   // exact: 1D eigenvalues per axis

@@ -61,9 +61,9 @@ int64_t footprint(const mm_request& r) {
     nmax = std::max<int64_t>(nmax, r.n[mu]);
   }
   // periodic: d diffusion fields (and the velocity copy), [D1 | D2 | A] per axis and the
-  // remainder's three scratch grid functions
+  // remainder's three scratch grid functions per axis
   const bool periodic = r.bc[0] == MM_BC_PERIODIC;
-  if (periodic) na = r.d * dof * (r.velocity ? 2 : 1) + 3 * dof + 3 * fac;
+  if (periodic) na = r.d * dof * (r.velocity ? 2 : 1) + 3 * r.d * dof + 3 * fac;
   // a, u, 4 scratch grid functions, factors (+ mixed copies), Pade workspace (7 n^2)
   return 8 * (na + 5 * dof + 2 * fac + 7 * nmax * nmax) + 4096;
 }

@@ -5,15 +5,16 @@
 // path) instead of an FFT. This file holds the element-wise passes of the spectral
 // remainder and the circulant builder; the GEMMs are the contraction kernels.
 //
-// The remainder of a periodic problem is evaluated in four kinds of passes:
-//   G  = r(u)                                                    (spec_react)
+// The remainder of a periodic problem is evaluated in four kinds of passes, each axis mu
+// accumulating into its own G_mu:
+//   G_0 = r(u) (spec_react), G_mu = 0 for mu > 0 (fill)
 //   per axis mu:  T1 = D_mu x_mu u  (D1 for the flux form, D2 for the non-divergence form)
 //                 flux:   T2 = (a_mu - lam a^max_mu) T1 + (b_mu - beta_bar_mu) u
-//                 nondiv: G += (a_mu - lam a^max_mu) T1,  T2 = (b_mu - beta_bar_mu) u
+//                 nondiv: G_mu += (a_mu - lam a^max_mu) T1,  T2 = (b_mu - beta_bar_mu) u
 //                                                            (spec_mid)
-//                 G += D1_mu x_mu T2                         (GEMM with accumulation)
-//   [F: G += A_mu x_mu u for every axis]
-//   outputs of the stage update from G                       (spec_combine)
+//                 G_mu += D1_mu x_mu T2                      (GEMM with accumulation)
+//                 [F: G_mu += A_mu x_mu u]
+//   outputs of the stage update from G_0 + G_1 [+ G_2]       (spec_combine)
 // b_mu is the velocity field of the problem or, without one, its constant velocity.
 #include "mm_internal.h"
 
@@ -70,12 +71,16 @@ hipError_t launch_spec_mid(const SpecMidArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// the output contract of the stencil: s = G - sub; out0 = base0 + c0 s (0 + c0 s without
-// base0), out1 likewise; the sticky flag is raised when out0 is not finite
-__global__ __launch_bounds__(256) void spec_combine_kernel(const double* __restrict__ G, StencilArgs p, int64_t n) {
+// the output contract of the stencil: s = G_0 + G_1 + G_2 - sub (absent terms skipped);
+// out0 = base0 + c0 s (0 + c0 s without base0), out1 likewise; the sticky flag is raised
+// when out0 is not finite
+__global__ __launch_bounds__(256) void spec_combine_kernel(const double* __restrict__ G0, const double* __restrict__ G1,
+                                                           const double* __restrict__ G2, StencilArgs p, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
-  double g = G[e];
+  double g = G0[e];
+  if (G1) g += G1[e];
+  if (G2) g += G2[e];
   if (p.sub) g -= p.sub[e];
   const double o0 = (p.base0 ? p.base0[e] : 0.0) + p.c0 * g;
   double o1 = 0.0;
@@ -94,8 +99,8 @@ __global__ __launch_bounds__(256) void spec_combine_kernel(const double* __restr
   }
 }
 
-hipError_t launch_spec_combine(const double* G, const StencilArgs& a, int64_t n, hipStream_t s) {
-  spec_combine_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(G, a, n);
+hipError_t launch_spec_combine(const double* const (&G)[3], const StencilArgs& a, int64_t n, hipStream_t s) {
+  spec_combine_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(G[0], G[1], G[2], a, n);
   return hipGetLastError();
 }
 
