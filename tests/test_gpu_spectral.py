@@ -326,3 +326,39 @@ def test_periodic_with_forced_tiles(mm, ctx, tile):
         op.close()
     finally:
         ctx.set_gemm_tile(0)
+
+
+def test_periodic_3d_side_streams_under_graphs_and_a_user_stream(mm, ctx):
+    """The 3D remainder forks the x2 and x3 chains onto two side streams of the op and joins
+    them back with events. Recorded into step graphs (three replays of 3 steps, each
+    replay checked against direct launches, with eager work between) and run on a
+    non-default stream, the steps give the same bits as direct launches on the default
+    stream, and agree with the oracle."""
+    import torch
+    p = random_periodic((10, 9, 8), 11, scheme="l2b", steps=9, tau=4e-3)
+    op = mm.setup_problem(ctx, p)
+    try:
+        ref = []
+        u = dev(p.u0)
+        for _ in range(3):
+            mm.step(op, u, 3)
+            ref.append(host(u))
+        assert relerr(ref[-1], spectral.solve(p)) <= FP64_TOL
+        ctx.set_graph_steps(3)
+        try:
+            u = dev(p.u0)
+            for r in range(3):
+                mm.step(op, u, 3)
+                assert np.array_equal(host(u), ref[r]), r
+                junk = torch.randn(4096, device="cuda", dtype=torch.float64).sum().item()   # eager work
+                assert np.isfinite(junk)
+        finally:
+            ctx.set_graph_steps(0)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            u = dev(p.u0)
+            mm.step(op, u, 9, stream=s)
+        s.synchronize()
+        assert np.array_equal(host(u), ref[-1])
+    finally:
+        op.close()
