@@ -241,9 +241,12 @@ mm_status mm_timing_read(mm_ctx* ctx, int kind, int64_t* launches, double* total
 
 /* Workgroup tile of the mode-product kernels launched through this context (tuning and
  * tests). tile = 0 (default): 128 x 128 tiles, or 64 x 64 when a launch has fewer
- * 128-tiles than the chip holds at once; 64 or 128 force that size. Both give results
- * that agree to rounding (the sum over k runs in the same order in both). Other values:
- * MM_EINVAL. Takes effect for launches enqueued after the call. */
+ * 128-tiles than the chip holds at once, or in FP64 32 x 32 when it has fewer 64-tiles
+ * than the chip has compute units; 32, 64 or 128 force that size (32 applies to FP64
+ * launches, the other precisions take 64 then). FP64 results are bit-identical across
+ * tile sizes (every output's sum over k runs in the same order); in the other precisions
+ * 64 and 128 agree likewise. Other values: MM_EINVAL. Takes effect for launches enqueued
+ * after the call. */
 mm_status mm_set_gemm_tile(mm_ctx* ctx, int tile);
 
 /* Small 2D Lawson solves (n1, n2 <= 64, FP64, Lawson-Euler or Lawson2b) run their whole

@@ -185,7 +185,7 @@ class Context:
         self.check(lib().mm_timing_enable(self._h, int(enable)), "mm_timing_enable")
 
     def set_gemm_tile(self, tile: int):
-        """0: automatic; 64 or 128: force that workgroup tile for mode products."""
+        """0: automatic; 32 (FP64 only), 64 or 128: force that workgroup tile for mode products."""
         self.check(lib().mm_set_gemm_tile(self._h, int(tile)), "mm_set_gemm_tile")
 
     def set_small_fused(self, enable: bool):

@@ -1683,8 +1683,8 @@ mm_status mm_timing_enable(mm_ctx* ctx, int enable) {
 
 mm_status mm_set_gemm_tile(mm_ctx* ctx, int tile) {
   if (!ctx) return MM_EINVAL;
-  if (tile != 0 && tile != 64 && tile != 128) {
-    set_err(ctx, "gemm tile must be 0, 64 or 128");
+  if (tile != 0 && tile != 32 && tile != 64 && tile != 128) {
+    set_err(ctx, "gemm tile must be 0, 32, 64 or 128");
     return MM_EINVAL;
   }
   ctx->gemm_tile = tile;

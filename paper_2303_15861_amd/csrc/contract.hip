@@ -587,22 +587,33 @@ hipError_t launch_tile(int prec, GemmArgs& g, hipStream_t s) {
     else gemm_f64<0, T><<<grid, fblock, 0, s>>>(g);
     return hipGetLastError();
   }
-  return g.b_trans ? launch_mixed<1, T>(prec, g, grid, block, s) : launch_mixed<0, T>(prec, g, grid, block, s);
+  if constexpr (T == 32) {
+    return hipErrorInvalidValue;   // 32-tiles are FP64 only
+  } else {
+    return g.b_trans ? launch_mixed<1, T>(prec, g, grid, block, s) : launch_mixed<0, T>(prec, g, grid, block, s);
+  }
 }
 
 // Workgroups of 128-tiles that fill every compute unit at their occupancy (256 CUs x 2).
 constexpr int64_t kFillSlots = 512;
+// FP64 launches with fewer 64-tiles than compute units take 32-tiles (four waves of
+// 16 x 16): four times the workgroups, and a quarter of the serial MFMA chain per wave,
+// which is what bounds such a launch (the small grids of the paper's own examples).
+constexpr int64_t kComputeUnits = 256;
 
-int choose_tile(const GemmArgs& g) {
+int choose_tile(const GemmArgs& g, int prec) {
+  if (g.tile == 32) return prec == MM_FP64 ? 32 : 64;
   if (g.tile == 64 || g.tile == 128) return g.tile;
   const int64_t t128 = (int64_t)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.inner * g.groups;
-  return t128 < kFillSlots ? 64 : 128;
+  if (t128 >= kFillSlots) return 128;
+  const int64_t t64 = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.inner * g.groups;
+  return prec == MM_FP64 && t64 < kComputeUnits ? 32 : 64;
 }
 
 hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.inner <= 0 || g.groups <= 0 || g.groups > kMaxGroups)
     return hipErrorInvalidValue;
-  if (g.tile != 0 && g.tile != 64 && g.tile != 128) return hipErrorInvalidValue;
+  if (g.tile != 0 && g.tile != 32 && g.tile != 64 && g.tile != 128) return hipErrorInvalidValue;
   if (prec == MM_SLICED && (g.in_f32 || g.out_f32)) return hipErrorInvalidValue;
   // in-batch offsets are 32-bit
   const int64_t lim = (int64_t)1 << 31;
@@ -624,7 +635,11 @@ hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s) {
     const int ldf = g.b_trans ? g.lda : g.ldb;
     if (ldf < fac_ld(g.K) || ldf % kFacPad != 0) return hipErrorInvalidValue;
   }
-  return choose_tile(g) == 64 ? launch_tile<64>(prec, g, s) : launch_tile<128>(prec, g, s);
+  switch (choose_tile(g, prec)) {
+    case 32: return launch_tile<32>(prec, g, s);
+    case 64: return launch_tile<64>(prec, g, s);
+    default: return launch_tile<128>(prec, g, s);
+  }
 }
 
 }  // namespace mm

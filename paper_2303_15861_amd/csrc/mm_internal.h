@@ -118,9 +118,10 @@ bool small2d_fits(int d, int n1, int n2);
 hipError_t launch_lawson_small2d(const SmallArgs& a, bool l2b, hipStream_t s);
 
 hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s);
-// Tile size the launcher takes for g (g.tile if set, else 64 when 128-tiles would not
-// fill the chip once).
-int choose_tile(const GemmArgs& g);
+// Tile size the launcher takes for g in precision prec (g.tile if set, else 64 when
+// 128-tiles would not fill the chip once, and in FP64 32 when 64-tiles would not give
+// every compute unit one).
+int choose_tile(const GemmArgs& g, int prec);
 // MM_SLICED mode product (64 x 64 tiles; factor operand as digit planes).
 hipError_t launch_gemm_sliced(GemmArgs& g, hipStream_t s);
 // Split rows x k (row stride lds) into S digit planes of row stride ldd (plane stride

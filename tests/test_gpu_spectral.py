@@ -308,9 +308,9 @@ def test_fig1_printed_errors_with_gpu_solves(mm, ctx):
     assert checked == 20
 
 
-@pytest.mark.parametrize("tile", [64, 128])
+@pytest.mark.parametrize("tile", [32, 64, 128])
 def test_periodic_with_forced_tiles(mm, ctx, tile):
-    """Both workgroup tiles of the mode products (ragged 40 x 36 x 30 grid, the 128-tile
+    """Every workgroup tile of the mode products (ragged 40 x 36 x 30 grid, the 128-tile
     kernels otherwise reserved for large grids) on the spectral remainder's in-place
     accumulation and on Lawson2b steps."""
     p = random_periodic((40, 36, 30), 11, scheme="l2b", steps=3, tau=4e-3)

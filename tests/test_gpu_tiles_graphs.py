@@ -56,7 +56,7 @@ def test_tiles_agree_and_match_oracle(mm, n, prec):
     V = np.random.default_rng(9).standard_normal(p.shape)
     ref = expo.KronOperator(p.n, adr.extracted_amax(p.a), p.lam, p.beta_bar, p.tau).expv(1.0, V)
     got = {}
-    for tile in (64, 128):
+    for tile in (32, 64, 128):   # 32 applies to FP64; the other precisions take 64 then
         ctx = mm.Context(0)
         ctx.set_gemm_tile(tile)
         op = mm.setup_problem(ctx, p, prec=prec)
@@ -66,6 +66,7 @@ def test_tiles_agree_and_match_oracle(mm, n, prec):
         op.close()
         ctx.close()
     assert np.array_equal(got[64], got[128])
+    assert np.array_equal(got[32], got[64])
     assert relerr(got[64], ref) <= ACTION_TOL[prec]
 
 
