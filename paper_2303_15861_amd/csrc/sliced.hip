@@ -34,7 +34,9 @@ namespace {
 
 constexpr int T8 = 64;      // workgroup tile
 constexpr int KC8 = 64;     // k per chunk (two int8 MFMA k-steps)
-constexpr int PI8 = 80;     // LDS row pitch in bytes (16 lanes of 16-byte reads from consecutive rows hit all 64 banks once)
+constexpr int PI8 = 80;     // LDS row pitch in bytes (chosen so that 16 lanes of 16-byte reads from
+                            // consecutive rows would hit 64 banks once; gfx950's bank-conflict
+                            // counter still counts conflicts on this kernel's LDS accesses)
 constexpr int TH = 256;
 
 // Balanced base-256 digits of x relative to exponent e, packed: byte i of (lo, hi) is
