@@ -14,6 +14,15 @@ D = diag(rho^j), rho = sqrt(s/t), to the symmetric tridiagonal matrix with
 off-diagonal sigma = sign(t) sqrt(s t), whose eigenvectors are the columns of the
 orthogonal DST-I matrix S[j,k] = sqrt(2/(n+1)) sin(j k pi/(n+1)) with eigenvalues
 delta + 2 sigma cos(k pi/(n+1)). Hence exp(c T) = D S diag(exp(c ev)) S D^{-1}.
+Two rewritings that are exact in real arithmetic keep the rounding at the level of
+the data: the eigenvalues are evaluated as (delta + 2 sigma) - 4 sigma
+sin^2(k pi/(2(n+1))) (half-angle identity), with delta + 2 sigma =
+(delta^2 - 4 sigma^2)/(delta - 2 sigma) = 4 adv^2/(delta - 2 sigma) for
+s = diff - adv, t = diff + adv, delta = -2 diff -- the cosine form loses about
+2 |delta| u to cancellation in the smallest eigenvalues, which the stiffest
+exponentials turn into relative errors near 1e-13; and the sine arguments
+j k pi/(n+1) are reduced exactly, j k mod 2(n+1), before the multiplication by
+pi/(n+1).
 
 phi-functions (Sec. 1): phi1(z) = (e^z - 1)/z, phi2(z) = (phi1(z) - 1)/z.
 phi1 of a Kronecker sum is not a product of 1D functions; it is evaluated
@@ -38,7 +47,8 @@ from .adr import axis_of
 def dst1_matrix(n: int) -> np.ndarray:
     """Orthogonal symmetric DST-I matrix S[j,k] = sqrt(2/(n+1)) sin(j k pi/(n+1)), j,k=1..n."""
     j = np.arange(1, n + 1)
-    return np.sqrt(2.0 / (n + 1)) * np.sin(np.outer(j, j) * np.pi / (n + 1))
+    m = np.outer(j, j) % (2 * (n + 1))          # sin(x pi/(n+1)) has period 2(n+1) in x
+    return np.sqrt(2.0 / (n + 1)) * np.sin(m * np.pi / (n + 1))
 
 
 def toeplitz_eigen(n: int, a_max: float, lam: float, beta_bar: float):
@@ -55,7 +65,9 @@ def toeplitz_eigen(n: int, a_max: float, lam: float, beta_bar: float):
     rho = np.sqrt(s / t)
     sigma = np.sign(t) * np.sqrt(s * t)
     k = np.arange(1, n + 1)
-    ev = delta + 2.0 * sigma * np.cos(k * np.pi / (n + 1))
+    # delta + 2 sigma cos(theta_k) without cancellation (module docstring)
+    c0 = 4.0 * adv ** 2 / (delta - 2.0 * sigma) if delta != 2.0 * sigma else delta + 2.0 * sigma
+    ev = c0 - 4.0 * sigma * np.sin(k * np.pi / (2 * (n + 1))) ** 2
     S = dst1_matrix(n)
     jj = np.arange(1, n + 1).astype(np.float64)
     Dg = rho ** jj

@@ -128,3 +128,34 @@ def test_sine_series_closed_form(sizes):
     for scheme in ("le", "l2b"):
         u = S.solve(p, scheme=scheme)
         assert np.max(np.abs(u - ref)) <= 1e-13 * np.max(np.abs(ref)), scheme
+
+
+def _expm_longdouble(M):
+    """exp(M) in extended precision (numpy long double) by a Taylor series of M/2^s with
+    |M/2^s|_1 <= 1/4, then s squarings: an independent method whose rounding (~1e-19 per
+    operation, doubled by each squaring) is far below FP64's."""
+    A = np.asarray(M, dtype=np.longdouble)
+    nrm = float(np.max(np.sum(np.abs(A), axis=0)))
+    s = max(0, int(np.ceil(np.log2(max(nrm, 1e-300) / 0.25))))
+    B = A / np.longdouble(2.0) ** s
+    X = np.eye(A.shape[0], dtype=np.longdouble)
+    term = np.eye(A.shape[0], dtype=np.longdouble)
+    for k in range(1, 30):
+        term = term @ B / k
+        X = X + term
+    for _ in range(s):
+        X = X @ X
+    return X
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("n,amax,ct", [(255, 1.9, 5e-3), (127, 1.465, 5e-3)])
+def test_stiff_factor_vs_extended_precision(n, amax, ct):
+    """Stiff factors (|ct A|_1 up to 2.5e3): the closed form stays within a few units of
+    FP64 rounding of an extended-precision scaling-and-squaring exponential. Evaluating
+    the eigenvalues as delta + 2 sigma cos(theta) instead loses ~2 |delta ct| u to
+    cancellation (1.4e-13 relative at the first size) and fails this bar."""
+    E = expo.exp_factor(n, amax, 1.0, 0.0, ct)
+    R = _expm_longdouble(ct * operator_1d(n, amax, 1.0, 0.0))
+    err = float(np.max(np.abs(E - R)) / np.max(np.abs(R)))
+    assert err <= 5e-15, err
