@@ -39,9 +39,9 @@ DESCRIPTION = {
                             "200 steps",
     "3d_n383_etd2rk_exact": "3D Dirichlet ADR 383^3 interior, anisotropic a in (0.01, 2), ETD2RK with exact "
                             "phi1 (eigenbasis), tau=2e-3, 50 steps",
-    "3d_paper_n60_sl2": "the 3D ADR problem of Sec. 5.3 (a Lap u, Dirichlet at 0, Neumann at 1), N = 60, b = -0.01, "
+    "3d_paper_n60_sl2": "the 3D ADR problem of Sec. 5.2 (a Lap u, Dirichlet at 0, Neumann at 1), N = 60, b = -0.01, "
                         "SL2 with lambda = 0.53, 256 steps to T = 1/4",
-    "2d_paper_n256_sl2": "the periodic 2D ADR problem of Sec. 5.2 (pseudo-spectral, circulant factors), N = 256, "
+    "2d_paper_n256_sl2": "the periodic 2D ADR problem of Sec. 5.1 (pseudo-spectral, circulant factors), N = 256, "
                          "SL2 with lambda = 0.57, 256 steps to T = 4",
 }
 HBM_PEAK = 8.0e12

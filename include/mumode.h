@@ -102,7 +102,7 @@ enum { MM_LAWSON = 0, MM_ERK = 1 };
 enum { MM_LAWSON_EULER = 0, MM_LAWSON2B = 1, MM_SLE = 2, MM_LAWSON2A = 3, MM_SL2 = 4 };
 enum { MM_ETD2RK = 0, MM_ERK2P1 = 1, MM_EE = 2, MM_ERK2P2 = 3 };
 
-/* Boundary data per axis (Sec. 5.3, eq. (eq:adr3d)): MM_BC_DIRICHLET is zero data at
+/* Boundary data per axis (Sec. 5.2, eq. (eq:adr3d)): MM_BC_DIRICHLET is zero data at
  * x = 0 and x = 1 (n unknowns at i/(n+1)); MM_BC_NEUMANN is zero data at x = 0 and a zero
  * normal derivative at x = 1 (n unknowns at i/n, i = 1..n, the value beyond x = 1 taken as
  * the mirror u_{n+1} = u_{n-1}, so the 1D operator's last row reads [.., 2, -2]/h^2 and
@@ -110,7 +110,7 @@ enum { MM_ETD2RK = 0, MM_ERK2P1 = 1, MM_EE = 2, MM_ERK2P2 = 3 };
  * with face means of the nodal a (eq. (eq:nonlin)); MM_FORM_NONDIV is a Lap u, the form
  * of eq. (eq:adr3d), which reads a at the unknowns only.
  *
- * MM_BC_PERIODIC (every axis at once; Sec. 4.1, 4.2 and 5.2) selects the Fourier
+ * MM_BC_PERIODIC (every axis at once; Sec. 4.1, 4.2 and 5.1) selects the Fourier
  * pseudo-spectral discretization on n equispaced points per period length[mu]: a is then
  * the diagonal diffusion tensor, d fields of n1 n2 (n3) values (a_11 first) on those
  * points, and `velocity` (nullable) holds d fields b_mu entering as div(b u) (without it
@@ -220,6 +220,22 @@ mm_status mumode_phi1v(mm_ctx* ctx, const mm_op* op, const double* in, double* o
 /* Advance u (device, in place) by nsteps Lawson steps (family MM_LAWSON). */
 mm_status lawson_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* stream);
 
+/* Grouped Lawson steps (Appendix, the Lawson-Euler and Lawson2b schemes): advance u[i]
+ * (device, in place, n1*n2*n3 values each) by nsteps steps of ops[i], for i < count
+ * (1..8). Every op must come from ctx, be a finite-difference (not periodic) MM_LAWSON
+ * operator with scheme MM_LAWSON_EULER or MM_LAWSON2B, and share op 0's d, n, precision,
+ * digit count and scheme; each op keeps its own coefficients, tau and factors. No two
+ * entries may share an op or a state. Each pass of a step is one launch for all count
+ * problems (the stencil, and one grouped mode product per axis), so problems too small
+ * to fill the GPU alone fill it together; small 2D problems that lawson_step solves in
+ * one workgroup run one workgroup each in a single launch. Results are bit-identical to
+ * lawson_step on each op alone. MM_SLICED groups use a digit workspace the context
+ * keeps per stream (allocated stream-ordered on first use and grown when a larger group
+ * needs it). Errors: MM_EINVAL (mismatched or invalid entries), MM_ENOMEM, MM_EDEVICE;
+ * enqueued on `stream`, asynchronous like lawson_step. */
+mm_status lawson_step_batch(mm_ctx* ctx, const mm_op* const* ops, double* const* u, int count, int nsteps,
+                            void* stream);
+
 /* Advance u (device, in place) by nsteps ERK steps (family MM_ERK). */
 mm_status erk_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* stream);
 
@@ -268,10 +284,16 @@ mm_status mm_set_graph_steps(mm_ctx* ctx, int steps);
 /* ---------------------------------------------------------------------------------
  * Serving: continuous batching of Lawson2b solves. Four admission threads, each with
  * its own context and stream, copy a request's data to the device and build its
- * operator as soon as a slot and its device-memory footprint fit; a step thread then
- * enqueues all of the request's steps on the least-loaded of four streams, so the
- * kernels of concurrent requests interleave on the device, and retires finished
- * requests (result copied back, memory released) as their completion events fire.
+ * operator as soon as a slot and its device-memory footprint fit. A step thread then
+ * batches at the granularity of steps: finite-difference requests of equal (d, n,
+ * precision, digit count) form a class on one of four streams, and each tick enqueues
+ * the next few steps of every member together through grouped launches (lawson_step_batch's
+ * kernels, up to eight requests per launch), so requests join and leave the group
+ * between ticks as they arrive and finish; at most two ticks per class are in flight.
+ * Small 2D requests (the one-workgroup solver's sizes, FP64) run whole, up to sixteen
+ * per launch; periodic requests run alone on the least loaded stream. Finished
+ * requests are retired (result copied back, memory released) as their events fire.
+ * A request's result does not depend on what else is being served (bit for bit).
  * ------------------------------------------------------------------------------- */
 typedef struct {
   int d;
@@ -319,6 +341,19 @@ mm_status solve_submit(mm_server* srv, const mm_request* req, uint64_t* id);
 mm_status solve_poll(mm_server* srv, uint64_t id, double* u_out, mm_stats* stats);
 /* Seconds on the server clock (same clock as mm_stats). */
 double mm_server_clock(const mm_server* srv);
+
+/* What the step thread has launched since the server was created (diagnostics):
+ * problem_steps / group_steps is the mean number of requests per grouped launch. */
+typedef struct {
+  int64_t ticks;           /* class ticks enqueued                                      */
+  int64_t group_launches;  /* grouped step sequences (per tick, per group of up to 8)   */
+  int64_t group_steps;     /* steps those sequences enqueued                            */
+  int64_t problem_steps;   /* request-steps they advanced                               */
+  int64_t small_launches;  /* launches of the one-workgroup small-2D solver             */
+  int64_t small_solves;    /* whole solves in those launches                            */
+  int64_t single_solves;   /* requests stepped on their own (periodic problems)         */
+} mm_server_counters;
+mm_status mm_server_read_counters(mm_server* srv, mm_server_counters* out);
 
 #ifdef __cplusplus
 }

@@ -1,4 +1,4 @@
-"""The three-dimensional problem of Sec. 5.3 and the boundary and diffusion forms it
+"""The three-dimensional problem of Sec. 5.2 and the boundary and diffusion forms it
 needs (oracle; test infrastructure only: tests and the benchmark's CPU baseline use
 it, the product path never does).
 

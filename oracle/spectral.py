@@ -1,4 +1,4 @@
-"""Periodic pseudo-spectral problems of Sec. 4.1, 4.2 and 5.2 (oracle; test
+"""Periodic pseudo-spectral problems of Sec. 4.1, 4.2 and 5.1 (oracle; test
 infrastructure only: tests and the benchmark's CPU baseline use it, the product path
 never does).
 
@@ -30,7 +30,7 @@ A problem with no velocity field uses the constant velocity beta of the problem 
 Pins: tests/test_oracle_spectral.py (the printed errors of Figure fig:ad1dex0_diffdeltaa
 through this backend; derivatives and exponentials of trigonometric polynomials in
 closed form; F = A u + g; the lambda values of Table tab:adr2d_lambdaopt and the printed
-errors of Figure fig:adr2d_diffl for the problem of Sec. 5.2).
+errors of Figure fig:adr2d_diffl for the problem of Sec. 5.1).
 """
 from __future__ import annotations
 

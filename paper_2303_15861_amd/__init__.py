@@ -10,8 +10,10 @@ lawson_step, erk_step, mm_check, solve_submit, solve_poll.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from ctypes import POINTER, Structure, byref, c_char_p, c_double, c_int, c_int64, c_uint64, c_void_p
 from typing import Optional, Sequence
 
@@ -50,7 +52,8 @@ EXPORTS = ("mm_ctx_create", "mm_ctx_destroy", "mm_last_error", "mm_version", "mu
            "mumode_phi1v", "lawson_step", "erk_step", "mm_check", "mm_server_create",
            "mm_server_destroy", "solve_submit", "solve_poll", "mm_server_clock", "mm_timing_enable",
            "mm_timing_read", "mm_synchronize", "mm_set_gemm_tile",
-           "mm_set_graph_steps", "mm_set_small_fused")
+           "mm_set_graph_steps", "mm_set_small_fused", "lawson_step_batch",
+           "mm_server_read_counters")
 MM_KIND_STENCIL, MM_KIND_GEMM_K, MM_KIND_GEMM_N, MM_KIND_FUSED = 0, 1, 2, 3
 
 
@@ -79,18 +82,43 @@ class MMStats(Structure):
                 ("bytes", c_int64), ("steps", c_int), ("status", c_int)]
 
 
+class MMServerCounters(Structure):
+    _fields_ = [("ticks", c_int64), ("group_launches", c_int64), ("group_steps", c_int64),
+                ("problem_steps", c_int64), ("small_launches", c_int64), ("small_solves", c_int64),
+                ("single_solves", c_int64)]
+
+
 class MumodeError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
 
 
+def _hip_runtimes() -> set:
+    """Files of HIP runtimes mapped into this process (Linux)."""
+    try:
+        with open("/proc/self/maps") as f:
+            return {l.split()[-1] for l in f if "libamdhip64" in l}
+    except OSError:
+        return set()
+
+
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
-    """Load libmumode.so and declare its signatures. Raises if it is not built."""
+    """Load libmumode.so and declare its signatures. Raises if it is not built.
+
+    torch is imported first: its own HIP runtime (a libamdhip64 with the same SONAME as
+    the one libmumode.so is linked against) is then already mapped, so the dynamic
+    loader resolves libmumode's dependency to it and the process holds one runtime.
+    Loaded the other way round, the process would map two runtimes, each with its own
+    view of the device, and torch would report that no GPU is available."""
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with paper_2303_15861_amd.build "
                           "(there is no CPU fallback)")
+    import torch  # noqa: F401  (maps torch's HIP runtime before libmumode.so)
     lib = ctypes.CDLL(path)
+    if len(_hip_runtimes()) > 1:
+        raise ImportError(f"two HIP runtimes are mapped ({sorted(_hip_runtimes())}); "
+                          "libmumode.so must share torch's runtime")
     vp, i, d = c_void_p, c_int, c_double
     sig = {
         "mm_ctx_create": (i, [i, POINTER(vp)]),
@@ -106,12 +134,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mumode_phi1v": (i, [vp, vp, vp, vp, vp]),
         "lawson_step": (i, [vp, vp, vp, i, vp]),
         "erk_step": (i, [vp, vp, vp, i, vp]),
+        "lawson_step_batch": (i, [vp, POINTER(vp), POINTER(vp), i, i, vp]),
         "mm_check": (i, [vp, vp, vp]),
         "mm_server_create": (i, [i, i, c_int64, POINTER(vp)]),
         "mm_server_destroy": (None, [vp]),
         "solve_submit": (i, [vp, POINTER(MMRequest), POINTER(c_uint64)]),
         "solve_poll": (i, [vp, c_uint64, vp, POINTER(MMStats)]),
         "mm_server_clock": (d, [vp]),
+        "mm_server_read_counters": (i, [vp, POINTER(MMServerCounters)]),
         "mm_timing_enable": (i, [vp, i]),
         "mm_synchronize": (i, [vp]),
         "mm_set_gemm_tile": (i, [vp, i]),
@@ -141,14 +171,21 @@ def _torch():
     return torch
 
 
-def _ptr(t) -> int:
+def _ptr(t, numel: Optional[int] = None, what: str = "grid tensor", device: Optional[int] = None) -> int:
+    """Device address of a contiguous float64 GPU tensor of exactly `numel` values (when
+    given) on `device` (when given). The kernels index the buffers by the problem's sizes
+    alone, so a shorter tensor would be read or written past its end."""
     if t is None:
         return None
     torch = _torch()
     if not isinstance(t, torch.Tensor):
-        raise TypeError("expected a torch tensor")
+        raise TypeError(f"{what}: expected a torch tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: has {t.numel()} values, the problem needs {numel}")
     if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
-        raise TypeError("grid tensors must be contiguous float64 tensors on the GPU")
+        raise TypeError(f"{what}: must be a contiguous float64 tensor on the GPU")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{what}: is on cuda:{t.device.index}, the context on cuda:{device}")
     return t.data_ptr()
 
 
@@ -158,17 +195,49 @@ def _stream(stream=None) -> int:
     return s.cuda_stream
 
 
+def coefficient_size(d: int, n: Sequence[int], periodic: bool) -> int:
+    """Values of the diffusion coefficient a: the padded nodes (n_mu + 2 per axis), or for
+    periodic problems the d diagonal fields on the grid."""
+    dof, nodes = 1, 1
+    for i in range(d):
+        dof *= int(n[i])
+        nodes *= int(n[i]) + 2
+    return d * dof if periodic else nodes
+
+
+# Library objects still open, released in order (servers, then operators through their
+# contexts) by the exit handler below while the HIP runtime is certainly alive; once it
+# has run, finalisers do nothing. Without it, objects that outlive the test or script
+# (held by a traceback, a module global or a reference cycle) are released from the
+# garbage collector during interpreter shutdown, in no particular order.
+_OPEN = weakref.WeakSet()
+_EXITING = False
+
+
+@atexit.register
+def _release_all():
+    global _EXITING
+    live = list(_OPEN)
+    for obj in live:
+        if isinstance(obj, Server):
+            obj.close()
+    for obj in live:
+        if isinstance(obj, Context):
+            obj.close()
+    _EXITING = True
+
+
 class Context:
     """An mm_ctx on one device."""
 
     def __init__(self, device: int = 0):
-        import weakref
         self._h = c_void_p()
         self.device = device
         self._ops = weakref.WeakSet()     # live operators: released before the context
         st = lib().mm_ctx_create(device, byref(self._h))
         if st != MM_OK:
             raise MumodeError(st, f"mm_ctx_create(device={device}) failed")
+        _OPEN.add(self)
 
     @property
     def handle(self):
@@ -208,8 +277,11 @@ class Context:
                 op.close()
             lib().mm_ctx_destroy(self._h)
             self._h = c_void_p()
+        _OPEN.discard(self)
 
     def __del__(self):
+        if _EXITING:
+            return
         try:
             self.close()
         except Exception:
@@ -225,6 +297,9 @@ class Operator:
         self.d, self.n = prob.d, tuple(prob.n)
         self.scheme, self.prec, self.q = scheme, prec, q
         self.family = SCHEMES[scheme][0]
+        self.dof = 1
+        for i in range(self.d):
+            self.dof *= self.n[i]
 
     @property
     def handle(self):
@@ -232,7 +307,13 @@ class Operator:
 
     @property
     def shape(self):
-        return tuple(reversed(self.n))
+        return tuple(reversed(self.n[: self.d]))
+
+    def grid(self, t, what: str = "grid tensor") -> int:
+        """Address of a grid function of this operator's problem (checked size and device)."""
+        if not self._h:
+            raise ValueError("the operator is closed")
+        return _ptr(t, self.dof, what, self.ctx.device)
 
     def info(self):
         am = c_double()
@@ -258,6 +339,8 @@ class Operator:
         self._h = c_void_p()
 
     def __del__(self):
+        if _EXITING:
+            return
         try:
             self.close()
         except Exception:
@@ -282,10 +365,19 @@ def mumode_setup(ctx: Context, d: int, n: Sequence[int], a, beta: Sequence[float
     for i in range(4):
         prob.r[i] = float(r[i])
     prob.lam = float(lam)
-    prob.a = _ptr(a)
+    periodic = prob.bc[0] == MM_BC_PERIODIC
+    # sizes are checked for a well-formed problem; the library refuses any other (MM_EINVAL)
+    # before it reads a buffer
+    sized = d in (2, 3) and all(prob.n[i] >= 1 for i in range(d))
+    dof = 1
+    for i in range(min(d, 3)):
+        dof *= prob.n[i]
+    prob.a = _ptr(a, coefficient_size(d, prob.n, periodic) if sized else None, "diffusion coefficient a",
+                  ctx.device)
     for i in range(3):
         prob.length[i] = float(length[i]) if (length is not None and i < d) else 0.0
-    prob.velocity = _ptr(velocity) if velocity is not None else None
+    prob.velocity = (_ptr(velocity, d * dof if sized else None, "velocity", ctx.device)
+                     if velocity is not None else None)
     _torch().cuda.current_stream(a.device).synchronize()   # a must be complete
     fam, sch = SCHEMES[scheme]
     h = c_void_p()
@@ -297,27 +389,44 @@ def mumode_setup(ctx: Context, d: int, n: Sequence[int], a, beta: Sequence[float
 
 
 def remainder_eval(op: Operator, u, g, F=None, stream=None):
-    st = lib().remainder_eval(op.ctx.handle, op.handle, _ptr(u), _ptr(g), _ptr(F), _stream(stream))
+    st = lib().remainder_eval(op.ctx.handle, op.handle, op.grid(u, "u"), op.grid(g, "g"),
+                              op.grid(F, "F") if F is not None else None, _stream(stream))
     op.ctx.check(st, "remainder_eval")
 
 
 def mumode_expv(op: Operator, inp, out, j: int = 0, stream=None):
-    st = lib().mumode_expv(op.ctx.handle, op.handle, int(j), _ptr(inp), _ptr(out), _stream(stream))
+    st = lib().mumode_expv(op.ctx.handle, op.handle, int(j), op.grid(inp, "input"), op.grid(out, "output"),
+                           _stream(stream))
     op.ctx.check(st, "mumode_expv")
 
 
 def mumode_phi1v(op: Operator, inp, out, stream=None):
-    st = lib().mumode_phi1v(op.ctx.handle, op.handle, _ptr(inp), _ptr(out), _stream(stream))
+    st = lib().mumode_phi1v(op.ctx.handle, op.handle, op.grid(inp, "input"), op.grid(out, "output"),
+                            _stream(stream))
     op.ctx.check(st, "mumode_phi1v")
 
 
 def lawson_step(op: Operator, u, nsteps: int, stream=None):
-    st = lib().lawson_step(op.ctx.handle, op.handle, _ptr(u), int(nsteps), _stream(stream))
+    st = lib().lawson_step(op.ctx.handle, op.handle, op.grid(u, "u"), int(nsteps), _stream(stream))
     op.ctx.check(st, "lawson_step")
 
 
+def lawson_step_batch(ops: Sequence[Operator], us, nsteps: int, stream=None):
+    """Grouped Lawson steps: ops[i] advances us[i] (one class: shape, precision, scheme)."""
+    count = len(ops)
+    if count != len(us) or count < 1:
+        raise ValueError("lawson_step_batch needs as many states as operators (at least one)")
+    ctx = ops[0].ctx
+    if any(op.ctx is not ctx for op in ops):
+        raise ValueError("lawson_step_batch: every operator must come from the same context")
+    hops = (c_void_p * count)(*[op.handle.value for op in ops])
+    hus = (c_void_p * count)(*[op.grid(u, f"u[{i}]") for i, (op, u) in enumerate(zip(ops, us))])
+    st = lib().lawson_step_batch(ctx.handle, hops, hus, count, int(nsteps), _stream(stream))
+    ctx.check(st, "lawson_step_batch")
+
+
 def erk_step(op: Operator, u, nsteps: int, stream=None):
-    st = lib().erk_step(op.ctx.handle, op.handle, _ptr(u), int(nsteps), _stream(stream))
+    st = lib().erk_step(op.ctx.handle, op.handle, op.grid(u, "u"), int(nsteps), _stream(stream))
     op.ctx.check(st, "erk_step")
 
 

@@ -647,6 +647,10 @@ StencilArgs stencil_args(const mm_op* op, const double* u, bool full) {
 // sigma = sign(t) sqrt(s t), diagonalised by the orthogonal symmetric sine matrix
 // S[j][k] = sqrt(2/(n+1)) sin(j k pi/(n+1)), eigenvalues delta + 2 sigma cos(k pi/(n+1)).
 // Hence A = L diag(ev) R with L = D S and R = S D^-1 (R L = I), both row-major n x n.
+// The eigenvalues are evaluated as (delta + 2 sigma) - 4 sigma sin^2(k pi/(2(n+1))) with
+// delta + 2 sigma = (delta^2 - 4 s t)/(delta - 2 sigma): equal in real arithmetic to
+// delta + 2 sigma cos(k pi/(n+1)), whose small eigenvalues lose about 2 |delta| u to
+// cancellation (for the stiff exponentials of large grids, 1e-13 relative in exp).
 bool eigen_closed_form(int n, double s, double delta, double t, std::vector<double>& ev, std::vector<double>& R,
                        std::vector<double>& L) {
   double rho = 1.0, sigma = 0.0;
@@ -664,7 +668,15 @@ bool eigen_closed_form(int n, double s, double delta, double t, std::vector<doub
   L.resize((size_t)n * n);
   std::vector<double> dpow(n);
   for (int j = 0; j < n; ++j) dpow[j] = std::pow(rho, j + 1);
-  for (int k = 0; k < n; ++k) ev[k] = delta + 2.0 * sigma * std::cos((k + 1) * pi / (n + 1));
+  // The operators here are a second difference plus a centred first difference, so
+  // delta = -(s + t) up to the rounding of s and t, and delta^2 - 4 s t = (s - t)^2.
+  const double dm = delta - 2.0 * sigma;
+  const bool second_difference = std::fabs(delta + s + t) <= 1e-15 * std::fabs(delta);
+  const double c0 = (dm != 0.0 && second_difference) ? (s - t) * (s - t) / dm : delta + 2.0 * sigma;
+  for (int k = 0; k < n; ++k) {
+    const double h = std::sin((k + 1) * pi / (2.0 * (n + 1)));
+    ev[k] = c0 - 4.0 * sigma * h * h;
+  }
   for (int j = 0; j < n; ++j)
     for (int k = 0; k < n; ++k) {
       const int64_t m = ((int64_t)(j + 1) * (k + 1)) % per;   // exact argument reduction
@@ -726,6 +738,14 @@ mm_status mm_ctx_create(int device, mm_ctx** out) {
 void mm_ctx_destroy(mm_ctx* ctx) {
   if (!ctx) return;
   hipSetDevice(ctx->device);
+  if (!ctx->bws.empty()) {
+    // grouped sliced workspaces: their streams' work must be over before the release
+    hipDeviceSynchronize();
+    for (auto& w : ctx->bws) {
+      if (w.vdig) hipFreeAsync(w.vdig, ctx->stream);
+      if (w.vexp) hipFreeAsync(w.vexp, ctx->stream);
+    }
+  }
   if (ctx->stream) hipStreamSynchronize(ctx->stream);
   if (ctx->reduce_buf) hipFree(ctx->reduce_buf);
   for (auto& t : ctx->timed) {
@@ -1032,6 +1052,34 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     const double h = mesh_h(op, mu);
     const double diff = op->lam * op->a_max / (h * h);
     const double adv = op->beta_bar[mu] / (2.0 * h);
+    if (op->bc[mu] == MM_BC_DIRICHLET && adv == 0.0) {
+      // symmetric A_mu: exp(c tau A_mu) = S diag(exp(c tau ev)) S with the orthogonal sine
+      // matrix S (closed form, no squarings): one FP64 product per factor, accurate to
+      // rounding however stiff c tau A_mu is -- scaling and squaring doubles the error of
+      // the scaled exponential with every squaring (about 2^s u relative)
+      std::vector<double> ev, Sm, Lm;
+      eigen_closed_form(n, diff, -2.0 * diff, diff, ev, Sm, Lm);
+      const int64_t nn = (int64_t)n * n;
+      std::vector<double> W((size_t)nn);
+      bool ok = hipMemcpy(ws, Sm.data(), nn * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+      for (int j = 0; j < nf && ok; ++j) {
+        const double ct = cs[j] * tau;
+        std::vector<double> w(n);
+        for (int k = 0; k < n; ++k) w[k] = std::exp(ct * ev[k]);
+        for (int r = 0; r < n; ++r)
+          for (int k = 0; k < n; ++k) W[(size_t)r * n + k] = Sm[(size_t)r * n + k] * w[k];
+        ok = hipMemcpy(ws + nn, W.data(), nn * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+             gemm_sq(n, ws + nn, ws, op->fac[mu] + (int64_t)j * nn, st) == hipSuccess &&
+             hipStreamSynchronize(st) == hipSuccess;
+      }
+      if (!ok) {
+        hipFreeAsync(ws, st);
+        set_err(ctx, "closed-form factor setup failed");
+        return fail(MM_EDEVICE);
+      }
+      op->squarings[mu] = 0;
+      continue;
+    }
     for (int j = 0; j < nf; ++j) {
       const double ct = cs[j] * tau;
       int sq = 0;
@@ -1619,7 +1667,297 @@ mm_status run_steps(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hipStre
   return enqueue_steps(ctx, op, u, nsteps - reps * gs, s);
 }
 
+// One mode pass of the exponential for `count` problems of one class, as a single
+// grouped launch: group i applies problem i's factor exp(tau_i A_mu) to its own
+// `nvec` stacked grid functions (in[i] -> out[i], layouts as in exp_action).
+hipError_t group_pass(mm_ctx* ctx, const mm_op* const* ops, int count, int mu, int nvec, const void* const* in,
+                      void* const* out, PassIO io, const mm_batch_ws* ws, hipStream_t s) {
+  const mm_op* o0 = ops[0];
+  const int d = o0->d, n = o0->n[mu];
+  const int64_t dof = o0->dof;
+  GemmArgs g{};
+  for (int i = 0; i < count; ++i) {
+    const void* F = factor_op(ops[i], mu, 0);
+    g.fexp[i] = factor_exp(ops[i], mu, 0);
+    g.galpha[i] = 0.0;
+    g.Cadd[i] = nullptr;
+    g.C[i] = out[i];
+    if (mu == 0) {
+      g.A[i] = in[i];
+      g.B[i] = F;
+    } else {
+      g.A[i] = F;
+      g.B[i] = in[i];
+    }
+  }
+  g.groups = count;
+  g.slices = o0->slices;
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  g.in_f32 = io.in_f32;
+  g.out_f32 = io.out_f32;
+  g.fac_slice = factor_slice_stride(o0, n, n);
+  if (mu == 0) {
+    g.M = (int)(dof / n) * nvec;
+    g.N = g.K = n;
+    g.lda = g.ldc = n;
+    g.ldb = factor_ld(o0, n);
+    g.inner = 1;
+    g.b_trans = 0;
+  } else if (mu == d - 1) {
+    const int P = (int)(dof / n);
+    g.M = g.K = n;
+    g.N = P;
+    g.lda = factor_ld(o0, n);
+    g.ldb = g.ldc = P;
+    g.inner = nvec;
+    g.sA = 0;
+    g.sB = g.sC = dof;
+    g.b_trans = 1;
+  } else {
+    g.M = g.K = n;
+    g.N = o0->n[0];
+    g.lda = factor_ld(o0, n);
+    g.ldb = g.ldc = o0->n[0];
+    g.inner = o0->n[2] * nvec;
+    g.sA = 0;
+    g.sB = g.sC = (int64_t)o0->n[0] * o0->n[1];
+    g.b_trans = 1;
+  }
+  g.tile = ctx->gemm_tile;
+  if (ws) {
+    g.vdig = ws->vdig;
+    g.vexp = ws->vexp;
+    g.vdig_cap = ws->vdig_cap;
+    g.vexp_cap = ws->vexp_cap;
+  }
+  const double work = 2.0 * g.M * (double)g.N * g.K * g.inner * g.groups;
+  return timed_launch(ctx, g.b_trans ? MM_KIND_GEMM_N : MM_KIND_GEMM_K, work, s,
+                      [&] { return launch_gemm(o0->prec, g, s); });
+}
+
+// The digit-plane workspace of grouped sliced launches on stream s, at least dig bytes
+// and ex exponents (stream-ordered reallocation when it has to grow).
+mm_status group_workspace(mm_ctx* ctx, hipStream_t s, int64_t dig, int64_t ex, mm_batch_ws** out) {
+  mm_batch_ws* w = nullptr;
+  for (auto& b : ctx->bws)
+    if (b.stream == s) w = &b;
+  if (!w) {
+    ctx->bws.push_back(mm_batch_ws{});
+    w = &ctx->bws.back();
+    w->stream = s;
+  }
+  if (w->vdig_cap < dig) {
+    if (w->vdig) hipFreeAsync(w->vdig, s);
+    w->vdig = nullptr;
+    w->vdig_cap = 0;
+    if (hipMallocAsync((void**)&w->vdig, (size_t)dig, s) != hipSuccess) {
+      w->vdig = nullptr;
+      set_err(ctx, "grouped sliced workspace allocation (%lld bytes) failed", (long long)dig);
+      return MM_ENOMEM;
+    }
+    w->vdig_cap = dig;
+  }
+  if (w->vexp_cap < ex) {
+    if (w->vexp) hipFreeAsync(w->vexp, s);
+    w->vexp = nullptr;
+    w->vexp_cap = 0;
+    if (hipMallocAsync((void**)&w->vexp, (size_t)ex * sizeof(int), s) != hipSuccess) {
+      w->vexp = nullptr;
+      set_err(ctx, "grouped sliced workspace allocation failed");
+      return MM_ENOMEM;
+    }
+    w->vexp_cap = ex;
+  }
+  *out = w;
+  return MM_OK;
+}
+
 }  // namespace
+
+namespace mm {
+
+bool lawson_groupable(const mm_op* op) {
+  return op && op->family == MM_LAWSON && !op->periodic &&
+         (op->scheme == MM_LAWSON_EULER || op->scheme == MM_LAWSON2B);
+}
+
+bool small2d_fusable(const mm_ctx* ctx, const mm_op* op) {
+  return ctx->small_fused && op->family == MM_LAWSON && op->prec == MM_FP64 && !op->periodic &&
+         small2d_fits(op->d, op->n[0], op->n[1]) && op->form == MM_FORM_FLUX && op->bc[0] == MM_BC_DIRICHLET &&
+         op->bc[1] == MM_BC_DIRICHLET && (op->scheme == MM_LAWSON_EULER || op->scheme == MM_LAWSON2B);
+}
+
+bool same_class(const mm_op* a, const mm_op* b) {
+  return a->d == b->d && a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->n[2] == b->n[2] && a->prec == b->prec &&
+         a->slices == b->slices && a->family == b->family && a->scheme == b->scheme;
+}
+
+// Steps of `count` problems of one class (Lawson-Euler or Lawson2b, the pass sequence
+// of enqueue_lawson): per pass one stencil launch for all problems and one grouped
+// launch per mode, every problem with its own factors, coefficients, tau and scratch.
+// Each output is computed by the same kernels in the same order as for the problem
+// alone (the stencil per point; a mode product per output, whatever the tile), so the
+// results are bit-identical to lawson_step's.
+mm_status enqueue_lawson_group(mm_ctx* ctx, const mm_op* const* ops, double* const* u, int count, int nsteps,
+                               hipStream_t s) {
+  const mm_op* o0 = ops[0];
+  const int64_t dof = o0->dof;
+  const int d = o0->d;
+  const bool mixed = lowp(o0);
+  const bool l2b = o0->scheme == MM_LAWSON2B;
+  const int nvec = l2b ? 2 : 1;
+  mm_batch_ws* ws = nullptr;
+  if (o0->prec == MM_SLICED) {
+    // the largest grid-operand split over the modes of one grouped action
+    int64_t dig = 0, ex = 0;
+    for (int mu = 0; mu < d; ++mu) {
+      const int64_t fib = (int64_t)count * nvec * (dof / o0->n[mu]);
+      dig = std::max(dig, fib * o0->slices * slice_ld(o0->n[mu]));
+      ex = std::max(ex, fib);
+    }
+    mm_status rc = group_workspace(ctx, s, dig, ex, &ws);
+    if (rc != MM_OK) return rc;
+  }
+  StencilArgs sa[kMaxGroups];
+  const void* in[kMaxGroups];
+  void *t0[kMaxGroups], *t1[kMaxGroups], *out[kMaxGroups];
+  for (int i = 0; i < count; ++i) {
+    in[i] = ops[i]->buf[0];
+    t0[i] = ops[i]->buf[1];
+    t1[i] = ops[i]->buf[0];
+    out[i] = l2b ? (d == 3 ? ops[i]->buf[1] : ops[i]->buf[0]) : u[i];
+  }
+  for (int it = 0; it < nsteps; ++it) {
+    // v1 = u + tau g(u) (and for Lawson2b v2 = u + tau/2 g(u)) into buf[0]
+    for (int i = 0; i < count; ++i) {
+      const mm_op* op = ops[i];
+      double* b0 = op->buf[0];
+      StencilArgs a = stencil_args(op, u[i], false);
+      a.base0 = u[i];
+      a.c0 = op->tau;
+      if (l2b) {
+        a.base1 = u[i];
+        a.c1 = 0.5 * op->tau;
+      }
+      if (mixed) {
+        a.out0f = (float*)b0;
+        if (l2b) a.out1f = (float*)b0 + dof;
+      } else {
+        a.out0 = b0;
+        if (l2b) a.out1 = b0 + dof;
+      }
+      sa[i] = a;
+    }
+    HIPCHK(ctx, timed_launch(ctx, MM_KIND_STENCIL, (double)dof * count, s,
+                             [&] { return launch_stencil_batch(d, sa, count, s); }));
+    // e^{tau A}: buf[0] -> buf[1] (-> buf[0]) -> out
+    HIPCHK(ctx, group_pass(ctx, ops, count, 0, nvec, in, t0, PassIO{mixed, mixed}, ws, s));
+    if (d == 3) {
+      HIPCHK(ctx, group_pass(ctx, ops, count, 1, nvec, (const void* const*)t0, t1, PassIO{mixed, mixed}, ws, s));
+      HIPCHK(ctx, group_pass(ctx, ops, count, 2, nvec, (const void* const*)t1, out, PassIO{mixed, false}, ws, s));
+    } else {
+      HIPCHK(ctx, group_pass(ctx, ops, count, 1, nvec, (const void* const*)t0, out, PassIO{mixed, false}, ws, s));
+    }
+    if (!l2b) continue;
+    // u+ = W + tau/2 g(U) with [U, W] the transformed pair
+    for (int i = 0; i < count; ++i) {
+      const mm_op* op = ops[i];
+      const double* res = (const double*)out[i];
+      StencilArgs c = stencil_args(op, res, false);
+      c.base0 = res + dof;
+      c.c0 = 0.5 * op->tau;
+      c.out0 = u[i];
+      sa[i] = c;
+    }
+    HIPCHK(ctx, timed_launch(ctx, MM_KIND_STENCIL, (double)dof * count, s,
+                             [&] { return launch_stencil_batch(d, sa, count, s); }));
+  }
+  return MM_OK;
+}
+
+// Whole solves of small 2D problems, one workgroup each (any sizes up to 64 x 64 and any
+// step counts), each computed exactly as by the one-problem launch.
+mm_status enqueue_small2d_group(mm_ctx* ctx, const mm_op* const* ops, double* const* u, const int* nsteps,
+                                int count, hipStream_t s) {
+  if (count < 1 || count > kMaxSmallBatch) return MM_EINVAL;
+  const bool l2b = ops[0]->scheme == MM_LAWSON2B;
+  SmallArgs args[kMaxSmallBatch];
+  double work = 0.0;
+  for (int i = 0; i < count; ++i) {
+    const mm_op* op = ops[i];
+    if ((op->scheme == MM_LAWSON2B) != l2b) return MM_EINVAL;
+    const StencilArgs sa = stencil_args(op, u[i], false);
+    SmallArgs& a = args[i];
+    a = SmallArgs{};
+    a.u = u[i];
+    a.a = op->a;
+    a.E1 = factor(op, 0, 0);
+    a.E2 = factor(op, 1, 0);
+    a.n1 = op->n[0];
+    a.n2 = op->n[1];
+    a.nsteps = nsteps[i];
+    a.tau = op->tau;
+    for (int mu = 0; mu < 2; ++mu) {
+      a.ih2[mu] = sa.ih2[mu];
+      a.cadv[mu] = sa.cadv[mu];
+    }
+    a.lam_amax = sa.lam_amax;
+    a.r0 = sa.r0;
+    a.r1 = sa.r1;
+    a.r2 = sa.r2;
+    a.r3 = sa.r3;
+    a.flag = op->flag;
+    work += (double)nsteps[i] * (l2b ? 2 : 1) * 2.0 * (double)op->dof * (op->n[0] + op->n[1]);
+  }
+  HIPCHK(ctx, timed_launch(ctx, MM_KIND_FUSED, work, s,
+                           [&] { return launch_lawson_small2d_batch(args, count, l2b, s); }));
+  return MM_OK;
+}
+
+}  // namespace mm
+
+extern "C" {
+
+mm_status lawson_step_batch(mm_ctx* ctx, const mm_op* const* ops, double* const* u, int count, int nsteps,
+                            void* stream) {
+  if (!ctx) return MM_EINVAL;
+  if (!ops || !u || count < 1 || count > kMaxGroups || nsteps < 0) {
+    set_err(ctx, "lawson_step_batch: null arrays, count outside 1..%d or nsteps < 0", kMaxGroups);
+    return MM_EINVAL;
+  }
+  for (int i = 0; i < count; ++i) {
+    mm_status rc = check_op(ctx, ops[i]);
+    if (rc != MM_OK) return rc;
+    if (!u[i]) {
+      set_err(ctx, "lawson_step_batch: null state %d", i);
+      return MM_EINVAL;
+    }
+    if (!lawson_groupable(ops[i])) {
+      set_err(ctx, "lawson_step_batch: op %d is not a finite-difference Lawson-Euler or Lawson2b operator", i);
+      return MM_EINVAL;
+    }
+    if (!same_class(ops[0], ops[i])) {
+      set_err(ctx, "lawson_step_batch: op %d differs from op 0 in shape, precision, digits or scheme", i);
+      return MM_EINVAL;
+    }
+    for (int j = 0; j < i; ++j)
+      if (ops[j] == ops[i] || u[j] == u[i]) {
+        set_err(ctx, "lawson_step_batch: entries %d and %d share an operator or a state", j, i);
+        return MM_EINVAL;
+      }
+  }
+  if (nsteps == 0) return MM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  if (small2d_fusable(ctx, ops[0])) {
+    int ns[kMaxGroups];
+    for (int i = 0; i < count; ++i) ns[i] = nsteps;
+    return enqueue_small2d_group(ctx, ops, u, ns, count, s);
+  }
+  return enqueue_lawson_group(ctx, ops, u, count, nsteps, s);
+}
+
+}  // extern "C"
 
 extern "C" {
 

@@ -89,6 +89,11 @@ struct StencilArgs {
                         // the stencil gets F through lam_amax = 0 and cadv)
 };
 
+// Up to kMaxGroups stencil problems of one grid shape, launched together.
+struct StencilBatch {
+  StencilArgs a[kMaxGroups];
+};
+
 // One axis of the pointwise pass of the spectral remainder (spectral.hip).
 struct SpecMidArgs {
   double* G;            // remainder accumulator (nondiv: += (a - lam a_max) T1)
@@ -116,6 +121,12 @@ struct SmallArgs {
 };
 bool small2d_fits(int d, int n1, int n2);
 hipError_t launch_lawson_small2d(const SmallArgs& a, bool l2b, hipStream_t s);
+// Up to kMaxSmallBatch whole solves in one launch, one workgroup each.
+constexpr int kMaxSmallBatch = 16;
+struct SmallBatch {
+  SmallArgs a[kMaxSmallBatch];
+};
+hipError_t launch_lawson_small2d_batch(const SmallArgs* a, int count, bool l2b, hipStream_t s);
 
 hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s);
 // Tile size the launcher takes for g in precision prec (g.tile if set, else 64 when
@@ -129,6 +140,9 @@ hipError_t launch_gemm_sliced(GemmArgs& g, hipStream_t s);
 hipError_t launch_slice_rows(signed char* dst, int* exps, const double* src, int rows, int k, int lds, int ldd,
                              int S, hipStream_t s);
 hipError_t launch_stencil(int d, const StencilArgs& a, hipStream_t s);
+// count (1..kMaxGroups) problems with equal n1, n2, n3 in one launch; each problem's
+// outputs are bit-identical to launch_stencil's.
+hipError_t launch_stencil_batch(int d, const StencilArgs* a, int count, hipStream_t s);
 hipError_t launch_build_circulant(double* M, int n, const double* col, hipStream_t s);
 hipError_t launch_spec_react(double* G, const double* u, int64_t n, const double* r, hipStream_t s);
 hipError_t launch_spec_mid(const SpecMidArgs& a, hipStream_t s);
@@ -169,12 +183,33 @@ hipError_t launch_convert_factor(int prec, void* dst, const double* src, int row
                                  hipStream_t s);
 int factor_slices(int prec);
 
+// Grouped stepping (used by lawson_step_batch and the request server). A problem can be
+// advanced together with others of its class when it is a finite-difference problem
+// (not periodic) stepped by Lawson-Euler or Lawson2b; a class is (d, n, precision,
+// digit count, scheme). Small 2D problems that the one-workgroup solver takes run one
+// workgroup each, any mix of sizes and step counts.
+bool lawson_groupable(const mm_op* op);
+bool small2d_fusable(const mm_ctx* ctx, const mm_op* op);
+bool same_class(const mm_op* a, const mm_op* b);
+mm_status enqueue_lawson_group(mm_ctx* ctx, const mm_op* const* ops, double* const* u, int count, int nsteps,
+                               hipStream_t s);
+mm_status enqueue_small2d_group(mm_ctx* ctx, const mm_op* const* ops, double* const* u, const int* nsteps,
+                                int count, hipStream_t s);
+
 }  // namespace mm
 
 struct mm_timed {
   int kind;
   double work;
   hipEvent_t start, stop;
+};
+
+// Digit-plane workspace of grouped sliced launches on one stream (grown on demand).
+struct mm_batch_ws {
+  hipStream_t stream = nullptr;
+  signed char* vdig = nullptr;
+  int* vexp = nullptr;
+  int64_t vdig_cap = 0, vexp_cap = 0;
 };
 
 struct mm_ctx {
@@ -190,6 +225,7 @@ struct mm_ctx {
   hipStream_t capture = nullptr;  // private stream used only to record graphs
   std::vector<mm_timed> timed;
   size_t timed_used = 0;
+  std::vector<mm_batch_ws> bws;   // per stream: grouped sliced launches
 };
 
 struct mm_op {

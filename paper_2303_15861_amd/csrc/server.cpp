@@ -3,16 +3,22 @@
 // A server owns a few admission threads and one step thread, each with its own mm_ctx,
 // and a pool of HIP streams (default priority):
 //   admission threads: take submitted requests in arrival order while fewer than
-//     max_active are admitted and the HBM budget covers the request's footprint; uploads
-//     a and u0 and runs mumode_setup (operator, Pade factors) on its own stream, with
-//     stream-ordered allocations, then hands the request to the step thread;
-//   step thread: enqueues all steps of each handed-over request on the least loaded
-//     stream, so kernels of different requests run side by side on the device, and
-//     retires requests whose completion event has fired (non-finite flag, copy-out,
-//     release of device memory and budget).
-// Setup of new requests therefore overlaps the steps of running ones. Each request runs
-// the same kernels on the same shapes whatever else is admitted, so its result does not
-// depend on the mix.
+//     max_active are admitted and the HBM budget covers the request's footprint; upload
+//     a and u0 and run mumode_setup (operator, Pade factors) on their own streams, with
+//     stream-ordered allocations, then hand the request to the step thread;
+//   step thread: batches at the granularity of steps. Admitted finite-difference
+//     requests are grouped into classes of equal (d, n, precision, digit count); a
+//     class lives on one stream, and every tick the step thread enqueues the next few
+//     steps of all its members together -- per pass one stencil launch and one grouped
+//     mode product per axis for up to eight requests -- so a request that arrives while
+//     others run joins their launches at the next tick, and one that finishes leaves.
+//     At most two ticks per class are in flight, which bounds how long a newcomer
+//     waits. Small 2D requests run whole in the one-workgroup solver, up to sixteen
+//     per launch; periodic requests run their own step loops. Requests whose events
+//     have fired are retired (non-finite flag, copy-out, release of memory and budget).
+// Setup of new requests overlaps the steps of running ones. Every output of a grouped
+// launch is computed by the same kernel code in the same order as for its request
+// alone, so a result does not depend on the mix.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -31,6 +37,8 @@ namespace {
 
 constexpr int kStreams = 4;
 constexpr int kAdmitThreads = 4;
+constexpr int kTicksInFlight = 2;       // per class
+constexpr int kMaxTickSteps = 32;
 
 struct Job {
   uint64_t id = 0;
@@ -41,9 +49,20 @@ struct Job {
   double t_submit = 0, t_admit = 0, t_done = 0;
   mm_op* op = nullptr;
   double* u = nullptr;
-  int slot = 0;
+  int slot = 0;              // stream index
+  int remaining = 0;         // steps not yet enqueued (grouped requests)
+  bool enqueued = false;     // every step is on a stream and ev follows the last one
   hipEvent_t ev = nullptr;
   int64_t bytes = 0;
+};
+
+// Requests that step together: equal d, n, precision, digit count and scheme.
+struct Klass {
+  int d = 0, n[3] = {0, 0, 0}, prec = 0, slices = 0, scheme = 0;
+  int slot = 0;
+  double load = 0;                      // work estimate of the members
+  std::vector<Job*> members;            // arrival order, steps remaining
+  std::deque<hipEvent_t> ticks;         // enqueued ticks not yet known complete
 };
 
 struct Result {
@@ -68,13 +87,14 @@ int64_t footprint(const mm_request& r) {
   return 8 * (na + 5 * dof + 2 * fac + 7 * nmax * nmax) + 4096;
 }
 
-double work_estimate(const mm_request& r) {
+// flops of one Lawson2b step (two actions of d mode products) plus the stencil passes
+double step_work(const mm_request& r) {
   double dof = 1, nsum = 0;
   for (int mu = 0; mu < r.d; ++mu) {
     dof *= r.n[mu];
     nsum += r.n[mu];
   }
-  return r.steps * dof * (4.0 * nsum + 200.0);
+  return dof * (4.0 * nsum + 200.0);
 }
 
 }  // namespace
@@ -254,62 +274,268 @@ struct mm_server {
     cv_admit.notify_all();
   }
 
+  // ---------------------------------------------------------------- step thread
+  std::vector<std::unique_ptr<Klass>> classes;
+  std::vector<hipEvent_t> spare_events;
+  mutable std::mutex cmu;                     // guards counters
+  mm_server_counters counters{};
+
+  hipEvent_t take_event() {
+    if (!spare_events.empty()) {
+      hipEvent_t e = spare_events.back();
+      spare_events.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+  }
+
+  int least_loaded() const { return (int)(std::min_element(stream_load, stream_load + kStreams) - stream_load); }
+
+  Klass* class_of(const mm_op* op) {
+    for (auto& k : classes)
+      if (k->d == op->d && k->n[0] == op->n[0] && k->n[1] == op->n[1] && k->n[2] == op->n[2] &&
+          k->prec == op->prec && k->slices == op->slices && k->scheme == op->scheme) {
+        if (k->members.empty() && k->ticks.empty()) k->slot = least_loaded();   // idle: may move
+        return k.get();
+      }
+    auto k = std::make_unique<Klass>();
+    k->d = op->d;
+    for (int i = 0; i < 3; ++i) k->n[i] = op->n[i];
+    k->prec = op->prec;
+    k->slices = op->slices;
+    k->scheme = op->scheme;
+    k->slot = least_loaded();
+    classes.push_back(std::move(k));
+    return classes.back().get();
+  }
+
+  // Enqueue a request's whole solve on the least loaded stream (periodic problems)
+  int enqueue_alone(Job& j) {
+    const int s = least_loaded();
+    j.slot = s;
+    int st = lawson_step(ctx, j.op, j.u, j.req.steps, streams[s]);
+    if (st == MM_OK && hipEventRecord(j.ev, streams[s]) != hipSuccess) st = MM_EDEVICE;
+    if (st == MM_OK) {
+      stream_load[s] += j.work;
+      j.enqueued = true;
+      std::lock_guard<std::mutex> lk(cmu);
+      ++counters.single_solves;
+    }
+    return st;
+  }
+
+  // Small 2D requests: whole solves, up to kMaxSmallBatch per launch
+  void enqueue_small(std::vector<Job*>& small, std::vector<Job*>& failed) {
+    for (size_t i0 = 0; i0 < small.size(); i0 += mm::kMaxSmallBatch) {
+      const int cnt = (int)std::min<size_t>(mm::kMaxSmallBatch, small.size() - i0);
+      const mm_op* ops[mm::kMaxSmallBatch];
+      double* us[mm::kMaxSmallBatch];
+      int ns[mm::kMaxSmallBatch];
+      double work = 0;
+      for (int i = 0; i < cnt; ++i) {
+        Job* j = small[i0 + i];
+        ops[i] = j->op;
+        us[i] = j->u;
+        ns[i] = j->req.steps;
+        work += j->work;
+      }
+      const int s = least_loaded();
+      // one launch per scheme (Lawson-Euler and Lawson2b kernels differ); the server
+      // serves Lawson2b only, so this is one launch
+      int st = mm::enqueue_small2d_group(ctx, ops, us, ns, cnt, streams[s]);
+      for (int i = 0; i < cnt; ++i) {
+        Job* j = small[i0 + i];
+        j->slot = s;
+        if (st == MM_OK && hipEventRecord(j->ev, streams[s]) == hipSuccess) {
+          j->enqueued = true;
+        } else {
+          failed.push_back(j);
+        }
+      }
+      if (st == MM_OK) {
+        stream_load[s] += work;
+        std::lock_guard<std::mutex> lk(cmu);
+        ++counters.small_launches;
+        counters.small_solves += cnt;
+      }
+    }
+    small.clear();
+  }
+
+  // One tick of a class: the next k steps of every member with steps left, in groups of
+  // up to kMaxGroups per launch sequence, on the class's stream.
+  void enqueue_tick(Klass& k, std::vector<Job*>& failed) {
+    if (k.members.empty()) return;
+    hipStream_t st = streams[k.slot];
+    // steps per tick: about a millisecond of work at a few tens of TFLOP/s, so that
+    // newcomers join quickly and the host keeps ahead of the device
+    double wstep = 0;
+    int kmin = kMaxTickSteps;
+    for (Job* j : k.members) {
+      wstep += j->work / std::max(1, j->req.steps);
+      kmin = std::min(kmin, j->remaining);
+    }
+    const int ktarget = (int)std::max(1.0, std::min((double)kMaxTickSteps, 3e10 / std::max(wstep, 1.0)));
+    const int ksteps = std::max(1, std::min(ktarget, kmin));
+    for (size_t i0 = 0; i0 < k.members.size(); i0 += mm::kMaxGroups) {
+      const int cnt = (int)std::min<size_t>(mm::kMaxGroups, k.members.size() - i0);
+      const mm_op* ops[mm::kMaxGroups];
+      double* us[mm::kMaxGroups];
+      for (int i = 0; i < cnt; ++i) {
+        ops[i] = k.members[i0 + i]->op;
+        us[i] = k.members[i0 + i]->u;
+      }
+      const int rc = mm::enqueue_lawson_group(ctx, ops, us, cnt, ksteps, st);
+      {
+        std::lock_guard<std::mutex> lk(cmu);
+        ++counters.group_launches;
+        counters.problem_steps += (int64_t)cnt * ksteps;
+        counters.group_steps += ksteps;
+      }
+      for (int i = 0; i < cnt; ++i) {
+        Job* j = k.members[i0 + i];
+        if (rc != MM_OK) {
+          j->remaining = 0;
+          failed.push_back(j);
+          continue;
+        }
+        j->remaining -= ksteps;
+        if (j->remaining == 0) {
+          if (hipEventRecord(j->ev, st) == hipSuccess)
+            j->enqueued = true;
+          else
+            failed.push_back(j);
+        }
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(cmu);
+      ++counters.ticks;
+    }
+    hipEvent_t e = take_event();
+    if (e && hipEventRecord(e, st) == hipSuccess) k.ticks.push_back(e);
+    else if (e) spare_events.push_back(e);
+    // members whose steps are all enqueued leave the class
+    double gone = 0;
+    std::vector<Job*> keep;
+    for (Job* j : k.members)
+      if (j->remaining > 0)
+        keep.push_back(j);
+      else
+        gone += j->work;
+    k.members.swap(keep);
+    k.load -= gone;
+  }
+
   void step_loop() {
     hipSetDevice(device);
-    std::vector<std::unique_ptr<Job>> active;
+    std::vector<std::unique_ptr<Job>> active;    // every admitted request not yet retired
+    std::vector<Job*> small, failed;
     while (true) {
       std::deque<std::unique_ptr<Job>> fresh;
       {
         std::unique_lock<std::mutex> lk(mu);
         if (active.empty()) {
           cv_step.wait(lk, [&] { return !ready.empty() || (stop && pending.empty() && admitted == 0); });
-          if (ready.empty() && stop && pending.empty() && admitted == 0) return;
+          if (ready.empty() && stop && pending.empty() && admitted == 0) break;
         }
         fresh.swap(ready);
       }
+      bool progressed = !fresh.empty();
       for (auto& jp : fresh) {
         Job& j = *jp;
-        const int s = (int)(std::min_element(stream_load, stream_load + kStreams) - stream_load);
-        j.slot = s;
-        int st = lawson_step(ctx, j.op, j.u, j.req.steps, streams[s]);
-        if (st == MM_OK && hipEventRecord(j.ev, streams[s]) != hipSuccess) st = MM_EDEVICE;
-        if (st != MM_OK) {
-          hipStreamSynchronize(streams[s]);
-          retire(j, st);
-          continue;
+        if (j.req.steps == 0) {
+          // nothing to enqueue: the request is done once its setup is
+          if (hipEventRecord(j.ev, ctx->stream) == hipSuccess) j.enqueued = true;
+          else failed.push_back(&j);
+        } else if (mm::small2d_fusable(ctx, j.op)) {
+          small.push_back(&j);
+        } else if (mm::lawson_groupable(j.op)) {
+          Klass* k = class_of(j.op);
+          j.slot = k->slot;
+          j.remaining = j.req.steps;
+          k->members.push_back(&j);
+          k->load += j.work;
+          stream_load[k->slot] += j.work;
+        } else if (enqueue_alone(j) != MM_OK) {
+          failed.push_back(&j);
         }
-        stream_load[s] += j.work;
         active.push_back(std::move(jp));
       }
-      bool progressed = !fresh.empty();
+      if (!small.empty()) enqueue_small(small, failed);
+      for (auto& kp : classes) {
+        Klass& k = *kp;
+        while (!k.ticks.empty()) {
+          const hipError_t q = hipEventQuery(k.ticks.front());
+          if (q == hipErrorNotReady) break;
+          spare_events.push_back(k.ticks.front());
+          k.ticks.pop_front();
+          progressed = true;
+        }
+        if (!k.members.empty() && (int)k.ticks.size() < kTicksInFlight) {
+          enqueue_tick(k, failed);
+          progressed = true;
+        }
+      }
+      // retire: requests that failed to enqueue (after their stream has drained) and
+      // requests whose last step has completed
       for (size_t i = 0; i < active.size();) {
         Job& j = *active[i];
-        const hipError_t q = hipEventQuery(j.ev);
-        if (q == hipErrorNotReady) {
-          ++i;
-          continue;
-        }
+        bool is_failed = std::find(failed.begin(), failed.end(), &j) != failed.end();
         int status = MM_OK;
-        if (q != hipSuccess) {
+        if (is_failed) {
+          hipStreamSynchronize(streams[j.slot]);
           status = MM_EDEVICE;
         } else {
-          int flag = 0;
-          if (hipMemcpy(&flag, j.op->flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+          if (!j.enqueued) {
+            ++i;
+            continue;
+          }
+          const hipError_t q = hipEventQuery(j.ev);
+          if (q == hipErrorNotReady) {
+            ++i;
+            continue;
+          }
+          if (q != hipSuccess) {
             status = MM_EDEVICE;
-          else if (flag)
-            status = MM_EUNSTABLE;
+          } else {
+            int flag = 0;
+            if (hipMemcpy(&flag, j.op->flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+              status = MM_EDEVICE;
+            else if (flag)
+              status = MM_EUNSTABLE;
+          }
         }
         stream_load[j.slot] -= j.work;
+        if (is_failed) {
+          // take it out of its class, if it is still a member
+          for (auto& kp : classes) {
+            auto& m = kp->members;
+            auto it = std::find(m.begin(), m.end(), &j);
+            if (it != m.end()) {
+              kp->load -= j.work;
+              m.erase(it);
+            }
+          }
+          failed.erase(std::find(failed.begin(), failed.end(), &j));
+        }
         retire(j, status);
         active.erase(active.begin() + i);
         progressed = true;
       }
       if (!progressed && !active.empty()) {
-        // nothing finished: wait for new work or poll the events again shortly
+        // nothing finished or enqueued: wait for new work or poll the events again shortly
         std::unique_lock<std::mutex> lk(mu);
-        cv_step.wait_for(lk, std::chrono::microseconds(200), [&] { return !ready.empty(); });
+        cv_step.wait_for(lk, std::chrono::microseconds(100), [&] { return !ready.empty(); });
       }
     }
+    for (auto& kp : classes)
+      for (hipEvent_t e : kp->ticks) hipEventDestroy(e);
+    for (hipEvent_t e : spare_events) hipEventDestroy(e);
+    classes.clear();
+    spare_events.clear();
   }
 };
 
@@ -381,6 +607,13 @@ void mm_server_destroy(mm_server* s) {
 
 double mm_server_clock(const mm_server* s) { return s ? s->now() : 0.0; }
 
+mm_status mm_server_read_counters(mm_server* s, mm_server_counters* out) {
+  if (!s || !out) return MM_EINVAL;
+  std::lock_guard<std::mutex> lk(s->cmu);
+  *out = s->counters;
+  return MM_OK;
+}
+
 mm_status solve_submit(mm_server* s, const mm_request* r, uint64_t* id) {
   if (!s || !r || !id) return MM_EINVAL;
   if ((r->d != 2 && r->d != 3) || !r->a || !r->u0 || !(r->tau > 0) || r->steps < 0 ||
@@ -411,7 +644,7 @@ mm_status solve_submit(mm_server* s, const mm_request* r, uint64_t* id) {
   j->req.a = nullptr;
   j->req.u0 = nullptr;
   j->est_bytes = footprint(j->req);
-  j->work = work_estimate(j->req);
+  j->work = step_work(j->req) * std::max(1, j->req.steps);
   j->req.velocity = nullptr;   // copied into j->vel
   if (j->est_bytes > s->budget) return MM_ENOMEM;
   j->t_submit = s->now();

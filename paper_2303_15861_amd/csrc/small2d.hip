@@ -96,7 +96,7 @@ __device__ __forceinline__ void mode_product(double* X, const FactorFrags& F, in
 
 // LE (L2B = 0) or Lawson2b (L2B = 1), nsteps steps of u (global, n2 x n1) in place.
 template <int L2B>
-__global__ __launch_bounds__(THS) void lawson_small2d(SmallArgs p) {
+__device__ __forceinline__ void lawson_small2d_body(const SmallArgs& p) {
   __shared__ double Us[NS * PS], V1[NS * PS], V2[L2B ? NS * PS : 1], As[PA * PA];
   const int n1 = p.n1, n2 = p.n2, tid = threadIdx.x;
   // factor fragments for the whole solve: mode 1 uses E1 rows of the wave's columns,
@@ -151,14 +151,31 @@ __global__ __launch_bounds__(THS) void lawson_small2d(SmallArgs p) {
   if (bad && p.flag) p.flag[0] = 1;
 }
 
+// One solve per workgroup: blockIdx.x selects the problem (its own sizes, factors,
+// coefficients and step count). A single solve is launched the same way with one entry,
+// so a problem's result does not depend on whether it ran alone or in a group.
+template <int L2B>
+__global__ __launch_bounds__(THS) void lawson_small2d_batch(SmallBatch b) {
+  lawson_small2d_body<L2B>(b.a[blockIdx.x]);
+}
+
 bool small2d_fits(int d, int n1, int n2) { return d == 2 && n1 >= 1 && n2 >= 1 && n1 <= NS && n2 <= NS; }
 
 hipError_t launch_lawson_small2d(const SmallArgs& a, bool l2b, hipStream_t s) {
-  if (a.n1 < 1 || a.n2 < 1 || a.n1 > NS || a.n2 > NS || a.nsteps < 0) return hipErrorInvalidValue;
+  return launch_lawson_small2d_batch(&a, 1, l2b, s);
+}
+
+hipError_t launch_lawson_small2d_batch(const SmallArgs* a, int count, bool l2b, hipStream_t s) {
+  if (count < 1 || count > kMaxSmallBatch) return hipErrorInvalidValue;
+  SmallBatch b;
+  for (int i = 0; i < count; ++i) {
+    if (a[i].n1 < 1 || a[i].n2 < 1 || a[i].n1 > NS || a[i].n2 > NS || a[i].nsteps < 0) return hipErrorInvalidValue;
+    b.a[i] = a[i];
+  }
   if (l2b)
-    lawson_small2d<1><<<1, THS, 0, s>>>(a);
+    lawson_small2d_batch<1><<<count, THS, 0, s>>>(b);
   else
-    lawson_small2d<0><<<1, THS, 0, s>>>(a);
+    lawson_small2d_batch<0><<<count, THS, 0, s>>>(b);
   return hipGetLastError();
 }
 

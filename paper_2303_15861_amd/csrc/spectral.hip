@@ -1,4 +1,4 @@
-// Periodic pseudo-spectral problems (Sec. 4.1, 4.2 and 5.2) in mu-mode form: the
+// Periodic pseudo-spectral problems (Sec. 4.1, 4.2 and 5.1) in mu-mode form: the
 // Fourier differentiation matrices and the exponentials of the extracted operator are
 // circulant along each axis, so every derivative and every exponential action is a mode
 // product with a dense n x n circulant factor (the same GEMMs as the finite-difference

@@ -5,7 +5,7 @@
 //     + sum_mu (beta_mu - beta_bar_mu)(u+ - u-)/(2 h_mu) + r0 + r1 u + r2 u^2 + r3 u^3,
 // abar = mean of the two nodal coefficients at a face, zero Dirichlet ghosts. With
 // lam_amax = 0 and the full velocity the same kernel yields F(u) (Appendix, u' = F(u)).
-// Sec. 5.3, eq. (eq:adr3d): the diffusion may instead be in non-divergence form,
+// Sec. 5.2, eq. (eq:adr3d): the diffusion may instead be in non-divergence form,
 // (a - lam a_max) Lap_h u, and an axis may carry a zero normal derivative at x = 1,
 // whose ghost beyond the last unknown is the mirror value: at that unknown the + and -
 // neighbours along the axis are equal (u_{n+1} = u_{n-1}), so no extra loads.
@@ -97,7 +97,7 @@ __device__ __forceinline__ void store_row(float* __restrict__ base, int64_t off,
 }
 
 template <int D, int P>
-__global__ __launch_bounds__(64 * SW) void stencil_kernel(StencilArgs p, StencilGrid sg) {
+__device__ __forceinline__ void stencil_body(const StencilArgs& p, const StencilGrid& sg) {
   constexpr int YT = (D == 3) ? 1 : 2;   // rows per lane along x2
   constexpr int ZT = (D == 3) ? 2 : 1;   // rows per lane along x3
   constexpr int YH = YT + 2;             // with the x2 halo
@@ -263,6 +263,16 @@ __global__ __launch_bounds__(64 * SW) void stencil_kernel(StencilArgs p, Stencil
     }
 }
 
+// blockIdx.y selects one of up to kMaxGroups problems of the same grid shape (their own
+// u, a, coefficients and outputs). A single problem is launched the same way with one
+// entry, so one compiled kernel serves both, and a problem's results do not depend on
+// whether it ran alone or in a group (two instantiations of the body may contract
+// multiply-adds differently, which changes last bits).
+template <int D, int P>
+__global__ __launch_bounds__(64 * SW) void stencil_batch_kernel(StencilBatch b, StencilGrid sg) {
+  stencil_body<D, P>(b.a[blockIdx.y], sg);
+}
+
 // Points per lane: the P in {4, 2, 1} that pads n1 least to whole 64 P-point segments,
 // the larger P on ties. Measured per pass at n^3 (us, P = 1 / 2 / 4): n = 63: 5 / 7 / 8;
 // 191: 54 / 71 / 59; 255: 129-149 / 141-146 / 132-134; 383: 510 / 481 / 591 -- idle lanes
@@ -281,29 +291,44 @@ static int points_per_lane(int n1) {
 }
 
 template <int D>
-static void launch_d(int P, const StencilArgs& a, StencilGrid sg, unsigned blocks, hipStream_t s) {
+static void launch_batch_d(int P, const StencilBatch& b, int count, StencilGrid sg, unsigned blocks, hipStream_t s) {
+  const dim3 grid(blocks, (unsigned)count);
   if (P == 4)
-    stencil_kernel<D, 4><<<dim3(blocks), dim3(64 * SW), 0, s>>>(a, sg);
+    stencil_batch_kernel<D, 4><<<grid, dim3(64 * SW), 0, s>>>(b, sg);
   else if (P == 2)
-    stencil_kernel<D, 2><<<dim3(blocks), dim3(64 * SW), 0, s>>>(a, sg);
+    stencil_batch_kernel<D, 2><<<grid, dim3(64 * SW), 0, s>>>(b, sg);
   else
-    stencil_kernel<D, 1><<<dim3(blocks), dim3(64 * SW), 0, s>>>(a, sg);
+    stencil_batch_kernel<D, 1><<<grid, dim3(64 * SW), 0, s>>>(b, sg);
 }
 
-hipError_t launch_stencil(int d, const StencilArgs& a, hipStream_t s) {
-  if (a.n1 < 1 || a.n2 < 1 || a.n3 < 1) return hipErrorInvalidValue;
-  const int P = points_per_lane(a.n1);
-  StencilGrid sg;
-  sg.nxs = (a.n1 + 64 * P - 1) / (64 * P);
+// Work decomposition of one grid (blocks of four waves); false if it does not fit a grid.
+static bool stencil_grid(int d, int n1, int n2, int n3, int& P, StencilGrid& sg, int64_t& blocks) {
+  if (n1 < 1 || n2 < 1 || n3 < 1) return false;
+  P = points_per_lane(n1);
+  sg.nxs = (n1 + 64 * P - 1) / (64 * P);
   const int yt = (d == 3) ? 1 : 2, zt = (d == 3) ? 2 : 1;
-  sg.nyb = (a.n2 + SW * yt - 1) / (SW * yt);
-  sg.nzb = (d == 3) ? (a.n3 + zt - 1) / zt : 1;
-  const int64_t blocks = (int64_t)sg.nxs * sg.nyb * sg.nzb;
-  if (blocks >= (1LL << 31)) return hipErrorInvalidValue;
+  sg.nyb = (n2 + SW * yt - 1) / (SW * yt);
+  sg.nzb = (d == 3) ? (n3 + zt - 1) / zt : 1;
+  blocks = (int64_t)sg.nxs * sg.nyb * sg.nzb;
+  return blocks < (1LL << 31);
+}
+
+hipError_t launch_stencil(int d, const StencilArgs& a, hipStream_t s) { return launch_stencil_batch(d, &a, 1, s); }
+
+hipError_t launch_stencil_batch(int d, const StencilArgs* a, int count, hipStream_t s) {
+  if (count < 1 || count > kMaxGroups) return hipErrorInvalidValue;
+  for (int i = 1; i < count; ++i)
+    if (a[i].n1 != a[0].n1 || a[i].n2 != a[0].n2 || a[i].n3 != a[0].n3) return hipErrorInvalidValue;
+  int P;
+  StencilGrid sg;
+  int64_t blocks;
+  if (!stencil_grid(d, a[0].n1, a[0].n2, a[0].n3, P, sg, blocks)) return hipErrorInvalidValue;
+  StencilBatch b;
+  for (int i = 0; i < count; ++i) b.a[i] = a[i];
   if (d == 3)
-    launch_d<3>(P, a, sg, (unsigned)blocks, s);
+    launch_batch_d<3>(P, b, count, sg, (unsigned)blocks, s);
   else
-    launch_d<2>(P, a, sg, (unsigned)blocks, s);
+    launch_batch_d<2>(P, b, count, sg, (unsigned)blocks, s);
   return hipGetLastError();
 }
 

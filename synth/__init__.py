@@ -215,7 +215,7 @@ def workload(name: str, seed: int = 0) -> Problem:
                               tau=5e-4, steps=200, scheme="etd2rk", q=0, name=name)
     if name == "3d_n383_etd2rk_exact":
         return anisotropic_problem(383, seed, tau=2e-3, steps=50, scheme="etd2rk", q=0, name=name)
-    # the paper's own 3D problem at the size of its timing runs (Sec. 5.3: N = 60, b = -0.01,
+    # the paper's own 3D problem at the size of its timing runs (Sec. 5.2: N = 60, b = -0.01,
     # SL2 with the lambda of Table tab:adr3d_lambdaopt, m = 2^8 steps to T = 1/4)
     if name == "3d_paper_n60_sl2":
         return paper3d_problem(60, -0.01, 0.53, scheme="sl2", steps=256, name=name)
@@ -226,7 +226,7 @@ def workload(name: str, seed: int = 0) -> Problem:
 
 def paper3d_problem(N: int, b: float, lam: float, *, scheme: str = "l2b", steps: int = 256, T: float = 0.25,
                     name: str = "") -> Problem:
-    """The three-dimensional problem of Sec. 5.3, eq. (eq:adr3d), split as eq. (eq:adr3dstab):
+    """The three-dimensional problem of Sec. 5.2, eq. (eq:adr3d), split as eq. (eq:adr3dstab):
     u_t = a Lap u + b (d_1 + d_2 + d_3) u + u(1 + u^2) on (0,1)^3, Dirichlet data on the faces
     x_mu = 0, homogeneous Neumann data on x_mu = 1, a = exp(-|x - 1/2|^2)/10,
     u0 = (27/4)^3 prod x_mu (1 - x_mu)^2, N points per direction (x_i = i/N), the whole
@@ -249,7 +249,7 @@ PERIODIC = 2
 
 def paper2d_problem(N: int, lam: float, *, scheme: str = "l2b", steps: int = 256, T: float = 4.0,
                     name: str = "") -> Problem:
-    """The two-dimensional problem of Sec. 5.2, eq. (eq:ad2d): periodic on (-3 pi, 3 pi)^2,
+    """The two-dimensional problem of Sec. 5.1, eq. (eq:ad2d): periodic on (-3 pi, 3 pi)^2,
     diffusion tensor diag(1/2 + sin^2 x1 sin^2 x2 / 6, 1/2 + cos^2 x1 cos^2 x2 / 6), velocity
     b = (sin^2 x1, sin^2 x2)/5 in div(b u), r(u) = u(1 - u)/4, u0 = exp(-(x1^2 + x2^2)),
     N points per direction. The extracted velocity of eq. (eq:amaxbeta) is the mean of

@@ -4,6 +4,7 @@ import os
 import re
 
 import pytest
+import torch  # noqa: F401  (the HIP runtime the library shares, mapped before it is loaded)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 LIB = os.path.join(ROOT, "paper_2303_15861_amd", "libmumode.so")
@@ -69,7 +70,8 @@ int main(void) {{
 
 
 @pytest.mark.parametrize("cls,struct", [("MMProblem", "mm_problem"), ("MMRequest", "mm_request"),
-                                        ("MMStats", "mm_stats")])
+                                        ("MMStats", "mm_stats"),
+                                        ("MMServerCounters", "mm_server_counters")])
 def test_binding_structs_match_the_header(cls, struct):
     """The ctypes mirrors of the ABI structs have the header's size and field offsets (the
     binding's field names map to the header's: lam -> lambda)."""
@@ -123,4 +125,6 @@ def test_entry_points_reject_null_handles_before_any_device_call():
     assert lib.solve_submit(None, ctypes.byref(req), ctypes.byref(rid)) == EINVAL
     assert lib.solve_poll(None, 1, None, None) == EINVAL
     assert lib.mm_server_clock(None) == 0.0
+    assert lib.mm_server_read_counters(None, None) == EINVAL
+    assert lib.lawson_step_batch(None, None, None, 1, 1, None) == EINVAL
     lib.mm_server_destroy(None)

@@ -1,4 +1,4 @@
-"""The problem of Sec. 5.3 (Dirichlet data at x = 0, zero normal derivative at x = 1,
+"""The problem of Sec. 5.2 (Dirichlet data at x = 0, zero normal derivative at x = 1,
 diffusion a Lap u) and other mixed-boundary problems on the GPU against
 oracle/adr3d.py, plus the errors printed in Figure fig:adr3d_diffl reproduced with
 the GPU path alone (reference and solutions both computed on the device)."""

@@ -41,32 +41,53 @@ def relerr(got, ref):
     return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
 
 
+def fp64_bar(p):
+    """FP64 parity bar of a stiff request. Two FP64 evaluations of a Lawson2b solve differ
+    by their rounding, which the last stage multiplies (tau/2 g of an action's output,
+    no exponential after it) by up to amp = 1 + 2 d tau (a_max - a_min)/h^2 in the
+    high-frequency modes: one unit of rounding in u0 alone moves the 511^2 request with
+    tau = 5e-3 (amp 3.8e3) by 3.2e-12 in the oracle itself. The bar is 1e-12, or 32 units
+    of rounding times amp where that is larger."""
+    h = 1.0 / (max(p.n) + 1)
+    amp = 1.0 + 2 * p.d * p.tau * (float(p.a.max()) - float(p.a.min())) / h ** 2
+    return max(1e-12, 32 * 2.0 ** -53 * amp)
+
+
 def test_alone_equals_mix_and_oracle(mm):
+    """The target alone, then among requests of its own class (grouped launches with
+    different partners as they join and finish) and of other classes."""
     target = synth.smooth_problem((24, 20, 16), 11, tau=2e-3, steps=20, scheme="l2b", beta=(3, -2, 1))
     others = [synth.smooth_problem((31, 31, 31), 21, tau=1e-3, steps=30),
               synth.smooth_problem((63, 63), 22, tau=1e-3, steps=40, beta=(5, 1)),
+              synth.smooth_problem((24, 20, 16), 27, tau=1e-3, steps=35, beta=(0, 4, 8)),
               synth.smooth_problem((40, 33, 28), 23, tau=1e-3, steps=25),
+              synth.smooth_problem((24, 20, 16), 28, tau=4e-3, steps=7),
               synth.smooth_problem((127, 127), 24, tau=5e-4, steps=50, beta=(0, 9)),
               synth.smooth_problem((24, 20, 16), 25, tau=2e-3, steps=20),
+              synth.smooth_problem((24, 20, 16), 29, tau=2.5e-3, steps=60, r=synth.R_LOGISTIC),
               synth.smooth_problem((63, 63, 63), 26, tau=1e-3, steps=10)]
-    srv = mm.Server(0, max_active=8)
+    srv = mm.Server(0, max_active=12)
     try:
         st, rid = mm.solve_submit(srv, target)
         assert st == mm.MM_OK
         st, u_alone, info = wait(mm, srv, rid, target.shape)
         assert st == mm.MM_OK and info["steps"] == target.steps
         ids = []
-        for p in others[:3]:
+        for p in others[:4]:
             ids.append((p, mm.solve_submit(srv, p)[1]))
         st, rid2 = mm.solve_submit(srv, target)
-        for p in others[3:]:
+        for p in others[4:]:
             ids.append((p, mm.solve_submit(srv, p)[1]))
         st, u_mix, _ = wait(mm, srv, rid2, target.shape)
         assert st == mm.MM_OK
         results = [(p, wait(mm, srv, i, p.shape)) for p, i in ids]
+        counters = srv.counters()
     finally:
         srv.close()
+    print("server counters", counters)
     assert np.array_equal(u_alone, u_mix)
+    # five requests of the target's class: some launches carried more than one
+    assert counters["mean_group"] > 1.0 and counters["small_solves"] >= 1
     assert relerr(u_alone, S.solve(target)) <= 1e-12
     for p, (st, u, _) in results:
         assert st == mm.MM_OK
@@ -113,7 +134,7 @@ def test_nonfinite_request_fails_alone(mm):
     assert relerr(ug, S.solve(good)) <= 1e-12
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "sliced6"])
 def test_mixed_precision_requests(mm, prec):
     p = synth.smooth_problem((40, 36, 32), 50, tau=1e-3, steps=10)
     srv = mm.Server(0, max_active=4)
@@ -123,11 +144,35 @@ def test_mixed_precision_requests(mm, prec):
     finally:
         srv.close()
     assert st == mm.MM_OK
-    assert relerr(u, S.solve(p)) <= (1e-4 if prec == "fp32" else 1e-3)
+    assert relerr(u, S.solve(p)) <= {"fp32": 1e-4, "bf16x3": 1e-3, "sliced6": 1e-9}[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "sliced6"])
+def test_largest_stream_requests(mm, prec):
+    """The largest sizes of the served stream, 511^2 and 191^3, drawn by its recipe (beta
+    uniform in [0, 20]^d, seeded a and u0; 20 Lawson2b steps of tau = 0.1/20), served side
+    by side and each checked against the oracle."""
+    reqs = [synth.StreamRequest(index=0, arrival_s=0.0, d=2, n=511, beta=(13.0, 4.5), r=synth.R_LOGISTIC,
+                                steps=20, seed=7001),
+            synth.StreamRequest(index=1, arrival_s=0.0, d=3, n=191, beta=(2.0, 17.5, 9.0), r=synth.R_CUBIC,
+                                steps=20, seed=7002)]
+    probs = [r.problem() for r in reqs]
+    srv = mm.Server(0, max_active=4)
+    try:
+        ids = [mm.solve_submit(srv, p, prec=prec)[1] for p in probs]
+        outs = [wait(mm, srv, i, p.shape, timeout=200.0) for i, p in zip(ids, probs)]
+    finally:
+        srv.close()
+    for (st, u, _), p in zip(outs, probs):
+        assert st == mm.MM_OK
+        err = relerr(u, S.solve(p))
+        bar = fp64_bar(p) if prec == "fp64" else 1e-9
+        print(f"{prec} {p.n} {p.steps} steps: rel. error vs oracle {err:.2e} (bar {bar:.1e})")
+        assert err <= bar
 
 
 def test_neumann_requests_next_to_dirichlet_ones(mm):
-    """Requests carry the boundary type and diffusion form: the problem of Sec. 5.3
+    """Requests carry the boundary type and diffusion form: the problem of Sec. 5.2
     (Lawson2b, lambda = 1) served next to an all-Dirichlet flux-form request, each
     against its oracle."""
     from oracle import adr3d
@@ -150,7 +195,7 @@ def test_neumann_requests_next_to_dirichlet_ones(mm):
 
 
 def test_periodic_requests_next_to_dirichlet_ones(mm):
-    """Periodic (pseudo-spectral) requests: the problem of Sec. 5.2 with its velocity field
+    """Periodic (pseudo-spectral) requests: the problem of Sec. 5.1 with its velocity field
     and the problem of Sec. 4.2 without one, served next to an all-Dirichlet request, each
     Lawson2b solve against its oracle; a request mixing periodic and Dirichlet axes is
     refused."""

@@ -1,7 +1,7 @@
-"""Periodic pseudo-spectral problems (Sec. 4.1, 4.2, 5.2) on the GPU, where every Fourier
+"""Periodic pseudo-spectral problems (Sec. 4.1, 4.2, 5.1) on the GPU, where every Fourier
 derivative and every exponential is a mode product with a dense circulant factor,
 against oracle/spectral.py (numpy FFT); plus the errors printed for the problem of
-Sec. 5.2 (Figure fig:adr2d_diffl) and the lambda values of Table tab:adr2d_lambdaopt
+Sec. 5.1 (Figure fig:adr2d_diffl) and the lambda values of Table tab:adr2d_lambdaopt
 reproduced with GPU solves."""
 import dataclasses
 
@@ -114,7 +114,7 @@ def test_exp_action_is_exact_exponential(mm, ctx, n):
 
 @pytest.mark.parametrize("scheme", ["le", "l2b", "sle", "l2a", "sl2", "etd2rk", "erk2p1f"])
 def test_paper2d_solves(mm, ctx, scheme):
-    """Whole solves of the problem of Sec. 5.2 at N = 64 (16 steps of tau = 1/64, lambda
+    """Whole solves of the problem of Sec. 5.1 at N = 64 (16 steps of tau = 1/64, lambda
     0.5) against the oracle."""
     p = synth.paper2d_problem(64, 0.5, scheme=scheme, steps=256)
     p = dataclasses.replace(p, steps=16)
@@ -153,7 +153,7 @@ def test_periodic_3d_solves(mm, ctx, n, scheme):
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 4e-4), ("sliced6", 1e-10)])
 def test_paper2d_mixed_precision(mm, ctx, prec, tol):
     """The exponential actions in the mixed precisions (the spectral remainder stays FP64)
-    against the FP64 oracle: 16 Lawson2b steps of the Sec. 5.2 problem. Bars: the
+    against the FP64 oracle: 16 Lawson2b steps of the Sec. 5.1 problem. Bars: the
     per-contraction errors of the modes (FP32 ~1e-7, BF16x3 ~2e-6, sliced6 ~1e-14 of the
     largest term) times the two actions per step over 16 steps and the magnification by
     the stiff modes of the factors (the BF16x3 solve measures 1.0e-4)."""

@@ -1,4 +1,4 @@
-"""Pins of oracle/adr3d.py (the problem of Sec. 5.3 with Dirichlet/Neumann data and the
+"""Pins of oracle/adr3d.py (the problem of Sec. 5.2 with Dirichlet/Neumann data and the
 non-divergence diffusion form) against facts that do not depend on it: the errors
 printed in Figure fig:adr3d_diffl, textbook eigenpairs, an independent implementation
 of the all-Dirichlet case, and consistency identities."""

@@ -1,4 +1,4 @@
-"""Pins of oracle/spectral.py (periodic pseudo-spectral problems of Sec. 4 and 5.2)
+"""Pins of oracle/spectral.py (periodic pseudo-spectral problems of Sec. 4 and 5.1)
 against facts that do not depend on it: closed-form derivatives and exponentials of
 trigonometric polynomials, the independent one-dimensional Fourier backend that
 reproduces Figure fig:ad1dex0_diffdeltaa, the errors printed in Figure
@@ -157,7 +157,7 @@ def _fig_adr2d(N):
 
 
 def test_fig_adr2d_printed_errors_and_lambda_table():
-    """Sec. 5.2 at N = 2^6, m = 2^8, T = 4 against a Lawson2b reference (lambda = 1, 2^13
+    """Sec. 5.1 at N = 2^6, m = 2^8, T = 4 against a Lawson2b reference (lambda = 1, 2^13
     steps): the printed errors of LE, SLE, SL2 and EE within -2.5%/+1.5% (they come out
     about 2% low at most lambda, uniformly for EE: a systematic offset whose cause is not
     identified), L2a within -6%/+17%, and the smallest error on the printed lambda grid at
