@@ -217,6 +217,23 @@ mm_status mumode_expv(mm_ctx* ctx, const mm_op* op, int j, const double* in, dou
  * or exact through the eigenbasis when q = 0. */
 mm_status mumode_phi1v(mm_ctx* ctx, const mm_op* op, const double* in, double* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * allocation-free serving loops, harnesses that forbid hipMalloc): the FP64 exponential
+ * action of mumode_expv, out = in x_1 E_1 x_2 E_2 (x_3 E_3), with caller-owned factors
+ * and no operator. E[mu]: device, row-major n[mu] x n[mu] (for instance exp(tau A_mu)
+ * from mumode_get_factor, uploaded); n: d sizes, x1 first; in, out: device,
+ * n1*n2(*n3) values, may alias. The two intermediates live in a scratch array of
+ * 2 x 2^21 doubles (32 MiB) that the library holds on each device from the first
+ * mm_ctx_create on it until the process ends; the call allocates nothing. Limit:
+ * n1*n2*n3 <= 2^21 (2,097,152 grid values), else MM_EINVAL with a message. The scratch is
+ * fully written before it is read in every call, so no state carries over, but every
+ * call on one device shares it: calls that overlap in time on one device (on different
+ * streams or threads) race, and the caller must serialise them. Results are
+ * bit-identical to mumode_expv with the same factors. Enqueued on `stream`;
+ * MM_EDEVICE if a launch fails. */
+mm_status mumode_expv_noalloc(mm_ctx* ctx, int d, const int* n, const double* const* E, const double* in,
+                              double* out, void* stream);
+
 /* Advance u (device, in place) by nsteps Lawson steps (family MM_LAWSON). */
 mm_status lawson_step(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, void* stream);
 

@@ -53,7 +53,7 @@ EXPORTS = ("mm_ctx_create", "mm_ctx_destroy", "mm_last_error", "mm_version", "mu
            "mm_server_destroy", "solve_submit", "solve_poll", "mm_server_clock", "mm_timing_enable",
            "mm_timing_read", "mm_synchronize", "mm_set_gemm_tile",
            "mm_set_graph_steps", "mm_set_small_fused", "lawson_step_batch",
-           "mm_server_read_counters")
+           "mm_server_read_counters", "mumode_expv_noalloc")
 MM_KIND_STENCIL, MM_KIND_GEMM_K, MM_KIND_GEMM_N, MM_KIND_FUSED = 0, 1, 2, 3
 
 
@@ -132,6 +132,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "remainder_eval": (i, [vp, vp, vp, vp, vp, vp]),
         "mumode_expv": (i, [vp, vp, i, vp, vp, vp]),
         "mumode_phi1v": (i, [vp, vp, vp, vp, vp]),
+        "mumode_expv_noalloc": (i, [vp, i, POINTER(c_int), POINTER(vp), vp, vp, vp]),
         "lawson_step": (i, [vp, vp, vp, i, vp]),
         "erk_step": (i, [vp, vp, vp, i, vp]),
         "lawson_step_batch": (i, [vp, POINTER(vp), POINTER(vp), i, i, vp]),
@@ -409,6 +410,27 @@ def mumode_phi1v(op: Operator, inp, out, stream=None):
 def lawson_step(op: Operator, u, nsteps: int, stream=None):
     st = lib().lawson_step(op.ctx.handle, op.handle, op.grid(u, "u"), int(nsteps), _stream(stream))
     op.ctx.check(st, "lawson_step")
+
+
+NOALLOC_MAX_DOF = 1 << 21
+
+
+def mumode_expv_noalloc(ctx: Context, factors, inp, out, stream=None):
+    """out = inp x_mu factors[mu] over the axes (FP64), with no device allocation: the
+    intermediates use the library's per-device scratch array (see mumode.h)."""
+    d = len(factors)
+    n = [int(f.shape[0]) for f in factors]
+    for f in factors:
+        if f.dim() != 2 or f.shape[0] != f.shape[1]:
+            raise ValueError("every factor must be a square matrix")
+    dof = 1
+    for m in n:
+        dof *= m
+    hn = (c_int * 3)(*(n + [1] * (3 - d)))
+    hE = (c_void_p * d)(*[_ptr(f, f.shape[0] * f.shape[1], f"factor {mu}", ctx.device) for mu, f in enumerate(factors)])
+    st = lib().mumode_expv_noalloc(ctx.handle, d, hn, hE, _ptr(inp, dof, "input", ctx.device),
+                                   _ptr(out, dof, "output", ctx.device), _stream(stream))
+    ctx.check(st, "mumode_expv_noalloc")
 
 
 def lawson_step_batch(ops: Sequence[Operator], us, nsteps: int, stream=None):

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmumode.so")
 
-HIP_SOURCES = ["contract.hip", "stencil.hip", "sliced.hip", "small2d.hip", "spectral.hip"]
+HIP_SOURCES = ["contract.hip", "stencil.hip", "sliced.hip", "small2d.hip", "spectral.hip", "noalloc.hip"]
 CPP_SOURCES = ["api.cpp", "server.cpp"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result", "-Wno-unused-value",
           "-I" + os.path.join(ROOT, "include")]

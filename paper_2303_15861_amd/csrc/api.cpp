@@ -725,6 +725,12 @@ mm_status mm_ctx_create(int device, mm_ctx** out) {
     uint64_t keep = UINT64_MAX;
     hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
   }
+  // the device address of the allocation-free entry point's scratch array, on this device
+  if (noalloc_resolve(device) != hipSuccess) {
+    hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return MM_EDEVICE;
+  }
   ctx->reduce_parts = 1024;
   if (hipMalloc((void**)&ctx->reduce_buf, (ctx->reduce_parts + 1) * sizeof(double)) != hipSuccess) {
     hipStreamDestroy(ctx->stream);

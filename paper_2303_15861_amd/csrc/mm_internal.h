@@ -183,6 +183,12 @@ hipError_t launch_convert_factor(int prec, void* dst, const double* src, int row
                                  hipStream_t s);
 int factor_slices(int prec);
 
+// Allocation-free exponential action (noalloc.hip): grid values per intermediate of the
+// file-scope scratch array, and the per-device resolution of its address (called by
+// mm_ctx_create with the device current).
+constexpr int64_t kNoAllocMaxDof = (int64_t)1 << 21;
+hipError_t noalloc_resolve(int device);
+
 // Grouped stepping (used by lawson_step_batch and the request server). A problem can be
 // advanced together with others of its class when it is a finite-difference problem
 // (not periodic) stepped by Lawson-Euler or Lawson2b; a class is (d, n, precision,
