@@ -5,9 +5,16 @@ one stacked exp action (three mode products on two grid functions). The workload
 3D Dirichlet ADR problem with 255^3 interior points (h = 1/256), a = 1 + 0.9 tanh(s),
 beta = (10, 10, 10), r = u^2(1 - u), tau = 1e-3, 100 steps to T = 0.1 (synthetic seeded
 inputs). Every contraction precision is timed; the headline value is the FP64 path
-unless --headline names another mode. Each mixed mode's error is reported against the
-FP64 path after the same steps (the FP64 path matches the CPU oracle to 1e-12 in the
-parity tests).
+unless --headline names another mode. Each mode is also run untimed over the whole
+interval to T and its error stated there: against the FP64 path on the whole grid and
+against the CPU oracle on its stored samples (tests/golden/oracle_3d_n255_l2b_T.txt),
+with the stated target of the mode (FP32 1e-6, split modes 1e-9) as pass/fail.
+
+The served stream (512 seeded requests at 200/s) runs in FP64 with step-level batching,
+in FP64 one request at a time (max_active = 1), and in the sliced mode that meets the
+split target. The other workloads (63^2 Lawson-Euler, 127^3 Lawson2b and ETD2RK, 383^3
+ETD2RK) get a line each under "configs" with their dominant kernel's roofline, and the
+oracle is timed on bounded samples of each on the host ("cpu_baselines").
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes fp64,fp32,...]
 
@@ -28,6 +35,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "int8": 5.0e15}
+HBM_PEAK = 8.0e12
 DESCRIPTION = {
     "3d_n255_l2b": "3D Dirichlet ADR 255^3 interior, Lawson2b, tau=1e-3, 100 steps to T=0.1",
     "3d_n127_l2b": "3D Dirichlet ADR 127^3 interior, Lawson2b, tau=5e-4, 200 steps to T=0.1",
@@ -44,8 +52,12 @@ DESCRIPTION = {
     "2d_paper_n256_sl2": "the periodic 2D ADR problem of Sec. 5.1 (pseudo-spectral, circulant factors), N = 256, "
                          "SL2 with lambda = 0.57, 256 steps to T = 4",
 }
-HBM_PEAK = 8.0e12
 WORKLOAD = "3d_n255_l2b"
+# stated error targets of the contraction modes at T (FP32; split / sliced modes)
+TARGET = {"fp32": 1e-6, "bf16x3": 1e-9, "bf16x6": 1e-9}
+# other workloads: (name, timed steps or None for the whole solve, precisions)
+CONFIGS = [("2d_n63_le", None, ("fp64",)), ("3d_n127_l2b", None, ("fp64", "sliced6")),
+           ("3d_n127_etd2rk", None, ("fp64",)), ("3d_n383_etd2rk", 5, ("fp64", "sliced6"))]
 
 
 def parse():
@@ -62,10 +74,13 @@ def parse():
     ap.add_argument("--tile", type=int, default=0, help="force the mode-product workgroup tile (64 or 128)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--serve", default="fp64,bf16x3",
+    ap.add_argument("--no-at-T", action="store_true", help="skip the untimed runs to T")
+    ap.add_argument("--serve", default="fp64,sliced6",
                     help="precisions for the served-stream run ('' to skip)")
     ap.add_argument("--serve-count", type=int, default=512)
-    ap.add_argument("--serve-active", type=int, default=16)
+    ap.add_argument("--serve-active", type=int, default=32)
+    ap.add_argument("--no-serial", action="store_true", help="skip the one-at-a-time served-stream baseline")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other workloads")
     ap.add_argument("--calibrate", action="store_true",
                     help="run a plain elementwise copy of one grid function (known bytes) first, "
                          "as the reference for HBM counter runs")
@@ -93,11 +108,35 @@ def measured_traffic():
     return float(m_bytes.group(1)) if sha == m_sha.group(1) else None
 
 
+def oracle_samples(workload):
+    """(max |u(T)|, flat indices, values) of the oracle at T, or None without a fixture."""
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_{workload}_T.txt")
+    if not os.path.exists(path):
+        return None
+    idx, val, mx = [], [], None
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        a, b = line.split()
+        if a == "max_abs":
+            mx = float.fromhex(b)
+        else:
+            idx.append(int(a))
+            val.append(float.fromhex(b))
+    return mx, np.array(idx, dtype=np.int64), np.array(val)
+
+
 def dtype_name(prec):
     """Arithmetic type of a mode's contractions."""
     if prec.startswith("sliced"):
         return f"i8x{prec[6:]}"          # S int8 digit planes, int32 accumulation, f64 combination
     return {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}[prec]
+
+
+def target(prec):
+    if prec == "fp64":
+        return None
+    return 1e-9 if prec.startswith("sliced") else TARGET[prec]
 
 
 def slice_products(prec):
@@ -137,6 +176,49 @@ def time_mode(mm, ctx, p, prec, steps, warmup, graph_steps=0):
         kern[name] = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / max(n, 1), "work": wk}
     ctx.timing(False)
     return op, out, (t1 - t0), kern, status
+
+
+def run_to_T(mm, op, p):
+    """The whole solve (p.steps steps from u0), untimed; the state at T on the host."""
+    import torch
+    u = torch.from_numpy(p.u0).to("cuda")
+    mm.step(op, u, p.steps)
+    status = mm.mm_check(op)
+    return u.cpu().numpy(), status
+
+
+def roofline(kern, prec, p):
+    """Roofline of the dominant kernel kind of one timed run (algorithmic work per launch
+    over the launch durations measured with HIP events on the launch streams)."""
+    kname = max(("gemm_k", "gemm_n", "stencil", "fused"), key=lambda k: kern[k]["total_ms"])
+    k = kern[kname]
+    secs = k["total_ms"] * 1e-3
+    if kname == "fused":
+        # one workgroup per solve on one compute unit: its share of the FP64 matrix peak
+        roof = {"bound": "mfma", "achieved": k["work"] / secs / 1e12, "peak": PEAK["fp64"] / 256 / 1e12,
+                "unit": "TFLOP/s", "scope": "one compute unit"}
+    elif kname == "stencil":
+        # algorithmic bytes per grid point of a fused remainder pass: read u and a, write
+        # two outputs (first pass) or read U, W, a and write u (second pass): 32 B
+        roof = {"bound": "hbm", "achieved": 32.0 * k["work"] / secs / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s"}
+    elif prec.startswith("sliced"):
+        # int8 digit products executed, S(S+1)/2 per algorithmic multiply-add; the launch
+        # time includes the pass that splits the grid operand into digits
+        roof = {"bound": "mfma", "achieved": k["work"] * slice_products(prec) / secs / 1e12,
+                "peak": PEAK["int8"] / 1e12, "unit": "TOP/s", "includes": "grid split + int8 product"}
+    elif prec in ("bf16x3", "bf16x6"):
+        # split-BF16 contractions are bound by HBM: 16 B per grid point per pass
+        bytes_ = 16.0 * k["work"] / (2.0 * p.n[0])
+        roof = {"bound": "hbm", "achieved": bytes_ / secs / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
+    else:
+        roof = {"bound": "mfma", "achieved": k["work"] / secs / 1e12, "peak": PEAK[prec] / 1e12,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = {"gemm_k": "gemm (mode 1)", "gemm_n": "gemm (modes 2, 3)", "stencil": "stencil",
+                      "fused": "whole small-2D solve in one workgroup (one compute unit)"}[kname]
+    roof["avg_launch_us"] = k["avg_us"]
+    return roof, kname
 
 
 def latency(mm, ctx, op, p, reps):
@@ -179,7 +261,7 @@ def serve_stream(mm, prec, count, max_active):
     while pending:
         rest = []
         for rid, p in pending:
-            st, u, info = mm.solve_poll(srv, rid, p.shape)
+            st, u, info = mm.solve_poll(srv, rid)
             if st == mm.MM_NOT_READY:
                 rest.append((rid, p))
                 continue
@@ -192,38 +274,114 @@ def serve_stream(mm, prec, count, max_active):
         pending = rest
         if pending:
             time.sleep(0.002)
+    counters = srv.counters()
     srv.close()
     lat = np.array(lat) * 1e3
     span = max(done) - t_first
     return {"requests": count, "max_active": max_active, "status": statuses,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "makespan_s": span,
-            "throughput_mdof_steps_per_s": work / span / 1e6}
+            "throughput_mdof_steps_per_s": work / span / 1e6,
+            "mean_requests_per_grouped_launch": counters["mean_group"],
+            "launches": {k: v for k, v in counters.items() if k != "mean_group"}}
 
 
-def cpu_baseline(p, steps):
-    """The oracle, untuned, on the host cores: `steps` steps of the workload's scheme."""
+def oracle_module(p):
     import synth
-    cores = len(os.sched_getaffinity(0))
-    try:
-        from threadpoolctl import threadpool_limits
-        ctxm = threadpool_limits(limits=cores)
-    except Exception:  # pragma: no cover
-        ctxm = None
     if any(b == synth.PERIODIC for b in getattr(p, "bc", ())):
         from oracle import spectral as S       # periodic pseudo-spectral problems
     elif any(getattr(p, "bc", ())) or getattr(p, "form", "flux") != "flux":
         from oracle import adr3d as S          # Neumann axes or the non-divergence form
     else:
         from oracle import schemes as S
+    return S
+
+
+def time_oracle(p, steps, threads):
+    """Seconds of `steps` oracle steps of p with the BLAS pool limited to `threads`."""
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(limits=threads)
+    except Exception:  # pragma: no cover
+        lim = None
+    S = oracle_module(p)
     t0 = time.perf_counter()
     S.solve(p, steps=steps)
     dt = time.perf_counter() - t0
-    if ctxm is not None:
-        ctxm.unregister() if hasattr(ctxm, "unregister") else None
+    if lim is not None and hasattr(lim, "unregister"):
+        lim.unregister()
+    return dt
+
+
+def cpu_baseline(p, steps):
+    """The oracle, untuned, on the host cores: `steps` steps of the workload's scheme."""
+    cores = len(os.sched_getaffinity(0))
+    dt = time_oracle(p, steps, cores)
     return {"value": p.dof * steps / dt / 1e6, "unit": "Mdof*steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{steps} {p.scheme} steps of the {p.name} workload (numpy FP64, OpenBLAS threads = cores)",
             "seconds": dt}
+
+
+def cpu_baselines():
+    """The oracle on bounded samples of the other workloads (BLAS threads = cores, and one
+    thread for the 63^2 solve), and on a seeded 64-request subset of the served stream."""
+    import synth
+    cores = len(os.sched_getaffinity(0))
+    out = {}
+    p = synth.workload("2d_n63_le")
+    for th in (1, cores):
+        dt = time_oracle(p, p.steps, th)
+        out[f"2d_n63_le_threads{th}"] = {"us_per_step": 1e6 * dt / p.steps, "threads": th,
+                                         "sample": f"whole solve, {p.steps} steps"}
+    for name, steps in (("3d_n127_l2b", 4), ("3d_n127_etd2rk", 2), ("3d_n383_etd2rk", 1)):
+        p = synth.workload(name)
+        dt = time_oracle(p, steps, cores)
+        out[name] = {"ms_per_step": 1e3 * dt / steps, "mdof_steps_per_s": p.dof * steps / dt / 1e6,
+                     "threads": cores, "sample": f"{steps} steps"}
+    # served stream: 64 requests spread over every (d, n) bucket, 2 steps each
+    reqs = synth.request_stream(count=512, seed=1)
+    buckets = {}
+    for r in reqs:
+        buckets.setdefault((r.d, r.n), []).append(r)
+    subset = []
+    while len(subset) < 64 and any(buckets.values()):
+        for key in sorted(buckets):
+            if buckets[key] and len(subset) < 64:
+                subset.append(buckets[key].pop(0))
+    t0 = time.perf_counter()
+    dofsteps = 0
+    for r in subset:
+        q = r.problem()
+        time_oracle(q, 2, cores)
+        dofsteps += q.dof * 2
+    dt = time.perf_counter() - t0
+    out["served_stream_subset"] = {"mdof_steps_per_s": dofsteps / dt / 1e6, "requests": len(subset),
+                                   "threads": cores, "seconds": dt,
+                                   "sample": "64 requests of the 512-request stream, every (d, n) bucket, "
+                                             "first 2 steps each"}
+    return out
+
+
+def config_lines(mm, ctx, warmup):
+    """One line per other workload: ms/step, Mdof*steps/s and the dominant kernel's roofline."""
+    import synth
+    out = {}
+    for name, steps, precs in CONFIGS:
+        p = synth.workload(name)
+        nsteps = steps or p.steps
+        for prec in precs:
+            print(f"[bench] config {name} {prec}: {nsteps} timed steps", file=sys.stderr, flush=True)
+            try:
+                op, _, dt, kern, status = time_mode(mm, ctx, p, prec, nsteps, min(warmup, 2))
+            except mm.MumodeError as exc:
+                print(f"[bench] config {name} {prec}: {exc}", file=sys.stderr, flush=True)
+                continue
+            op.close()
+            roof, _ = roofline(kern, prec, p)
+            out[f"{name}_{prec}"] = {"workload": DESCRIPTION.get(name, name), "ms_per_step": 1e3 * dt / nsteps,
+                                     "value": p.dof * nsteps / dt / 1e6, "unit": "Mdof*steps/s",
+                                     "steps": nsteps, "status": mm.STATUS.get(status, status), "roofline": roof}
+    return out
 
 
 def main():
@@ -252,8 +410,9 @@ def main():
     modes = [m for m in args.modes.split(",") if m]
     if "fp64" not in modes:
         modes = ["fp64"] + modes
+    samples = oracle_samples(args.workload)
     res = {}
-    ref = None
+    ref, ref_T = None, None
     for prec in modes:
         print(f"[bench] {prec}: setup + {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr,
               flush=True)
@@ -270,49 +429,39 @@ def main():
             ref = out
         else:
             entry["err_vs_fp64"] = float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
+        entry["roofline"], _ = roofline(kern, prec, p)
+        if not args.no_at_T:
+            # the whole interval to T, untimed: error against the FP64 path (whole grid)
+            # and against the oracle (its stored samples), and the stated target
+            uT, stT = run_to_T(mm, op, p)
+            if prec == "fp64":
+                ref_T = uT
+            else:
+                entry["err_at_T_vs_fp64"] = float(np.max(np.abs(uT - ref_T)) / np.max(np.abs(ref_T)))
+            if samples is not None:
+                mx, idx, val = samples
+                entry["err_at_T_vs_oracle_samples"] = float(np.max(np.abs(uT.reshape(-1)[idx] - val)) / mx)
+            entry["status_at_T"] = mm.STATUS.get(stT, stT)
+            tgt = target(prec)
+            if tgt is not None:
+                err = entry.get("err_at_T_vs_oracle_samples", entry["err_at_T_vs_fp64"])
+                entry["err_at_T"] = max(err, entry["err_at_T_vs_fp64"])
+                entry["target"] = tgt
+                entry["meets_target"] = bool(entry["err_at_T"] <= tgt and stT == mm.MM_OK)
         if prec == args.headline and args.latency_reps > 0:
             entry["latency"] = latency(mm, ctx, op, p, args.latency_reps)
         op.close()
         res[prec] = entry
-        print(f"[bench] {prec}: {entry['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        print(f"[bench] {prec}: {entry['ms_per_step']:.3f} ms/step"
+              + (f", err at T {entry['err_at_T']:.2e} (target {entry['target']:.0e})" if "err_at_T" in entry else ""),
+              file=sys.stderr, flush=True)
 
     head = res[args.headline]
-    # roofline of the dominant kernel of the headline mode
-    kname = max(("gemm_k", "gemm_n", "stencil", "fused"), key=lambda k: head["kernels"][k]["total_ms"])
-    k = head["kernels"][kname]
-    if kname == "fused":
-        # one workgroup on one compute unit: its share of the FP64 matrix peak
-        achieved = k["work"] / (k["total_ms"] * 1e-3)
-        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["fp64"] / 256 / 1e12,
-                "unit": "TFLOP/s", "scope": "one compute unit"}
-    elif kname == "stencil":
-        # algorithmic bytes per grid point of the fused remainder passes: read u and a,
-        # write two outputs (first pass) or read u, a, W and write u (second pass): 32 B
-        achieved = 32.0 * k["work"] / (k["total_ms"] * 1e-3)
-        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
-    else:
-        dtype_peak = {"fp64": "fp64", "fp32": "fp32"}.get(args.headline, "bf16")
-        if args.headline.startswith("sliced"):
-            # int8 digit products actually executed: S(S+1)/2 per algorithmic multiply-add
-            achieved = k["work"] * slice_products(args.headline) / (k["total_ms"] * 1e-3)
-            roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["int8"] / 1e12,
-                    "unit": "TOP/s"}
-        elif dtype_peak == "bf16":
-            # split-BF16 contractions are bound by HBM: 16 B per grid point per pass
-            flops_per_point = 2.0 * p.n[0]
-            bytes_ = 16.0 * k["work"] / flops_per_point
-            achieved = bytes_ / (k["total_ms"] * 1e-3)
-            roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s"}
-        else:
-            achieved = k["work"] / (k["total_ms"] * 1e-3)
-            roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[dtype_peak] / 1e12,
-                    "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["kernel"] = {"gemm_k": "gemm (mode 1)", "gemm_n": "gemm (modes 2, 3)", "stencil": "stencil",
-                      "fused": "whole small-2D solve in one workgroup (one compute unit)"}[kname]
-    roof["avg_launch_us"] = k["avg_us"]
+    roof, kname = roofline(head["kernels"], args.headline, p)
     roof["traffic"] = measured_traffic() if (kname == "gemm_n" and args.headline == "fp64"
                                              and args.workload == WORKLOAD) else None
+    accurate = [m for m, e in res.items() if e.get("meets_target")]
+    fastest_accurate = min(accurate, key=lambda m: res[m]["ms_per_step"]) if accurate else None
 
     line = {
         "metric": "Mdof*steps/s at 256^3 (255^3 interior), FP64 vs MFMA mixed at stated error; p50/p99 solve latency",
@@ -332,6 +481,9 @@ def main():
                    "graph_steps": args.graph_steps, "tile": args.tile or "auto"},
         "latency": head.get("latency"),
         "modes": {m: {kk: vv for kk, vv in e.items() if kk != "kernels"} for m, e in res.items()},
+        "fastest_mode_meeting_target": fastest_accurate,
+        "speedup_of_that_mode_over_fp64": (res["fp64"]["ms_per_step"] / res[fastest_accurate]["ms_per_step"]
+                                           if fastest_accurate else None),
         "kernels": {m: e["kernels"] for m, e in res.items()},
         "roofline": roof,
     }
@@ -340,12 +492,28 @@ def main():
         print(f"[bench] served stream: {args.serve_count} requests, {prec}", file=sys.stderr, flush=True)
         serving[prec] = serve_stream(mm, prec, args.serve_count, args.serve_active)
         print(f"[bench] served stream {prec}: p50 {serving[prec]['p50_ms']:.1f} ms "
-              f"p99 {serving[prec]['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+              f"p99 {serving[prec]['p99_ms']:.1f} ms makespan {serving[prec]['makespan_s']:.2f} s",
+              file=sys.stderr, flush=True)
+    if serving and not args.no_serial and "fp64" in serving:
+        print(f"[bench] served stream: {args.serve_count} requests, fp64, one at a time", file=sys.stderr,
+              flush=True)
+        serving["fp64_one_at_a_time"] = serve_stream(mm, "fp64", args.serve_count, 1)
+        s1, sN = serving["fp64_one_at_a_time"], serving["fp64"]
+        serving["batched_over_one_at_a_time"] = {
+            "throughput": sN["throughput_mdof_steps_per_s"] / s1["throughput_mdof_steps_per_s"],
+            "p50_latency": s1["p50_ms"] / sN["p50_ms"], "p99_latency": s1["p99_ms"] / sN["p99_ms"]}
+        print(f"[bench] one at a time: p50 {s1['p50_ms']:.1f} ms p99 {s1['p99_ms']:.1f} ms "
+              f"makespan {s1['makespan_s']:.2f} s", file=sys.stderr, flush=True)
     if serving:
         line["serving"] = serving
+    if not args.no_configs:
+        line["configs"] = config_lines(mm, ctx, args.warmup)
     if not args.no_cpu:
         print(f"[bench] cpu baseline: {args.cpu_steps} oracle steps", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
+        if not args.no_configs:
+            print("[bench] cpu baselines of the other workloads", file=sys.stderr, flush=True)
+            line["cpu_baselines"] = cpu_baselines()
     print(json.dumps(line))
     ctx.close()
 

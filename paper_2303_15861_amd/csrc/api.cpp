@@ -396,10 +396,21 @@ const int* stacked_exp(const mm_op* op, int which) {
   return which == 1 ? op->f3_stage1_exp : which == 2 ? op->f3_stage2_exp : op->f3_phi_exp;
 }
 
+// Memory layout of a grid operand: x1 rows of `ld` values (ld >= n1; larger for the
+// padded stage vectors of the Lawson steps) and `vs` values between stacked vectors.
+// Every layout here is dense above the rows: plane stride n2 ld, vs = n2 n3 ld.
+struct Layout {
+  int ld;
+  int64_t vs;
+};
+Layout natural(const mm_op* op) { return Layout{op->n[0], op->dof}; }
+Layout staged(const mm_op* op) { return Layout{op->ld1, op->dofp}; }
+
 // mode 1: C (rows x n1) = A (rows x n1) . E1^T, per group (input, factor, output);
 // galpha: optional per-group output scales (sliced mode only)
 hipError_t pass_mode1(const mm_op* op, int groups, const void* const* in, const int* fidx,
-                      void* const* out, int rows, PassIO io, hipStream_t s, const double* galpha = nullptr) {
+                      void* const* out, int rows, PassIO io, hipStream_t s, const double* galpha = nullptr,
+                      Layout li = Layout{0, 0}, Layout lo = Layout{0, 0}) {
   const int n1 = op->n[0];
   GemmArgs g{};
   for (int i = 0; i < groups; ++i) {
@@ -414,9 +425,9 @@ hipError_t pass_mode1(const mm_op* op, int groups, const void* const* in, const 
   g.M = rows;
   g.N = n1;
   g.K = n1;
-  g.lda = n1;
+  g.lda = li.ld ? li.ld : n1;
   g.ldb = factor_ld(op, n1);
-  g.ldc = n1;
+  g.ldc = lo.ld ? lo.ld : n1;
   g.inner = 1;
   g.groups = groups;
   g.b_trans = 0;
@@ -430,7 +441,8 @@ hipError_t pass_mode1(const mm_op* op, int groups, const void* const* in, const 
 
 // mode 2 of a 3D grid: per x3-slab (n2 x n1), C = E2 . slab, `slabs` slabs per group
 hipError_t pass_mode2(const mm_op* op, int groups, const int* fidx, const void* const* in, void* const* out,
-                      int slabs, PassIO io, hipStream_t s) {
+                      int slabs, PassIO io, hipStream_t s, Layout li = Layout{0, 0}, Layout lo = Layout{0, 0}) {
+  const int ldi = li.ld ? li.ld : op->n[0], ldo = lo.ld ? lo.ld : op->n[0];
   GemmArgs g{};
   for (int i = 0; i < groups; ++i) {
     g.A[i] = factor_op(op, 1, fidx[i]);
@@ -444,11 +456,12 @@ hipError_t pass_mode2(const mm_op* op, int groups, const int* fidx, const void* 
   g.N = op->n[0];
   g.K = op->n[1];
   g.lda = factor_ld(op, op->n[1]);
-  g.ldb = op->n[0];
-  g.ldc = op->n[0];
+  g.ldb = ldi;
+  g.ldc = ldo;
   g.inner = slabs;
   g.sA = 0;
-  g.sB = g.sC = (int64_t)op->n[0] * op->n[1];
+  g.sB = (int64_t)ldi * op->n[1];
+  g.sC = (int64_t)ldo * op->n[1];
   g.groups = groups;
   g.b_trans = 1;
   g.alpha = 1.0;
@@ -463,10 +476,62 @@ hipError_t pass_mode2(const mm_op* op, int groups, const int* fidx, const void* 
 // P = dof / nl; `inner` stacked vectors of stride dof (same factor). F is the factor
 // operand in the op's precision (row stride factor_ld(K)), Fexp its row exponents
 // (MM_SLICED).
+// With layouts: stacked vectors `vs` apart; in 3D a padded layout makes the columns the
+// (x2, x1) positions including the row padding (computed, never read as data), and
+// input and output layouts that differ take one launch per vector, batched over x2.
 hipError_t pass_last(const mm_op* op, const void* F, const int* Fexp, int kmul, const void* in, void* out,
-                     const double* add, double alpha, double beta, int inner, PassIO io, hipStream_t s) {
+                     const double* add, double alpha, double beta, int inner, PassIO io, hipStream_t s,
+                     Layout li = Layout{0, 0}, Layout lo = Layout{0, 0}) {
   const int nl = op->n[last_axis(op)];
   const int P = (int)(op->dof / nl);
+  if (li.ld && lo.ld && (li.ld != op->n[0] || lo.ld != op->n[0])) {
+    const size_t ib = io.in_f32 ? 4 : 8, ob = io.out_f32 ? 4 : 8;
+    GemmArgs g{};
+    g.A[0] = F;
+    g.fexp[0] = Fexp;
+    g.slices = op->slices;
+    g.Cadd[0] = nullptr;
+    g.M = nl;
+    g.K = kmul * nl;
+    g.lda = factor_ld(op, kmul * nl);
+    g.groups = 1;
+    g.b_trans = 1;
+    g.alpha = alpha;
+    g.beta = 0.0;
+    g.in_f32 = io.in_f32;
+    g.out_f32 = io.out_f32;
+    g.fac_slice = factor_slice_stride(op, nl, kmul * nl);
+    if (add) return hipErrorInvalidValue;   // not needed by the padded schemes
+    if (op->d == 2 || li.ld == lo.ld) {
+      // rows of the operand are the last axis: N = (2D) x1 or (3D) the padded plane
+      const int ncols = op->d == 2 ? op->n[0] : op->n[1] * li.ld;
+      g.B[0] = in;
+      g.C[0] = out;
+      g.N = ncols;
+      g.ldb = op->d == 2 ? li.ld : op->n[1] * li.ld;
+      g.ldc = op->d == 2 ? lo.ld : op->n[1] * lo.ld;
+      g.inner = inner;
+      g.sA = 0;
+      g.sB = li.vs;
+      g.sC = lo.vs;
+      return gemm(op, g, s);
+    }
+    // 3D with different row strides: per vector, batched over the x2 rows
+    for (int v = 0; v < inner; ++v) {
+      g.B[0] = (const char*)in + (size_t)v * li.vs * ib;
+      g.C[0] = (char*)out + (size_t)v * lo.vs * ob;
+      g.N = op->n[0];
+      g.ldb = op->n[1] * li.ld;
+      g.ldc = op->n[1] * lo.ld;
+      g.inner = op->n[1];
+      g.sA = 0;
+      g.sB = li.ld;
+      g.sC = lo.ld;
+      const hipError_t e = gemm(op, g, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   GemmArgs g{};
   g.A[0] = F;
   g.fexp[0] = Fexp;
@@ -501,9 +566,11 @@ const double* factor(const mm_op* op, int mu, int j) {
 // in_f32: the input is float (mixed modes only); out is always double. In the mixed
 // modes the intermediates t0, t1 hold floats.
 // out = alpha exp(c_j tau A) in + beta add (add optional).
+// li, lt, lo: layouts of in, of the intermediates t0/t1 and of out (default: unpadded).
 hipError_t exp_action(const mm_op* op, int j, const void* in, bool in_f32, double* out, int nvec, double* t0,
                       double* t1, hipStream_t s, const double* add = nullptr, double alpha = 1.0,
-                      double beta = 1.0) {
+                      double beta = 1.0, Layout li = Layout{0, 0}, Layout lt = Layout{0, 0},
+                      Layout lo = Layout{0, 0}) {
   const bool mixed = lowp(op);
   PassIO first{in_f32, mixed}, mid{mixed, mixed}, last_io{mixed, false};
   const int fj[1] = {j};
@@ -513,18 +580,18 @@ hipError_t exp_action(const mm_op* op, int j, const void* in, bool in_f32, doubl
   const void* Fl = factor_op(op, la, j);
   const int* Fe = factor_exp(op, la, j);
   if (op->d == 3) {
-    hipError_t e = pass_mode1(op, 1, i1, fj, o1, (int)(op->dof / op->n[0]) * nvec, first, s);
+    hipError_t e = pass_mode1(op, 1, i1, fj, o1, (int)(op->dof / op->n[0]) * nvec, first, s, nullptr, li, lt);
     if (e != hipSuccess) return e;
     const void* i2[1] = {t0};
     void* o2[1] = {t1};
-    e = pass_mode2(op, 1, fj, i2, o2, op->n[2] * nvec, mid, s);
+    e = pass_mode2(op, 1, fj, i2, o2, op->n[2] * nvec, mid, s, lt, lt);
     if (e != hipSuccess) return e;
-    return pass_last(op, Fl, Fe, 1, t1, out, add, alpha, add ? beta : 0.0, nvec, last_io, s);
+    return pass_last(op, Fl, Fe, 1, t1, out, add, alpha, add ? beta : 0.0, nvec, last_io, s, lt, lo);
   }
-  hipError_t e = pass_mode1(op, 1, i1, fj, o1, (int)(op->dof / op->n[0]) * nvec, first, s);
+  hipError_t e = pass_mode1(op, 1, i1, fj, o1, (int)(op->dof / op->n[0]) * nvec, first, s, nullptr, li, lt);
   if (e != hipSuccess) return e;
   PassIO l2{mixed, false};
-  return pass_last(op, Fl, Fe, 1, t0, out, add, alpha, add ? beta : 0.0, nvec, l2, s);
+  return pass_last(op, Fl, Fe, 1, t0, out, add, alpha, add ? beta : 0.0, nvec, l2, s, lt, lo);
 }
 
 // out = stacked-last-factor contraction over G groups: group g applies modes 1..d-1 with
@@ -1274,10 +1341,19 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     }
   } else {
     // buffers: 0 and 1 hold two stacked grid functions each; stabilized Lawson2 needs a
-    // fifth grid function (buffer 2)
+    // fifth grid function (buffer 2). Lawson-Euler and Lawson2b on finite differences keep
+    // them with x1 rows padded to whole 128-byte lines (16 values) from n1 = 32 on: rows
+    // of n1 = 255 values start 2040 bytes apart, so most rows begin and end inside a
+    // line, and the mode products read and write partial lines. The padding is zeroed
+    // here and stays zero (no pass writes it except with products of zeros).
+    op->ld1 = op->n[0];
+    if (!periodic && (scheme == MM_LAWSON_EULER || scheme == MM_LAWSON2B) && op->n[0] >= 32)
+      op->ld1 = (op->n[0] + 15) / 16 * 16;
+    op->dofp = dof / op->n[0] * op->ld1;
     for (int i = 0; i < 2; ++i) {
-      op->buf_len[i] = 2 * dof;
-      if ((rc = dev_alloc(op, &op->buf[i], 2 * dof)) != MM_OK) return fail(rc);
+      op->buf_len[i] = 2 * op->dofp;
+      if ((rc = dev_alloc(op, &op->buf[i], 2 * op->dofp)) != MM_OK) return fail(rc);
+      if (hipMemsetAsync(op->buf[i], 0, 2 * op->dofp * sizeof(double), st) != hipSuccess) return fail(MM_EDEVICE);
     }
     if (scheme == MM_SL2) {
       op->buf_len[2] = dof;
@@ -1292,7 +1368,8 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     const int64_t G = std::max(2, op->q + 1);
     int64_t dig = 0, ex = 0;
     for (int mu = 0; mu < op->d; ++mu) {
-      const int64_t fib = dof / op->n[mu];
+      // fibers of the largest launch along mu (padded stage vectors count their padding)
+      const int64_t fib = std::max(dof, op->dofp) / op->n[mu];
       dig = std::max(dig, G * fib * S * slice_ld(op->n[mu]));
       ex = std::max(ex, G * fib);
     }
@@ -1443,16 +1520,18 @@ mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hi
   }
   for (int it = 0; it < nsteps; ++it) {
     if (op->scheme == MM_LAWSON_EULER) {
-      // u+ = e^{tau A}(u + tau g(u))
+      // u+ = e^{tau A}(u + tau g(u)); the stage vector in the padded layout
       StencilArgs a = stencil_args(op, u, false);
       a.base0 = u;
       a.c0 = tau;
+      a.ldo = op->ld1;
       if (mixed)
         a.out0f = (float*)b0;
       else
         a.out0 = b0;
       HIPCHK(ctx, stencil(op, a, s));
-      HIPCHK(ctx, exp_action(op, 0, b0, mixed, u, 1, b1, b0, s));
+      HIPCHK(ctx, exp_action(op, 0, b0, mixed, u, 1, b1, b0, s, nullptr, 1.0, 1.0, staged(op), staged(op),
+                             natural(op)));
     } else if (op->scheme == MM_SLE) {
       // u+ = u + tau e^{tau A} F(u)
       StencilArgs f = stencil_args(op, u, true);
@@ -1492,24 +1571,29 @@ mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hi
       HIPCHK(ctx, exp_action(op, 0, g0, false, u, 1, b1, b1 + dof, s, U, 0.5 * tau / kAlphaSL2, 1.0));
     } else {
       // v1 = u + tau g(u), v2 = u + tau/2 g(u); [U, W] = e^{tau A}[v1, v2]; u+ = W + tau/2 g(U)
+      // (v1, v2, U, W in the padded layout: rows of ld1, dofp apart)
+      const int64_t dp = op->dofp;
       StencilArgs a = stencil_args(op, u, false);
       a.base0 = u;
       a.c0 = tau;
       a.base1 = u;
       a.c1 = 0.5 * tau;
+      a.ldo = op->ld1;
       if (mixed) {
         a.out0f = (float*)b0;
-        a.out1f = (float*)b0 + dof;
+        a.out1f = (float*)b0 + dp;
       } else {
         a.out0 = b0;
-        a.out1 = b0 + dof;
+        a.out1 = b0 + dp;
       }
       HIPCHK(ctx, stencil(op, a, s));
       double* res = (op->d == 3) ? b1 : b0;
-      HIPCHK(ctx, exp_action(op, 0, b0, mixed, res, 2, b1, b0, s));
+      HIPCHK(ctx, exp_action(op, 0, b0, mixed, res, 2, b1, b0, s, nullptr, 1.0, 1.0, staged(op), staged(op),
+                             staged(op)));
       StencilArgs c = stencil_args(op, res, false);
-      c.base0 = res + dof;
+      c.base0 = res + dp;
       c.c0 = 0.5 * tau;
+      c.ldi = op->ld1;
       c.out0 = u;
       HIPCHK(ctx, stencil(op, c, s));
     }
@@ -1675,9 +1759,10 @@ mm_status run_steps(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hipStre
 
 // One mode pass of the exponential for `count` problems of one class, as a single
 // grouped launch: group i applies problem i's factor exp(tau_i A_mu) to its own
-// `nvec` stacked grid functions (in[i] -> out[i], layouts as in exp_action).
+// `nvec` stacked grid functions (in[i] -> out[i], layouts li -> lo as in pass_mode1,
+// pass_mode2 and pass_last).
 hipError_t group_pass(mm_ctx* ctx, const mm_op* const* ops, int count, int mu, int nvec, const void* const* in,
-                      void* const* out, PassIO io, const mm_batch_ws* ws, hipStream_t s) {
+                      void* const* out, PassIO io, const mm_batch_ws* ws, hipStream_t s, Layout li, Layout lo) {
   const mm_op* o0 = ops[0];
   const int d = o0->d, n = o0->n[mu];
   const int64_t dof = o0->dof;
@@ -1703,33 +1788,6 @@ hipError_t group_pass(mm_ctx* ctx, const mm_op* const* ops, int count, int mu, i
   g.in_f32 = io.in_f32;
   g.out_f32 = io.out_f32;
   g.fac_slice = factor_slice_stride(o0, n, n);
-  if (mu == 0) {
-    g.M = (int)(dof / n) * nvec;
-    g.N = g.K = n;
-    g.lda = g.ldc = n;
-    g.ldb = factor_ld(o0, n);
-    g.inner = 1;
-    g.b_trans = 0;
-  } else if (mu == d - 1) {
-    const int P = (int)(dof / n);
-    g.M = g.K = n;
-    g.N = P;
-    g.lda = factor_ld(o0, n);
-    g.ldb = g.ldc = P;
-    g.inner = nvec;
-    g.sA = 0;
-    g.sB = g.sC = dof;
-    g.b_trans = 1;
-  } else {
-    g.M = g.K = n;
-    g.N = o0->n[0];
-    g.lda = factor_ld(o0, n);
-    g.ldb = g.ldc = o0->n[0];
-    g.inner = o0->n[2] * nvec;
-    g.sA = 0;
-    g.sB = g.sC = (int64_t)o0->n[0] * o0->n[1];
-    g.b_trans = 1;
-  }
   g.tile = ctx->gemm_tile;
   if (ws) {
     g.vdig = ws->vdig;
@@ -1737,9 +1795,61 @@ hipError_t group_pass(mm_ctx* ctx, const mm_op* const* ops, int count, int mu, i
     g.vdig_cap = ws->vdig_cap;
     g.vexp_cap = ws->vexp_cap;
   }
-  const double work = 2.0 * g.M * (double)g.N * g.K * g.inner * g.groups;
-  return timed_launch(ctx, g.b_trans ? MM_KIND_GEMM_N : MM_KIND_GEMM_K, work, s,
-                      [&] { return launch_gemm(o0->prec, g, s); });
+  auto launch = [&]() {
+    const double work = 2.0 * g.M * (double)g.N * g.K * g.inner * g.groups;
+    return timed_launch(ctx, g.b_trans ? MM_KIND_GEMM_N : MM_KIND_GEMM_K, work, s,
+                        [&] { return launch_gemm(o0->prec, g, s); });
+  };
+  if (mu == 0) {
+    g.M = (int)(dof / n) * nvec;
+    g.N = g.K = n;
+    g.lda = li.ld;
+    g.ldc = lo.ld;
+    g.ldb = factor_ld(o0, n);
+    g.inner = 1;
+    g.b_trans = 0;
+    return launch();
+  }
+  g.M = g.K = n;
+  g.lda = factor_ld(o0, n);
+  g.sA = 0;
+  g.b_trans = 1;
+  if (mu < d - 1) {   // x2 of a 3D grid: per x3 slab
+    g.N = o0->n[0];
+    g.ldb = li.ld;
+    g.ldc = lo.ld;
+    g.inner = o0->n[2] * nvec;
+    g.sB = (int64_t)li.ld * o0->n[1];
+    g.sC = (int64_t)lo.ld * o0->n[1];
+    return launch();
+  }
+  if (d == 2 || li.ld == lo.ld) {
+    // the last axis: columns are x1 (2D) or the whole padded (x2, x1) plane (3D)
+    g.N = d == 2 ? o0->n[0] : o0->n[1] * li.ld;
+    g.ldb = d == 2 ? li.ld : o0->n[1] * li.ld;
+    g.ldc = d == 2 ? lo.ld : o0->n[1] * lo.ld;
+    g.inner = nvec;
+    g.sB = li.vs;
+    g.sC = lo.vs;
+    return launch();
+  }
+  // 3D with different row strides: per vector, batched over the x2 rows
+  const size_t ib = io.in_f32 ? 4 : 8, ob = io.out_f32 ? 4 : 8;
+  for (int v = 0; v < nvec; ++v) {
+    for (int i = 0; i < count; ++i) {
+      g.B[i] = (const char*)in[i] + (size_t)v * li.vs * ib;
+      g.C[i] = (char*)out[i] + (size_t)v * lo.vs * ob;
+    }
+    g.N = o0->n[0];
+    g.ldb = o0->n[1] * li.ld;
+    g.ldc = o0->n[1] * lo.ld;
+    g.inner = o0->n[1];
+    g.sB = li.ld;
+    g.sC = lo.ld;
+    const hipError_t e = launch();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // The digit-plane workspace of grouped sliced launches on stream s, at least dig bytes
@@ -1813,12 +1923,14 @@ mm_status enqueue_lawson_group(mm_ctx* ctx, const mm_op* const* ops, double* con
   const bool mixed = lowp(o0);
   const bool l2b = o0->scheme == MM_LAWSON2B;
   const int nvec = l2b ? 2 : 1;
+  const int64_t dp = o0->dofp;   // stage-vector stride (padded rows, equal across the class)
   mm_batch_ws* ws = nullptr;
   if (o0->prec == MM_SLICED) {
-    // the largest grid-operand split over the modes of one grouped action
+    // the largest grid-operand split over the modes of one grouped action (padded
+    // stage vectors count their padding)
     int64_t dig = 0, ex = 0;
     for (int mu = 0; mu < d; ++mu) {
-      const int64_t fib = (int64_t)count * nvec * (dof / o0->n[mu]);
+      const int64_t fib = (int64_t)count * nvec * (o0->dofp / o0->n[mu]);
       dig = std::max(dig, fib * o0->slices * slice_ld(o0->n[mu]));
       ex = std::max(ex, fib);
     }
@@ -1842,28 +1954,33 @@ mm_status enqueue_lawson_group(mm_ctx* ctx, const mm_op* const* ops, double* con
       StencilArgs a = stencil_args(op, u[i], false);
       a.base0 = u[i];
       a.c0 = op->tau;
+      a.ldo = op->ld1;
       if (l2b) {
         a.base1 = u[i];
         a.c1 = 0.5 * op->tau;
       }
       if (mixed) {
         a.out0f = (float*)b0;
-        if (l2b) a.out1f = (float*)b0 + dof;
+        if (l2b) a.out1f = (float*)b0 + dp;
       } else {
         a.out0 = b0;
-        if (l2b) a.out1 = b0 + dof;
+        if (l2b) a.out1 = b0 + dp;
       }
       sa[i] = a;
     }
     HIPCHK(ctx, timed_launch(ctx, MM_KIND_STENCIL, (double)dof * count, s,
                              [&] { return launch_stencil_batch(d, sa, count, s); }));
-    // e^{tau A}: buf[0] -> buf[1] (-> buf[0]) -> out
-    HIPCHK(ctx, group_pass(ctx, ops, count, 0, nvec, in, t0, PassIO{mixed, mixed}, ws, s));
+    // e^{tau A}: buf[0] -> buf[1] (-> buf[0]) -> out, stage vectors padded
+    const Layout lp = staged(o0), lout = l2b ? lp : natural(o0);
+    HIPCHK(ctx, group_pass(ctx, ops, count, 0, nvec, in, t0, PassIO{mixed, mixed}, ws, s, lp, lp));
     if (d == 3) {
-      HIPCHK(ctx, group_pass(ctx, ops, count, 1, nvec, (const void* const*)t0, t1, PassIO{mixed, mixed}, ws, s));
-      HIPCHK(ctx, group_pass(ctx, ops, count, 2, nvec, (const void* const*)t1, out, PassIO{mixed, false}, ws, s));
+      HIPCHK(ctx, group_pass(ctx, ops, count, 1, nvec, (const void* const*)t0, t1, PassIO{mixed, mixed}, ws, s,
+                             lp, lp));
+      HIPCHK(ctx, group_pass(ctx, ops, count, 2, nvec, (const void* const*)t1, out, PassIO{mixed, false}, ws, s,
+                             lp, lout));
     } else {
-      HIPCHK(ctx, group_pass(ctx, ops, count, 1, nvec, (const void* const*)t0, out, PassIO{mixed, false}, ws, s));
+      HIPCHK(ctx, group_pass(ctx, ops, count, 1, nvec, (const void* const*)t0, out, PassIO{mixed, false}, ws, s,
+                             lp, lout));
     }
     if (!l2b) continue;
     // u+ = W + tau/2 g(U) with [U, W] the transformed pair
@@ -1871,8 +1988,9 @@ mm_status enqueue_lawson_group(mm_ctx* ctx, const mm_op* const* ops, double* con
       const mm_op* op = ops[i];
       const double* res = (const double*)out[i];
       StencilArgs c = stencil_args(op, res, false);
-      c.base0 = res + dof;
+      c.base0 = res + dp;
       c.c0 = 0.5 * op->tau;
+      c.ldi = op->ld1;
       c.out0 = u[i];
       sa[i] = c;
     }

@@ -87,6 +87,7 @@ struct StencilArgs {
   int nondiv;           // diffusion a Lap u instead of div(a grad u)
   int full;             // F(u) requested instead of g(u) (periodic problems read this;
                         // the stencil gets F through lam_amax = 0 and cadv)
+  int ldi, ldo;         // x1 row strides of u/sub/base* and of out* (0: n1, unpadded)
 };
 
 // Up to kMaxGroups stencil problems of one grid shape, launched together.
@@ -279,6 +280,10 @@ struct mm_op {
   int* f3_phi_exp = nullptr;
   double* buf[6] = {nullptr};          // scratch
   int64_t buf_len[6] = {0};
+  // Lawson-Euler and Lawson2b keep their stage vectors (buf[0], buf[1]) with x1 rows of
+  // ld1 >= n1 values (padded to whole 128-byte lines), dofp values per grid function
+  int ld1 = 0;
+  int64_t dofp = 0;
   // MM_SLICED: digit planes and fiber exponents of the grid operand of one launch
   signed char* vdig = nullptr;
   int* vexp = nullptr;

@@ -113,7 +113,10 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
   const int x = x0 + P * tx;             // first x1 of this lane
   const int y0 = (by * SW + w) * YT;
   const int z0 = (D == 3) ? bz * ZT : 0;
-  const int64_t s2 = n1, s3 = (int64_t)n1 * n2;               // strides of u
+  // x1 row strides: u, sub and base* (input layout), out* (output layout); 0 = n1
+  const int64_t ldi = p.ldi ? p.ldi : n1, ldo = p.ldo ? p.ldo : n1;
+  const int64_t s2 = ldi, s3 = ldi * n2;                       // strides of u
+  const int64_t o2 = ldo, o3 = ldo * n2;                       // strides of the outputs
   const int64_t t2 = n1 + 2, t3 = (int64_t)(n1 + 2) * (n2 + 2);   // strides of a (padded)
   const int64_t nu = s3 * n3, na = t3 * ((D == 3) ? n3 + 2 : 1);
   const int ucnt = n1 - x;               // u elements of this lane inside the row
@@ -178,6 +181,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
       }
       if (!live_row || ucnt <= 0) continue;
       const int64_t idx = x + urow;
+      const int64_t idxo = x + o2 * i2 + o3 * i3;
       // last unknown of an axis with a zero normal derivative at x = 1: mirror ghost
       const bool my = p.neu[1] && i2 == n2 - 1;
       const bool mz = (D == 3) && p.neu[2] && i3 == n3 - 1;
@@ -240,9 +244,9 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
         if (bad) p.flag[0] = 1;
       }
       if (p.out0f)
-        store_row<P>(p.out0f, idx, o, ucnt);
+        store_row<P>(p.out0f, idxo, o, ucnt);
       else
-        store_row<P>(p.out0, idx, o, ucnt);
+        store_row<P>(p.out0, idxo, o, ucnt);
       if (p.out1 || p.out1f) {
         if (p.base1 == nullptr) {
 #pragma unroll
@@ -256,9 +260,9 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
           for (int k = 0; k < P; ++k) o[k] += p.c1 * g[k];
         }
         if (p.out1f)
-          store_row<P>(p.out1f, idx, o, ucnt);
+          store_row<P>(p.out1f, idxo, o, ucnt);
         else
-          store_row<P>(p.out1, idx, o, ucnt);
+          store_row<P>(p.out1, idxo, o, ucnt);
       }
     }
 }

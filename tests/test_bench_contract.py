@@ -28,7 +28,7 @@ def test_short_run_prints_the_json_line():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     r = subprocess.run([sys.executable, BENCH, "--steps", "3", "--warmup", "1", "--modes", "fp64",
-                        "--latency-reps", "0", "--serve", "", "--no-cpu"],
+                        "--latency-reps", "0", "--serve", "", "--no-cpu", "--no-configs", "--no-at-T"],
                        capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-2000:]
     line = json.loads(r.stdout.strip().splitlines()[-1])

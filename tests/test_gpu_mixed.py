@@ -1,17 +1,24 @@
 """Mixed-precision contractions against the FP64 oracle.
 
-Bars (relative to max |oracle|, smooth data). A mode product of length K whose
+Action bars (relative to max |oracle|, smooth data). A mode product of length K whose
 operands are rounded to a t-bit significand (u_t = 2^-t) and summed in FP32 errs by
 about (2 u_t + sqrt(K) u_24) |E||v| with random-walk accumulation; the heat-kernel
 factors have row sums of |E| at most 1. Three passes per action give
     eps_action = 3 (2 u_t + sqrt(256) u_24):
     FP32   (t = 24): 3.2e-6        BF16x6 (t = 24): 3.2e-6
     BF16x3 (t = 16, hi + lo, lo*lo dropped ~ 2^-16): 9.4e-5
-A whole solve carries one action error per step, and a stage that applies g to an
-action's output without a following exponential (the last stage of Lawson2b)
+
+Solve bars. A whole solve carries one action error per step, and a stage that applies
+g to an action's output without a following exponential (the last stage of Lawson2b)
 multiplies the high-frequency part of that error by up to
-    amp = 1 + 2 d tau (a_max - a_min) / h_min^2
-(|g| <= sum_mu 4 |abar - a_max| / h_mu^2). The solve bar is eps_action * amp.
+    amp = 1 + 2 d tau (a_max - a_min) / h_min^2,
+so eps_action * amp bounds the error; at 127^3 that is 158 times eps_action, and the
+measured errors sit 14 to 100 times below it. The solve bars are therefore three times
+the errors this build measures on MI355X (the kernels are deterministic), which fails
+any several-fold loss of accuracy; the amplification bound is asserted as well. None
+of these modes meets the stated targets of the 255^3 workload (1e-6 for FP32, 1e-9 for
+the split modes) under Lawson2b: 24 or 16 significand bits times the amplification
+(about 700 there) cannot. The exact-slice mode does (tests/test_gpu_full_size.py).
 """
 import numpy as np
 import pytest
@@ -77,6 +84,15 @@ def test_mixed_exp_action(mm, ctx, prec, n):
     assert err <= EPS_ACTION[prec]
 
 
+# relative errors measured on MI355X (this build) for the cases of test_mixed_solve
+MEASURED = {("fp32", "l2b", (48, 40, 36)): 1.33e-6, ("bf16x6", "l2b", (48, 40, 36)): 1.27e-6,
+            ("bf16x3", "l2b", (48, 40, 36)): 4.73e-5, ("fp32", "le", (63, 63)): 6.50e-7,
+            ("bf16x6", "le", (63, 63)): 3.76e-7, ("bf16x3", "le", (63, 63)): 2.81e-5,
+            ("fp32", "etd2rk", (30, 28, 26)): 9.34e-7, ("bf16x6", "etd2rk", (30, 28, 26)): 8.99e-7,
+            ("bf16x3", "etd2rk", (30, 28, 26)): 2.76e-5, ("fp32", "l2b", (127, 127, 127)): 2.78e-5,
+            ("bf16x6", "l2b", (127, 127, 127)): 2.46e-5, ("bf16x3", "l2b", (127, 127, 127)): 1.07e-4}
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x6", "bf16x3"])
 @pytest.mark.parametrize("scheme,n,steps", [("l2b", (48, 40, 36), 20), ("le", (63, 63), 20),
                                             ("etd2rk", (30, 28, 26), 10), ("l2b", (127, 127, 127), 10)])
@@ -90,6 +106,8 @@ def test_mixed_solve(mm, ctx, prec, scheme, n, steps):
     op.close()
     assert status == mm.MM_OK
     err = relerr(got, S.solve(p))
-    bar = EPS_ACTION[prec] * amplification(p)
-    print(f"{prec} {scheme} {n} x{steps} solve err {err:.3e} (bar {bar:.1e})")
+    bound = EPS_ACTION[prec] * amplification(p)
+    bar = 3.0 * MEASURED[(prec, scheme, n)]
+    print(f"{prec} {scheme} {n} x{steps} solve err {err:.3e} (bar {bar:.1e}, bound {bound:.1e})")
+    assert err <= bound
     assert err <= bar
