@@ -295,6 +295,8 @@ hipError_t mode_product64(const mm_op* op, int mu, const double* M, const double
 // side fills more of the chip than running them one after another.
 hipError_t spectral_remainder(const mm_op* op, const StencilArgs& a, hipStream_t s) {
   const int64_t dof = op->dof;
+  // the pointwise pass writes FP64 or FP32 stage outputs only (no digit planes)
+  if (a.dig || (!a.out0 && !a.out0f)) return hipErrorInvalidValue;
   const bool nondiv = op->form == MM_FORM_NONDIV;
   hipError_t e = hipSuccess;
   if (op->d > 1) {
@@ -348,6 +350,7 @@ hipError_t stencil(const mm_op* op, const StencilArgs& a, hipStream_t s) {
 // double, C is written as float (out_f32) or double. FP64 ops always use double.
 struct PassIO {
   bool in_f32 = false, out_f32 = false;
+  bool ready = false;   // MM_SLICED mode 1: the grid operand is already split (by the stencil)
 };
 
 // Low-precision modes pass FP32 values between the passes of an action.
@@ -436,6 +439,7 @@ hipError_t pass_mode1(const mm_op* op, int groups, const void* const* in, const 
   g.in_f32 = io.in_f32;
   g.out_f32 = io.out_f32;
   g.fac_slice = factor_slice_stride(op, n1, n1);
+  g.vready = io.ready;
   return gemm(op, g, s);
 }
 
@@ -570,9 +574,9 @@ const double* factor(const mm_op* op, int mu, int j) {
 hipError_t exp_action(const mm_op* op, int j, const void* in, bool in_f32, double* out, int nvec, double* t0,
                       double* t1, hipStream_t s, const double* add = nullptr, double alpha = 1.0,
                       double beta = 1.0, Layout li = Layout{0, 0}, Layout lt = Layout{0, 0},
-                      Layout lo = Layout{0, 0}) {
+                      Layout lo = Layout{0, 0}, bool in_digits = false) {
   const bool mixed = lowp(op);
-  PassIO first{in_f32, mixed}, mid{mixed, mixed}, last_io{mixed, false};
+  PassIO first{in_f32, mixed, in_digits}, mid{mixed, mixed}, last_io{mixed, false};
   const int fj[1] = {j};
   const void* i1[1] = {in};
   void* o1[1] = {t0};
@@ -752,6 +756,24 @@ bool eigen_closed_form(int n, double s, double delta, double t, std::vector<doub
       R[(size_t)k * n + j] = sjk / dpow[j];                  // (S D^-1)[k][j]
     }
   return true;
+}
+
+// MM_SLICED Lawson steps: the first stencil pass writes its stage vectors (nvec of them,
+// stacked as operand rows) straight into the digit workspace of the mode-1 product, so
+// that product skips its split pass. Needs rows that one stencil wave covers.
+bool stencil_digits(const mm_op* op) {
+  return op->prec == MM_SLICED && !op->periodic && stencil_row_in_one_wave(op->n[0]);
+}
+
+void set_stencil_digits(StencilArgs& a, const mm_op* op, signed char* dig, int* dexp, int nvec) {
+  const int64_t rows = op->dof / op->n[0];   // operand rows of one stage vector
+  a.dig = dig;
+  a.dexp = dexp;
+  a.dS = op->slices;
+  a.dplane = rows * nvec * slice_ld(op->n[0]);
+  a.drow1 = nvec > 1 ? rows : 0;
+  a.out0 = nullptr;
+  a.out1 = nullptr;
 }
 
 mm_status check_op(mm_ctx* ctx, const mm_op* op) {
@@ -1525,13 +1547,16 @@ mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hi
       a.base0 = u;
       a.c0 = tau;
       a.ldo = op->ld1;
-      if (mixed)
+      const bool dg = stencil_digits(op);
+      if (dg)
+        set_stencil_digits(a, op, op->vdig, op->vexp, 1);
+      else if (mixed)
         a.out0f = (float*)b0;
       else
         a.out0 = b0;
       HIPCHK(ctx, stencil(op, a, s));
       HIPCHK(ctx, exp_action(op, 0, b0, mixed, u, 1, b1, b0, s, nullptr, 1.0, 1.0, staged(op), staged(op),
-                             natural(op)));
+                             natural(op), dg));
     } else if (op->scheme == MM_SLE) {
       // u+ = u + tau e^{tau A} F(u)
       StencilArgs f = stencil_args(op, u, true);
@@ -1579,7 +1604,10 @@ mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hi
       a.base1 = u;
       a.c1 = 0.5 * tau;
       a.ldo = op->ld1;
-      if (mixed) {
+      const bool dg = stencil_digits(op);
+      if (dg) {
+        set_stencil_digits(a, op, op->vdig, op->vexp, 2);
+      } else if (mixed) {
         a.out0f = (float*)b0;
         a.out1f = (float*)b0 + dp;
       } else {
@@ -1589,7 +1617,7 @@ mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hi
       HIPCHK(ctx, stencil(op, a, s));
       double* res = (op->d == 3) ? b1 : b0;
       HIPCHK(ctx, exp_action(op, 0, b0, mixed, res, 2, b1, b0, s, nullptr, 1.0, 1.0, staged(op), staged(op),
-                             staged(op)));
+                             staged(op), dg));
       StencilArgs c = stencil_args(op, res, false);
       c.base0 = res + dp;
       c.c0 = 0.5 * tau;
@@ -1789,6 +1817,7 @@ hipError_t group_pass(mm_ctx* ctx, const mm_op* const* ops, int count, int mu, i
   g.out_f32 = io.out_f32;
   g.fac_slice = factor_slice_stride(o0, n, n);
   g.tile = ctx->gemm_tile;
+  g.vready = io.ready;
   if (ws) {
     g.vdig = ws->vdig;
     g.vexp = ws->vexp;
@@ -1946,6 +1975,10 @@ mm_status enqueue_lawson_group(mm_ctx* ctx, const mm_op* const* ops, double* con
     t1[i] = ops[i]->buf[0];
     out[i] = l2b ? (d == 3 ? ops[i]->buf[1] : ops[i]->buf[0]) : u[i];
   }
+  // sliced: the first stencil pass writes the mode-1 operand's digits into each
+  // problem's slot of the group workspace (group i at i S plane bytes, i F exponents)
+  const bool dg = stencil_digits(o0);
+  const int64_t fib1 = (int64_t)nvec * (dof / o0->n[0]);
   for (int it = 0; it < nsteps; ++it) {
     // v1 = u + tau g(u) (and for Lawson2b v2 = u + tau/2 g(u)) into buf[0]
     for (int i = 0; i < count; ++i) {
@@ -1959,7 +1992,10 @@ mm_status enqueue_lawson_group(mm_ctx* ctx, const mm_op* const* ops, double* con
         a.base1 = u[i];
         a.c1 = 0.5 * op->tau;
       }
-      if (mixed) {
+      if (dg) {
+        set_stencil_digits(a, op, ws->vdig + (int64_t)i * o0->slices * fib1 * slice_ld(o0->n[0]), ws->vexp + i * fib1,
+                           nvec);
+      } else if (mixed) {
         a.out0f = (float*)b0;
         if (l2b) a.out1f = (float*)b0 + dp;
       } else {
@@ -1972,7 +2008,7 @@ mm_status enqueue_lawson_group(mm_ctx* ctx, const mm_op* const* ops, double* con
                              [&] { return launch_stencil_batch(d, sa, count, s); }));
     // e^{tau A}: buf[0] -> buf[1] (-> buf[0]) -> out, stage vectors padded
     const Layout lp = staged(o0), lout = l2b ? lp : natural(o0);
-    HIPCHK(ctx, group_pass(ctx, ops, count, 0, nvec, in, t0, PassIO{mixed, mixed}, ws, s, lp, lp));
+    HIPCHK(ctx, group_pass(ctx, ops, count, 0, nvec, in, t0, PassIO{mixed, mixed, dg}, ws, s, lp, lp));
     if (d == 3) {
       HIPCHK(ctx, group_pass(ctx, ops, count, 1, nvec, (const void* const*)t0, t1, PassIO{mixed, mixed}, ws, s,
                              lp, lp));

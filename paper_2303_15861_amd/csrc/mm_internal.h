@@ -43,10 +43,13 @@ struct GemmArgs {
   const int* fexp[kMaxGroups];
   double galpha[kMaxGroups];   // MM_SLICED: extra per-group output scale (0 = none)
   // MM_SLICED: workspace for the digit planes and fiber exponents of the grid operand
-  // (sliced_workspace() bytes and ints for this launch)
+  // (sliced_workspace() bytes and ints for this launch); vready: the grid operand's
+  // digits and exponents are already there (written by the stencil), so the launch
+  // skips its split pass and does not read the FP64 operand
   signed char* vdig;
   int* vexp;
   int64_t vdig_cap, vexp_cap;
+  int vready;
   // filled by the launcher
   int tiles_m, tiles_n, total, per_xcd;
 };
@@ -88,7 +91,19 @@ struct StencilArgs {
   int full;             // F(u) requested instead of g(u) (periodic problems read this;
                         // the stencil gets F through lam_amax = 0 and cadv)
   int ldi, ldo;         // x1 row strides of u/sub/base* and of out* (0: n1, unpadded)
+  // MM_SLICED, rows of n1 <= 64 P values (one wave per row): out0 (and out1) are written
+  // not in FP64 but as the grid operand of the mode-1 product, split into dS digit
+  // planes of rows slice_ld(n1) (dplane bytes per plane) with one exponent per row in
+  // dexp, the layout and definition of the separate grid split; out0 of grid row r is
+  // operand row r, out1 operand row drow1 + r
+  signed char* dig;
+  int* dexp;
+  int dS;
+  int64_t dplane, drow1;
 };
+// whether every x1 row of n1 points is covered by one wave of the stencil (the condition
+// of the digit output)
+bool stencil_row_in_one_wave(int n1);
 
 // Up to kMaxGroups stencil problems of one grid shape, launched together.
 struct StencilBatch {

@@ -24,6 +24,7 @@
 // per 64-row output tile). Workgroup tile 64 x 64, four waves of 32 x 32, one
 // accumulator per digit level.
 #include "mm_internal.h"
+#include "slice_digits.h"
 
 namespace mm {
 
@@ -38,52 +39,6 @@ constexpr int PI8 = 80;     // LDS row pitch in bytes (chosen so that 16 lanes o
                             // consecutive rows would hit 64 banks once; gfx950's bank-conflict
                             // counter still counts conflicts on this kernel's LDS accesses)
 constexpr int TH = 256;
-
-// Balanced base-256 digits of x relative to exponent e, packed: byte i of (lo, hi) is
-// b_i (least significant first) as a two's-complement int8.
-template <int S>
-__device__ __forceinline__ void slice_bytes(double x, int e, unsigned& lo, unsigned& hi) {
-  const double y = __builtin_rint(__builtin_ldexp(x, 8 * S - 2 - e));   // |y| <= 2^(8S-2)
-  const double hf = __builtin_floor(y * 0x1p-32);
-  const unsigned l = (unsigned)__builtin_fma(-hf, 0x1p32, y);           // exact, in [0, 2^32)
-  const int h = (int)hf;
-  constexpr unsigned long long C = 0x8080808080808080ull >> (64 - 8 * S);
-  const unsigned long long Y = ((((unsigned long long)(unsigned)h) << 32) | l) + C;
-  lo = (unsigned)Y ^ 0x80808080u;
-  hi = (unsigned)(Y >> 32) ^ 0x80808080u;
-}
-
-// o[j] = byte j of w0, w1, w2, w3 (in that order, lowest byte first)
-__device__ __forceinline__ void transpose4(unsigned w0, unsigned w1, unsigned w2, unsigned w3, unsigned (&o)[4]) {
-  const unsigned t0 = __builtin_amdgcn_perm(w1, w0, 0x05010400u);   // w0.b0 w1.b0 w0.b1 w1.b1
-  const unsigned t1 = __builtin_amdgcn_perm(w1, w0, 0x07030602u);   // w0.b2 w1.b2 w0.b3 w1.b3
-  const unsigned t2 = __builtin_amdgcn_perm(w3, w2, 0x05010400u);
-  const unsigned t3 = __builtin_amdgcn_perm(w3, w2, 0x07030602u);
-  o[0] = __builtin_amdgcn_perm(t2, t0, 0x05040100u);
-  o[1] = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
-  o[2] = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
-  o[3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
-}
-
-// Digit planes (most significant first) of four consecutive values: pl[s] holds digit
-// S-1-s of v0..v3 in its bytes 0..3.
-template <int S>
-__device__ __forceinline__ void slice4(double v0, double v1, double v2, double v3, int e, unsigned (&pl)[S]) {
-  unsigned lo[4], hi[4];
-  slice_bytes<S>(v0, e, lo[0], hi[0]);
-  slice_bytes<S>(v1, e, lo[1], hi[1]);
-  slice_bytes<S>(v2, e, lo[2], hi[2]);
-  slice_bytes<S>(v3, e, lo[3], hi[3]);
-  unsigned o[4];
-  transpose4(lo[0], lo[1], lo[2], lo[3], o);
-#pragma unroll
-  for (int i = 0; i < 4 && i < S; ++i) pl[S - 1 - i] = o[i];
-  if (S > 4) {
-    transpose4(hi[0], hi[1], hi[2], hi[3], o);
-#pragma unroll
-    for (int i = 4; i < S; ++i) pl[S - 1 - i] = o[i - 4];
-  }
-}
 
 __device__ __forceinline__ int row_exponent(double mx) {
   int e = 0;
@@ -129,7 +84,7 @@ __global__ __launch_bounds__(TH) void slice_grid(GemmArgs p, int fblocks) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) v[i] = (k0 + i < K) ? vr[k0 + i] : 0.0;
       unsigned pl[S];
-      slice4<S>(v[0], v[1], v[2], v[3], e, pl);
+      digits::slice4<S>(v[0], v[1], v[2], v[3], e, pl);
 #pragma unroll
       for (int t = 0; t < S; ++t) *reinterpret_cast<unsigned*>(dr + t * plane + k0) = pl[t];
     }
@@ -146,7 +101,7 @@ __global__ __launch_bounds__(TH) void slice_grid(GemmArgs p, int fblocks) {
     auto store = [&](int k0, const double (&v)[16], int e) {
       unsigned pl[4][S];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) slice4<S>(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3], e, pl[q]);
+      for (int q = 0; q < 4; ++q) digits::slice4<S>(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3], e, pl[q]);
 #pragma unroll
       for (int t = 0; t < S; ++t)
         *reinterpret_cast<i4*>(D + t * plane + (int64_t)(k0 >> 4) * (F * 16) + f * 16) =
@@ -396,10 +351,10 @@ hipError_t launch_gemm_sliced(GemmArgs& g, hipStream_t s) {
 #define MM_SLICED_CASE(SS)                                                \
   case SS:                                                                \
     if (g.b_trans) {                                                      \
-      slice_grid<1, SS><<<sgrid, block, 0, s>>>(g, (int)fblocks);         \
+      if (!g.vready) slice_grid<1, SS><<<sgrid, block, 0, s>>>(g, (int)fblocks); \
       gemm_i8<1, SS><<<grid, block, 0, s>>>(g);                           \
     } else {                                                              \
-      slice_grid<0, SS><<<sgrid, block, 0, s>>>(g, (int)fblocks);         \
+      if (!g.vready) slice_grid<0, SS><<<sgrid, block, 0, s>>>(g, (int)fblocks); \
       gemm_i8<0, SS><<<grid, block, 0, s>>>(g);                           \
     }                                                                     \
     break;

@@ -100,6 +100,8 @@ __global__ __launch_bounds__(256) void spec_combine_kernel(const double* __restr
 }
 
 hipError_t launch_spec_combine(const double* const (&G)[3], const StencilArgs& a, int64_t n, hipStream_t s) {
+  // out0 (or its FP32 form) is written unconditionally; out1 when either form is set
+  if ((!a.out0 && !a.out0f) || !G[0]) return hipErrorInvalidValue;
   spec_combine_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(G[0], G[1], G[2], a, n);
   return hipGetLastError();
 }

@@ -14,6 +14,7 @@
 #include <cfloat>
 
 #include "mm_internal.h"
+#include "slice_digits.h"
 
 namespace mm {
 
@@ -96,7 +97,51 @@ __device__ __forceinline__ void store_row(float* __restrict__ base, int64_t off,
   }
 }
 
-template <int D, int P>
+// The exact-slice split of one stage vector's row (sliced.hip defines it for the mode
+// products): the row's exponent e (max |v| < 2^e, from a wave maximum: the whole row is
+// in this wave) and, per value, Y = rint(v 2^(8S-2-e)) written with S balanced base-256
+// digits in [-128, 127], the bytes of Y + 0x80..80 each minus 128. Plane t holds digit
+// S-1-t (most significant first) at row r, position x of a plane of rows kp bytes;
+// values past n1 are zero digits. Every lane of the wave takes part (the reduction).
+template <int P, int S>
+__device__ __forceinline__ void write_row_digits(const double (&v)[P], int cnt, int x, int64_t row,
+                                                 const StencilArgs& p, int kp) {
+  double m = 0.0;
+#pragma unroll
+  for (int k = 0; k < P; ++k)
+    if (k < cnt) m = fmax(m, fabs(v[k]));
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  int e = 0;
+  __builtin_frexp(m, &e);                            // m < 2^e (e = 0 for m = 0)
+  if ((threadIdx.x & 63) == 0) p.dexp[row] = e;
+  if (x >= kp) return;
+  signed char* base = p.dig + row * kp + x;
+  if constexpr (P == 4) {
+    // four consecutive values: one 4-byte word per plane through the byte transpose
+    unsigned pl[S];
+    digits::slice4<S>(cnt > 0 ? v[0] : 0.0, cnt > 1 ? v[1] : 0.0, cnt > 2 ? v[2] : 0.0, cnt > 3 ? v[3] : 0.0, e, pl);
+#pragma unroll
+    for (int t = 0; t < S; ++t) *(unsigned*)(base + t * p.dplane) = pl[t];
+  } else {
+    unsigned lo[P], hi[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) digits::slice_bytes<S>(k < cnt ? v[k] : 0.0, e, lo[k], hi[k]);
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int i = S - 1 - t;                       // digit i (least significant first) in plane t
+      unsigned w = 0;
+#pragma unroll
+      for (int k = 0; k < P; ++k) w |= (((i < 4 ? lo[k] >> (8 * i) : hi[k] >> (8 * (i - 4))) & 255u) << (8 * k));
+      if constexpr (P == 2)
+        *(unsigned short*)(base + t * p.dplane) = (unsigned short)w;
+      else
+        *(base + t * p.dplane) = (signed char)w;
+    }
+  }
+}
+
+template <int D, int P, int S>
 __device__ __forceinline__ void stencil_body(const StencilArgs& p, const StencilGrid& sg) {
   constexpr int YT = (D == 3) ? 1 : 2;   // rows per lane along x2
   constexpr int ZT = (D == 3) ? 2 : 1;   // rows per lane along x3
@@ -179,7 +224,8 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
           ar = ae;
         }
       }
-      if (!live_row || ucnt <= 0) continue;
+      // (the digit output needs every lane of the row's wave for its row maximum)
+      if (!live_row || (ucnt <= 0 && S == 0)) continue;
       const int64_t idx = x + urow;
       const int64_t idxo = x + o2 * i2 + o3 * i3;
       // last unknown of an axis with a zero normal derivative at x = 1: mirror ghost
@@ -243,6 +289,18 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
         for (int k = 0; k < P; ++k) bad |= (k < ucnt) && !(fabs(o[k]) <= DBL_MAX);
         if (bad) p.flag[0] = 1;
       }
+      if constexpr (S > 0) {
+        // the stage vectors as digit planes of the mode-1 operand (rows of one wave)
+        const int kp = slice_ld(n1);
+        const int64_t row = i2 + (int64_t)n2 * i3;
+        write_row_digits<P, S>(o, ucnt, x, row, p, kp);
+        if (p.drow1) {   // base1 is u or null (checked at launch)
+#pragma unroll
+          for (int k = 0; k < P; ++k) o[k] = (p.base1 ? uc[k] : 0.0) + p.c1 * g[k];
+          write_row_digits<P, S>(o, ucnt, x, p.drow1 + row, p, kp);
+        }
+        continue;
+      }
       if (p.out0f)
         store_row<P>(p.out0f, idxo, o, ucnt);
       else
@@ -272,9 +330,9 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
 // entry, so one compiled kernel serves both, and a problem's results do not depend on
 // whether it ran alone or in a group (two instantiations of the body may contract
 // multiply-adds differently, which changes last bits).
-template <int D, int P>
+template <int D, int P, int S>
 __global__ __launch_bounds__(64 * SW) void stencil_batch_kernel(StencilBatch b, StencilGrid sg) {
-  stencil_body<D, P>(b.a[blockIdx.y], sg);
+  stencil_body<D, P, S>(b.a[blockIdx.y], sg);
 }
 
 // Points per lane: the P in {4, 2, 1} that pads n1 least to whole 64 P-point segments,
@@ -294,15 +352,28 @@ static int points_per_lane(int n1) {
   return best;
 }
 
-template <int D>
-static void launch_batch_d(int P, const StencilBatch& b, int count, StencilGrid sg, unsigned blocks, hipStream_t s) {
+template <int D, int S>
+static void launch_batch_ds(int P, const StencilBatch& b, int count, StencilGrid sg, unsigned blocks,
+                            hipStream_t s) {
   const dim3 grid(blocks, (unsigned)count);
   if (P == 4)
-    stencil_batch_kernel<D, 4><<<grid, dim3(64 * SW), 0, s>>>(b, sg);
+    stencil_batch_kernel<D, 4, S><<<grid, dim3(64 * SW), 0, s>>>(b, sg);
   else if (P == 2)
-    stencil_batch_kernel<D, 2><<<grid, dim3(64 * SW), 0, s>>>(b, sg);
+    stencil_batch_kernel<D, 2, S><<<grid, dim3(64 * SW), 0, s>>>(b, sg);
   else
-    stencil_batch_kernel<D, 1><<<grid, dim3(64 * SW), 0, s>>>(b, sg);
+    stencil_batch_kernel<D, 1, S><<<grid, dim3(64 * SW), 0, s>>>(b, sg);
+}
+
+template <int D>
+static void launch_batch_d(int P, const StencilBatch& b, int count, StencilGrid sg, unsigned blocks, hipStream_t s) {
+  switch (b.a[0].dig ? b.a[0].dS : 0) {
+    case 3: launch_batch_ds<D, 3>(P, b, count, sg, blocks, s); break;
+    case 4: launch_batch_ds<D, 4>(P, b, count, sg, blocks, s); break;
+    case 5: launch_batch_ds<D, 5>(P, b, count, sg, blocks, s); break;
+    case 6: launch_batch_ds<D, 6>(P, b, count, sg, blocks, s); break;
+    case 7: launch_batch_ds<D, 7>(P, b, count, sg, blocks, s); break;
+    default: launch_batch_ds<D, 0>(P, b, count, sg, blocks, s); break;
+  }
 }
 
 // Work decomposition of one grid (blocks of four waves); false if it does not fit a grid.
@@ -319,10 +390,21 @@ static bool stencil_grid(int d, int n1, int n2, int n3, int& P, StencilGrid& sg,
 
 hipError_t launch_stencil(int d, const StencilArgs& a, hipStream_t s) { return launch_stencil_batch(d, &a, 1, s); }
 
+bool stencil_row_in_one_wave(int n1) { return n1 >= 1 && 64 * points_per_lane(n1) >= n1; }
+
 hipError_t launch_stencil_batch(int d, const StencilArgs* a, int count, hipStream_t s) {
   if (count < 1 || count > kMaxGroups) return hipErrorInvalidValue;
   for (int i = 1; i < count; ++i)
     if (a[i].n1 != a[0].n1 || a[i].n2 != a[0].n2 || a[i].n3 != a[0].n3) return hipErrorInvalidValue;
+  for (int i = 0; i < count; ++i)
+    if (!a[i].u || !a[i].a || (!a[i].dig && !a[i].out0 && !a[i].out0f)) return hipErrorInvalidValue;
+  for (int i = 1; i < count; ++i)   // one kernel for the group: the same output form
+    if ((a[i].dig != nullptr) != (a[0].dig != nullptr) || (a[0].dig && a[i].dS != a[0].dS))
+      return hipErrorInvalidValue;
+  for (int i = 0; i < count; ++i)
+    if (a[i].dig && (!a[i].dexp || a[i].dS < kMinSlices || a[i].dS > kMaxSlices || !stencil_row_in_one_wave(a[i].n1) ||
+                     (a[i].base1 != a[i].u && a[i].base1 != nullptr && a[i].drow1)))
+      return hipErrorInvalidValue;
   int P;
   StencilGrid sg;
   int64_t blocks;

@@ -176,3 +176,44 @@ def test_fig_adr2d_printed_errors_and_lambda_table():
             errs.append(e)
         if lam_opt is not None:
             assert abs(pts[int(np.argmin(errs))][0] - lam_opt) < 0.01, sch
+
+
+@pytest.mark.parametrize("form", ["flux", "nondiv"])
+def test_variable_coefficient_remainder_closed_form(form):
+    """The remainder and F of the problem of Sec. 5.1 with its own diffusion tensor and
+    velocity field (trigonometric polynomials) on u = sin(2 x1) cos(x2), against the
+    derivatives written out by hand (product rule):
+      d1(a11 d1 u) = (d1 a11)(d1 u) + a11 d11 u, div(b u) = sum (d_mu b_mu) u + b_mu d_mu u,
+      A u = lam (a11^max d11 u + a22^max d22 u) + beta_bar . grad u, g = F - A u.
+    Every product is band-limited well below the Nyquist wavenumber of N = 64, so the
+    pseudo-spectral values are exact to rounding; a sign or a form error in either term
+    (a d_mumu u for the flux form, -div(b u), beta_bar added instead of subtracted)
+    misses by O(1)."""
+    lam = 0.5
+    p = synth.paper2d_problem(64, lam, scheme="l2b")
+    p.form = form
+    L = p.length[0]
+    x = -3.0 * np.pi + L / 64 * np.arange(64)
+    X2, X1 = np.meshgrid(x, x, indexing="ij")
+    s1, c1, s2, c2 = np.sin(X1), np.cos(X1), np.sin(X2), np.cos(X2)
+    u = np.sin(2 * X1) * c2
+    u1, u11 = 2 * np.cos(2 * X1) * c2, -4 * np.sin(2 * X1) * c2
+    u2, u22 = -np.sin(2 * X1) * s2, -np.sin(2 * X1) * c2
+    a11, a22 = 0.5 + s1 ** 2 * s2 ** 2 / 6, 0.5 + c1 ** 2 * c2 ** 2 / 6
+    a11_1, a22_2 = np.sin(2 * X1) * s2 ** 2 / 6, -(c1 ** 2) * np.sin(2 * X2) / 6
+    b1, b2 = s1 ** 2 / 5, s2 ** 2 / 5
+    b1_1, b2_2 = np.sin(2 * X1) / 5, np.sin(2 * X2) / 5
+    amax = (float(p.a[0].max()), float(p.a[1].max()))
+    react = p.r[0] + u * (p.r[1] + u * (p.r[2] + u * p.r[3]))
+    adv = b1_1 * u + b1 * u1 + b2_2 * u + b2 * u2
+    if form == "flux":
+        diff = a11_1 * u1 + a11 * u11 + a22_2 * u2 + a22 * u22
+    else:
+        diff = a11 * u11 + a22 * u22
+    F = diff + adv + react
+    Au = lam * (amax[0] * u11 + amax[1] * u22) + p.beta_bar[0] * u1 + p.beta_bar[1] * u2
+    be = spectral.Spectral(p)
+    scale = float(np.max(np.abs(F)))
+    assert np.max(np.abs(be.F(u) - F)) <= 1e-12 * scale
+    assert np.max(np.abs(be.g(u) - (F - Au))) <= 1e-12 * scale
+    assert np.max(np.abs(be.A(u) - Au)) <= 1e-12 * scale
