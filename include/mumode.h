@@ -97,7 +97,12 @@ typedef enum { MM_FP64 = 0, MM_FP32 = 1, MM_BF16X3 = 2, MM_BF16X6 = 3, MM_SLICED
  *   phi1(tau A) v ~ sum_j w_j exp(theta_j tau A) v,  theta_j, w_j on [0, 1],
  * or (q = 0) evaluated exactly in the joint eigenbasis of the Kronecker sum: with
  * A_mu = L_mu diag(ev_mu) R_mu (closed form for the tridiagonal Toeplitz A_mu),
- *   f(tau A) v = (v x_mu R_mu over mu) scaled by f(tau (ev_1 + ev_2 + ev_3)) x_mu L_mu.  */
+ *   f(tau A) v = (v x_mu R_mu over mu) scaled by f(tau (ev_1 + ev_2 + ev_3)) x_mu L_mu.
+ * On periodic axes L_mu = Q_mu is the real orthonormal Fourier basis (the constant, the
+ * cos/sin pair of every wavenumber 0 < m < n/2, the alternating Nyquist vector for even
+ * n) and R_mu = Q_mu^T; A_mu is block diagonal there, with 2 x 2 blocks for the pairs
+ * (the advection's imaginary symbol), and f acts on the up to eight coefficients of one
+ * wavenumber triple through their complex amplitudes.                                */
 enum { MM_LAWSON = 0, MM_ERK = 1 };
 enum { MM_LAWSON_EULER = 0, MM_LAWSON2B = 1, MM_SLE = 2, MM_LAWSON2A = 3, MM_SL2 = 4 };
 enum { MM_ETD2RK = 0, MM_ERK2P1 = 1, MM_EE = 2, MM_ERK2P2 = 3 };
@@ -122,7 +127,7 @@ enum { MM_ETD2RK = 0, MM_ERK2P1 = 1, MM_EE = 2, MM_ERK2P2 = 3 };
  * sums from their Fourier symbols in FP64 at setup (no FFT on the step path). g follows
  * eq. (eq:nonlin): sum_mu d_mu((a_mumu - lam a^max_mumu) d_mu u) (MM_FORM_NONDIV:
  * (a_mumu - lam a^max_mumu) d_mumu u) + sum_mu d_mu((b_mu - beta_bar_mu) u) + r(u), and
- * F = A u + g. Exact phi (q = 0) is not offered for periodic problems. Their remainder
+ * F = A u + g. Exact phi (q = 0) goes through the Fourier basis (above). Their remainder
  * works in scratch held by the op (three grid functions per axis) and runs the chain of
  * every axis after the first on a side stream of the op, forked from and joined back to
  * the call's stream with events (so it stays stream-ordered and can be captured); calls
@@ -170,8 +175,8 @@ const char* mm_version(void);
  * theta_j for MM_ERK), plus the FP32, BF16-slice or digit-plane forms the precision
  * needs. Returns after the setup has finished. quad_nodes (q) is 1..7 for MM_ERK and
  * ignored for MM_LAWSON; q = 0 selects exact phi1 through the eigenbasis (FP64 only;
- * needs |beta_bar_mu| h_mu < 2 lambda a_max so that the eigenvalues are real), and
- * the op then also stores R_mu and L_mu. slices: digit count of MM_SLICED (0 = 6,
+ * Dirichlet or periodic axes; Dirichlet axes need |beta_bar_mu| h_mu < 2 lambda a_max
+ * so that the eigenvalues are real), and the op then also stores R_mu and L_mu. slices: digit count of MM_SLICED (0 = 6,
  * else 3..7), ignored by the other precisions. `a` must be complete when the call is
  * made (the copy runs on the context's own stream, which does not wait for others).
  * Errors: MM_EINVAL (d, n < 1, tau <= 0 or not finite, unknown family/scheme/prec/bc/form,

@@ -648,6 +648,9 @@ constexpr int kFacR = 1, kFacL = 2;
 
 hipError_t eig_scale(const mm_op* op, double* out, const double* a, double ca, int fa, const double* b, double cb,
                      int fb, hipStream_t s) {
+  if (op->periodic)
+    return launch_spec_eig_scale(out, a, ca, fa, b, cb, fb, op->ev[0], op->ev[1], op->d == 3 ? op->ev[2] : nullptr,
+                                 op->n[0], op->n[1], op->d == 3 ? op->n[2] : 1, op->tau, s);
   return launch_eig_scale(out, a, ca, fa, b, cb, fb, op->ev[0], op->ev[1], op->d == 3 ? op->ev[2] : nullptr,
                           op->n[0], op->n[1], op->d == 3 ? op->n[2] : 1, op->tau, s);
 }
@@ -710,6 +713,25 @@ StencilArgs stencil_args(const mm_op* op, const double* u, bool full) {
   a.nondiv = op->form == MM_FORM_NONDIV;
   a.full = full;
   return a;
+}
+
+// Real orthonormal Fourier basis of n equispaced points, Q[j][k] (row-major): column 0
+// the constant 1/sqrt(n); columns 2m - 1, 2m for 1 <= m < n/2 sqrt(2/n) cos(2 pi m j/n) and
+// sqrt(2/n) sin(2 pi m j/n); for even n column n - 1 the Nyquist mode (-1)^j/sqrt(n).
+// Angles from the exact residue m j mod n, in long double.
+void fourier_basis(int n, std::vector<double>& Q) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  const long double c0 = 1.0L / std::sqrt((long double)n), c1 = std::sqrt(2.0L / n);
+  Q.assign((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    Q[(size_t)j * n] = (double)c0;
+    for (int m = 1; 2 * m < n; ++m) {
+      const long double t = 2.0L * pi * (long double)(((int64_t)m * j) % n) / n;
+      Q[(size_t)j * n + 2 * m - 1] = (double)(c1 * std::cos(t));
+      Q[(size_t)j * n + 2 * m] = (double)(c1 * std::sin(t));
+    }
+    if (n % 2 == 0 && n > 1) Q[(size_t)j * n + n - 1] = (double)((j % 2 ? -c0 : c0));
+  }
 }
 
 // Closed-form eigen-decomposition of the tridiagonal Toeplitz matrix with sub-diagonal
@@ -939,10 +961,6 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
       return MM_EINVAL;
     }
   }
-  if (periodic && family == MM_ERK && quad_nodes == 0) {
-    set_err(ctx, "exact phi (quad_nodes = 0) is not offered for periodic problems");
-    return MM_EINVAL;
-  }
   if (prob->form != MM_FORM_FLUX && prob->form != MM_FORM_NONDIV) {
     set_err(ctx, "form = %d is not a diffusion form", prob->form);
     return MM_EINVAL;
@@ -973,8 +991,8 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
   }
   if (family == MM_ERK && quad_nodes == 0)
     for (int mu = 0; mu < prob->d; ++mu)
-      if (prob->bc[mu] != MM_BC_DIRICHLET) {
-        set_err(ctx, "exact phi1 (quad_nodes = 0) needs Dirichlet data on every axis (closed-form eigenbasis)");
+      if (prob->bc[mu] == MM_BC_NEUMANN) {
+        set_err(ctx, "exact phi1 (quad_nodes = 0) needs Dirichlet or periodic axes (closed-form eigenbasis)");
         return MM_EINVAL;
       }
   if (prec < MM_FP64 || prec > MM_SLICED) {
@@ -1244,7 +1262,32 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     set_err(ctx, "factor setup failed on the device");
     return fail(MM_EDEVICE);
   }
-  if (op->exact) {
+  if (op->exact && periodic) {
+    // real orthonormal Fourier basis of every axis (R = Q^T, L = Q, uploaded next to E(1))
+    // and the symbol of A_mu at the wavenumbers 0 .. n/2
+    for (int mu = 0; mu < op->d; ++mu) {
+      const int n = op->n[mu];
+      const int64_t nn = (int64_t)n * n;
+      std::vector<double> R((size_t)nn), L((size_t)nn), sym(2 * (n / 2 + 1));
+      fourier_basis(n, L);
+      for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) R[(size_t)k * n + j] = L[(size_t)j * n + k];
+      const long double kap = 2.0L * 3.141592653589793238462643383279502884L / op->length[mu];
+      for (int m = 0; m <= n / 2; ++m) {
+        const long double km = kap * m;
+        sym[2 * m] = (double)(-(long double)op->lam * op->amax_mu[mu] * km * km);
+        sym[2 * m + 1] = (n % 2 == 0 && m == n / 2) ? 0.0 : (double)((long double)op->beta_bar[mu] * km);
+      }
+      if ((rc = dev_alloc(op, &op->ev[mu], (int64_t)sym.size())) != MM_OK) return fail(rc);
+      if (hipMemcpy(op->ev[mu], sym.data(), sym.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+          (op->fac_owned[mu] &&
+           (hipMemcpy(op->fac[mu] + nn, R.data(), nn * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(op->fac[mu] + 2 * nn, L.data(), nn * sizeof(double), hipMemcpyHostToDevice) != hipSuccess))) {
+        set_err(ctx, "upload of the Fourier basis failed");
+        return fail(MM_EDEVICE);
+      }
+    }
+  } else if (op->exact) {
     // closed-form eigen-decomposition of every 1D operator (uploaded next to E(1))
     for (int mu = 0; mu < op->d; ++mu) {
       const int n = op->n[mu];

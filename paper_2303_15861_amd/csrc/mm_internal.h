@@ -188,6 +188,12 @@ enum { MM_EIG_ONE = 0, MM_EIG_EXP = 1, MM_EIG_PHI1 = 2, MM_EIG_PHI2 = 3 };
 hipError_t launch_eig_scale(double* out, const double* a, double ca, int fa, const double* b, double cb, int fb,
                             const double* ev1, const double* ev2, const double* ev3, int n1, int n2, int n3,
                             double tau, hipStream_t s);
+// The same for periodic axes in the real orthonormal Fourier basis (cos/sin pairs are
+// 2 x 2 blocks): sym_mu holds (alpha(m), omega(m)), the symbol of A_mu at wavenumber
+// m = 0 .. n_mu/2 (sym3 null in 2D).
+hipError_t launch_spec_eig_scale(double* out, const double* a, double ca, int fa, const double* b, double cb, int fb,
+                                 const double* sym1, const double* sym2, const double* sym3, int n1, int n2, int n3,
+                                 double tau, hipStream_t s);
 // out[0] = ||Q||_1, out[1] = ||Q||_inf (device); X = alpha Q^T; out[0] = max |R - I|
 hipError_t launch_norms(const double* Q, int n, double* out, hipStream_t s);
 hipError_t launch_scaled_transpose(double* X, const double* Q, int n, double alpha, hipStream_t s);

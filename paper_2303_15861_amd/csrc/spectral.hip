@@ -106,4 +106,160 @@ hipError_t launch_spec_combine(const double* const (&G)[3], const StencilArgs& a
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- exact phi, periodic axes
+// In the real orthonormal Fourier basis of an axis (transform index 0: the constant;
+// 2m - 1 and 2m: cos and sin of wavenumber m, 1 <= m < n/2; n - 1 for even n: the Nyquist
+// mode) a real circulant with symbol sigma(m) = alpha(m) + i omega(m) (alpha even and
+// omega odd in m) is block diagonal: a (cos, sin) coefficient pair (a, b) is the complex
+// amplitude c+ = (a - i b)/2 of e^{i theta} and c- = (a + i b)/2 of e^{-i theta}, which it
+// multiplies by sigma(m) and by its conjugate. So a function f of tau A = tau (A_1 (+)
+// A_2 (+) A_3) acts on the (up to eight) coefficients of one wavenumber triple through
+// these amplitudes: every sign pattern of the modes is multiplied by f(tau sum sigma_mu^+-),
+// and the pairs are assembled back, a = c+ + c-, b = i (c+ - c-).
+namespace {
+
+struct cplx {
+  double re, im;
+};
+
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return {a.re * s, a.im * s}; }
+__device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
+  const double d = b.re * b.re + b.im * b.im;
+  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+// f(z) for f = exp, phi1(z) = (e^z - 1)/z, phi2(z) = (e^z - 1 - z)/z^2 (series below |z| = 1/2,
+// where the closed forms cancel), or 1
+__device__ cplx cfun(int f, cplx z) {
+  if (f == MM_EIG_ONE) return {1.0, 0.0};
+  double sn, cs;
+  sincos(z.im, &sn, &cs);
+  const double ex = exp(z.re);
+  const cplx e = {ex * cs, ex * sn};
+  if (f == MM_EIG_EXP) return e;
+  const int k = (f == MM_EIG_PHI1) ? 1 : 2;
+  if (z.re * z.re + z.im * z.im < 0.25) {
+    cplx acc = {0.0, 0.0}, term = {k == 1 ? 1.0 : 0.5, 0.0};   // z^j / (j + k)!
+#pragma unroll 1
+    for (int j = 0; j < 25; ++j) {
+      acc = cadd(acc, term);
+      term = cscale(cmul(term, z), 1.0 / (j + k + 1));
+    }
+    return acc;
+  }
+  cplx num = {expm1(z.re) * cs - 2.0 * sin(0.5 * z.im) * sin(0.5 * z.im), ex * sn};   // e^z - 1
+  if (k == 1) return cdiv(num, z);
+  num = csub(num, z);
+  return cdiv(num, cmul(z, z));
+}
+
+// transform indices of wavenumber m on an axis of n points; returns whether it is a pair
+__device__ __forceinline__ bool mode_index(int m, int n, int& i0) {
+  if (m == 0) {
+    i0 = 0;
+    return false;
+  }
+  if ((n & 1) == 0 && m == n / 2) {
+    i0 = n - 1;
+    return false;
+  }
+  i0 = 2 * m - 1;
+  return true;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void spec_eig_scale_kernel(double* __restrict__ out, const double* __restrict__ a,
+                                                             double ca, int fa, const double* __restrict__ b,
+                                                             double cb, int fb, const double* __restrict__ sym1,
+                                                             const double* __restrict__ sym2,
+                                                             const double* __restrict__ sym3, int n1, int n2, int n3,
+                                                             int M1, int M2, int M3, double tau) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)M1 * M2 * M3) return;
+  const int m1 = (int)(e % M1);
+  const int64_t r = e / M1;
+  const int m2 = (int)(r % M2), m3 = (int)(r / M2);
+  int i1, i2, i3;
+  const bool p1 = mode_index(m1, n1, i1), p2 = mode_index(m2, n2, i2);
+  const bool p3 = n3 > 1 ? mode_index(m3, n3, i3) : (i3 = 0, false);
+  const bool pair[3] = {p1, p2, p3};
+  const double al[3] = {sym1[2 * m1], sym2[2 * m2], sym3 ? sym3[2 * m3] : 0.0};
+  const double om[3] = {sym1[2 * m1 + 1], sym2[2 * m2 + 1], sym3 ? sym3[2 * m3 + 1] : 0.0};
+  // slot t = t1 + 2 t2 + 4 t3 (t_mu = 1: the sin member of a pair)
+  int64_t idx[8];
+  bool used[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int t1 = t & 1, t2 = (t >> 1) & 1, t3 = t >> 2;
+    used[t] = (!t1 || p1) && (!t2 || p2) && (!t3 || p3);
+    idx[t] = used[t] ? (int64_t)(i3 + t3) * n2 * n1 + (int64_t)(i2 + t2) * n1 + (i1 + t1) : 0;
+  }
+  auto apply = [&](const double* src, int f, cplx (&res)[8]) {
+    cplx v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = {used[t] ? src[idx[t]] : 0.0, 0.0};
+    // to amplitudes: (a, b) -> ((a - i b)/2, (a + i b)/2) along every pair axis
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      if (!pair[ax]) continue;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (t & (1 << ax)) continue;
+        const cplx x = v[t], y = v[t | (1 << ax)];
+        const cplx iy = {-y.im, y.re};
+        v[t] = cscale(csub(x, iy), 0.5);
+        v[t | (1 << ax)] = cscale(cadd(x, iy), 0.5);
+      }
+    }
+    // amplitude of sign pattern t (bit set: the conjugate mode) times f(tau sum sigma)
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (!used[t]) continue;
+      cplx z = {0.0, 0.0};
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        z.re += al[ax];
+        z.im += (t & (1 << ax)) ? -om[ax] : om[ax];
+      }
+      v[t] = cmul(v[t], cfun(f, cscale(z, tau)));
+    }
+    // back: a = c+ + c-, b = i (c+ - c-)
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      if (!pair[ax]) continue;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (t & (1 << ax)) continue;
+        const cplx cp = v[t], cm = v[t | (1 << ax)];
+        const cplx d = csub(cp, cm);
+        v[t] = cadd(cp, cm);
+        v[t | (1 << ax)] = {-d.im, d.re};
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) res[t] = v[t];
+  };
+  cplx ra[8], rb[8];
+  apply(a, fa, ra);
+  if (b) apply(b, fb, rb);
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+    if (used[t]) out[idx[t]] = ca * ra[t].re + (b ? cb * rb[t].re : 0.0);
+}
+
+hipError_t launch_spec_eig_scale(double* out, const double* a, double ca, int fa, const double* b, double cb, int fb,
+                                 const double* sym1, const double* sym2, const double* sym3, int n1, int n2, int n3,
+                                 double tau, hipStream_t s) {
+  if (!out || !a || !sym1 || !sym2 || (n3 > 1 && !sym3) || n1 < 1 || n2 < 1 || n3 < 1) return hipErrorInvalidValue;
+  const int M1 = n1 / 2 + 1, M2 = n2 / 2 + 1, M3 = n3 > 1 ? n3 / 2 + 1 : 1;
+  const int64_t cnt = (int64_t)M1 * M2 * M3;
+  spec_eig_scale_kernel<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(out, a, ca, fa, b, cb, fb, sym1, sym2, sym3,
+                                                                      n1, n2, n3, M1, M2, M3, tau);
+  return hipGetLastError();
+}
+
 }  // namespace mm

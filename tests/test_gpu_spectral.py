@@ -166,14 +166,14 @@ def test_paper2d_mixed_precision(mm, ctx, prec, tol):
     op.close()
 
 
-def test_rejects_mixed_periodic_axes_and_exact_phi(mm, ctx):
+def test_rejects_mixed_periodic_axes_and_low_precision_exact_phi(mm, ctx):
     p = random_periodic((8, 6), 1)
     with pytest.raises(mm.MumodeError):
         mm.setup_problem(ctx, dataclasses.replace(p, bc=(PERIODIC, 0)))
     with pytest.raises(mm.MumodeError):
         mm.setup_problem(ctx, dataclasses.replace(p, length=(1.0, 0.0)))
     with pytest.raises(mm.MumodeError):
-        mm.setup_problem(ctx, dataclasses.replace(p, scheme="etd2rk", q=0))
+        mm.setup_problem(ctx, dataclasses.replace(p, scheme="etd2rk", q=0), prec="fp32")
 
 
 def _printed(N):
@@ -260,9 +260,10 @@ def test_fig_px91_printed_errors_with_gpu_solves(mm, ctx):
     m = 2 ** 13
     ref = Sch.integrate(p.u0, Unsplit(T_end / m), T_end / m, m, "erk2p2")
     for sch, lam, err in T.FIG_PX91:
+        p = synth.paper1d_problem(N, lam, nonlinear=True, scheme=sch, steps=4096)
         if sch in ("ee", "erk2p2"):
-            continue          # exact phi is not offered for periodic problems on the GPU
-        u = _gpu_solve(mm, ctx, synth.paper1d_problem(N, lam, nonlinear=True, scheme=sch, steps=4096))
+            p = dataclasses.replace(p, q=0)   # exact phi functions in the Fourier basis
+        u = _gpu_solve(mm, ctx, p)
         e = Sch.rel_inf_error(u, ref)
         assert abs(e - err) <= 1e-3 * err, (sch, lam, e, err)
 
@@ -362,3 +363,55 @@ def test_periodic_3d_side_streams_under_graphs_and_a_user_stream(mm, ctx):
         assert np.array_equal(host(u), ref[-1])
     finally:
         op.close()
+
+
+# ------------------------------------------------------------------ exact phi, periodic axes
+@pytest.mark.parametrize("n", [(64, 64), (45, 37), (30, 1), (12, 10, 9)])
+def test_periodic_exact_phi1_action(mm, ctx, n):
+    """phi1(tau A) through the real Fourier basis of every axis (2 x 2 blocks for the
+    cos/sin pairs, the advection's imaginary symbol included) against the oracle's
+    pointwise phi1 on the FFT symbol; even, odd and one-point axes, 2D and 3D."""
+    p = dataclasses.replace(random_periodic(n, 3, scheme="etd2rk", tau=4e-2), q=0)
+    V = np.random.default_rng(4).standard_normal(p.u0.shape)
+    op = mm.setup_problem(ctx, p)
+    out = dev(np.zeros(p.u0.shape))
+    mm.mumode_phi1v(op, dev(V), out)
+    ref = spectral.Spectral(p, phi="exact").phi1v(V)
+    assert relerr(host(out), ref) <= FP64_TOL
+    op.close()
+
+
+@pytest.mark.parametrize("scheme", ["ee", "erk2p2", "etd2rk", "erk2p1f"])
+def test_paper2d_exact_phi_solves(mm, ctx, scheme):
+    """Sixteen steps of the Sec. 5.1 problem with exact phi functions (the Appendix's EE,
+    erk2p2, erk2p1 and the Cox-Matthews form of erk2p1) against the oracle."""
+    p = dataclasses.replace(synth.paper2d_problem(64, 0.5, scheme=scheme, steps=256), steps=16, q=0)
+    u = _gpu_solve(mm, ctx, p)
+    assert relerr(u, spectral.solve(p, phi="exact")) <= FP64_TOL
+
+
+@pytest.mark.parametrize("scheme", ["ee", "etd2rk"])
+def test_periodic_3d_exact_phi_solves(mm, ctx, scheme):
+    p = dataclasses.replace(random_periodic((9, 8, 7), 7, scheme=scheme, steps=6, tau=5e-3), q=0)
+    u = _gpu_solve(mm, ctx, p)
+    assert relerr(u, spectral.solve(p, phi="exact")) <= FP64_TOL
+
+
+def test_fig_adr2d_ee_and_erk2p1_with_gpu_solves(mm, ctx):
+    """The EE and erk2p1 series of Figure fig:adr2d_diffl (N = 2^6, m = 2^8, exact phi
+    functions) with GPU solves against the GPU Lawson2b reference (lambda = 1, 2^13 steps):
+    every printed point within -2.5%/+1.5% (the systematic offset of the other series of
+    this figure), and the lambda of least error on the printed grid is the one of Table
+    tab:adr2d_lambdaopt: 0.50 for EE, 0.33 for erk2p1."""
+    ref = _gpu_solve(mm, ctx, synth.paper2d_problem(64, 1.0, scheme="l2b", steps=2 ** 13))
+    for sch, name, lam_opt in (("ee", "ee", 0.50), ("erk2p1f", "erk2p1", 0.33)):
+        pts = [(lam, err) for s, lam, err in _printed(64) if s == name]
+        assert len(pts) >= 13
+        errs = []
+        for lam, err in pts:
+            p = dataclasses.replace(synth.paper2d_problem(64, lam, scheme=sch), q=0)
+            e = Sch.rel_inf_error(_gpu_solve(mm, ctx, p), ref)
+            assert 0.975 * err <= e <= 1.015 * err, (sch, lam, e, err)
+            errs.append(e)
+        best = pts[int(np.argmin(errs))][0]
+        assert abs(best - lam_opt) < 0.01, (sch, best, lam_opt)
