@@ -144,8 +144,16 @@ def slice_products(prec):
     return S * (S + 1) // 2
 
 
+# Untimed steps before each timed region run for at least this long: under sustained
+# load the GPU's clocks take a few tenths of a second to settle (the 255^3 mode products
+# go from about 390 to about 300 us per launch over the first 25 steps of a cold run), so
+# a warmup of a few steps alone would time the ramp.
+WARMUP_MIN_S = 0.5
+
+
 def time_mode(mm, ctx, p, prec, steps, warmup, graph_steps=0):
-    """Timed region: `steps` steps on a resident state, no per-kernel events. A second,
+    """Timed region: `steps` steps on a resident state, no per-kernel events. Before it,
+    `warmup` untimed steps and then more until WARMUP_MIN_S of steps have run. A second,
     untimed pass of the same steps brackets every kernel with HIP events on its stream
     for the per-kernel table and the roofline. With graph replay the warmup runs at
     least one graph's worth of steps, so that the graph is recorded before timing."""
@@ -155,8 +163,15 @@ def time_mode(mm, ctx, p, prec, steps, warmup, graph_steps=0):
     u = u0.clone()
     stream = torch.cuda.current_stream()
     warmup = max(warmup, graph_steps)
+    t0 = time.perf_counter()
     if warmup:
         mm.step(op, u, warmup, stream)
+    torch.cuda.synchronize()
+    chunk = max(1, warmup)
+    while time.perf_counter() - t0 < WARMUP_MIN_S:
+        u.copy_(u0)
+        mm.step(op, u, chunk, stream)
+        torch.cuda.synchronize()
     u.copy_(u0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -478,7 +493,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": DESCRIPTION.get(args.workload, args.workload),
                    "dof": p.dof, "scheme": p.scheme, "headline_mode": args.headline,
-                   "graph_steps": args.graph_steps, "tile": args.tile or "auto"},
+                   "graph_steps": args.graph_steps, "tile": args.tile or "auto",
+                   "warmup_min_seconds": WARMUP_MIN_S},
         "latency": head.get("latency"),
         "modes": {m: {kk: vv for kk, vv in e.items() if kk != "kernels"} for m, e in res.items()},
         "fastest_mode_meeting_target": fastest_accurate,
