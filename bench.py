@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="replay step loops from recorded HIP graphs of this many steps (0: direct launches)")
     ap.add_argument("--tile", type=int, default=0, help="force the mode-product workgroup tile (64 or 128)")
+    ap.add_argument("--sliced-chain", type=int, default=1,
+                    help="chained exact-slice actions: 0 off, 1 automatic, 2 always, 3 four-wave workgroups")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-at-T", action="store_true", help="skip the untimed runs to T")
@@ -422,6 +424,7 @@ def main():
     ctx = mm.Context(0)
     ctx.set_graph_steps(args.graph_steps)
     ctx.set_gemm_tile(args.tile)
+    ctx.set_sliced_chain(args.sliced_chain)
     modes = [m for m in args.modes.split(",") if m]
     if "fp64" not in modes:
         modes = ["fp64"] + modes
@@ -494,6 +497,7 @@ def main():
         "config": {"workload": DESCRIPTION.get(args.workload, args.workload),
                    "dof": p.dof, "scheme": p.scheme, "headline_mode": args.headline,
                    "graph_steps": args.graph_steps, "tile": args.tile or "auto",
+                   "sliced_chain": args.sliced_chain,
                    "warmup_min_seconds": WARMUP_MIN_S},
         "latency": head.get("latency"),
         "modes": {m: {kk: vv for kk, vv in e.items() if kk != "kernels"} for m, e in res.items()},

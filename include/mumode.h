@@ -294,6 +294,17 @@ mm_status mm_set_gemm_tile(mm_ctx* ctx, int tile);
  * Default: enabled. Results agree with the launched path to rounding. */
 mm_status mm_set_small_fused(mm_ctx* ctx, int enable);
 
+/* Exact-slice (MM_SLICED) Lawson-Euler and Lawson2b steps on finite-difference grids with
+ * every n_mu <= 256 can run their exponential action as a chain of mode products whose
+ * epilogues write the next product's digit planes directly (no separate split passes):
+ * a workgroup covers 32 factor rows against a whole fiber group, so the exponent of every
+ * next-mode fiber is taken from the complete fiber, as the split pass takes it, and the
+ * results are bit-identical to the unchained path. mode = 0: off; 1 (default): on when
+ * every n_mu > 128 (smaller axes leave most of a 256-fiber tile idle); 2: on wherever
+ * possible (eight waves of 32 fibers); 3: as 2 with four waves of 64 fibers. Other modes:
+ * MM_EINVAL. */
+mm_status mm_set_sliced_chain(mm_ctx* ctx, int mode);
+
 /* Step replay through HIP graphs (launch-bound small problems). steps = 0 (default):
  * lawson_step / erk_step launch their kernels one by one. steps = G > 0: a call with
  * nsteps >= G records G steps on that state buffer into a graph once (kept by the op and

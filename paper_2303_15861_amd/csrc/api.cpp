@@ -798,6 +798,77 @@ void set_stencil_digits(StencilArgs& a, const mm_op* op, signed char* dig, int* 
   a.out1 = nullptr;
 }
 
+// MM_SLICED Lawson-Euler / Lawson2b on finite-difference grids whose axes all fit one
+// chained workgroup's 256 fibers: the exp action can run as chained mode products (the
+// stencil writes the first product's digits, every product but the last writes the
+// next one's). Decided at setup (it needs the second digit workspace).
+bool chain_capable(const mm_op* op) {
+  if (!stencil_digits(op) || op->family != MM_LAWSON ||
+      (op->scheme != MM_LAWSON_EULER && op->scheme != MM_LAWSON2B))
+    return false;
+  for (int mu = 0; mu < op->d; ++mu)
+    if (op->n[mu] > 256) return false;
+  return true;
+}
+
+// whether this op's Lawson steps take the chained action under the context's mode
+bool chain_active(const mm_op* op) {
+  const int mode = op->ctx ? op->ctx->sliced_chain : 0;
+  if (mode == 0 || !op->vdig2 || !chain_capable(op)) return false;
+  if (mode == 1)
+    for (int mu = 0; mu < op->d; ++mu)
+      if (op->n[mu] <= 128) return false;
+  return true;
+}
+
+// out = exp(tau A) v for the nvec stage vectors whose digit planes and fiber exponents the
+// stencil wrote into op->vdig / op->vexp (chain layout, groups of n2 fibers). Product mu contracts
+// axis mu; its fiber groups run along the next axis (F = n_(mu+1), Gv = dof / (n_mu F)
+// groups per vector), and its output rows are the next product's fibers, written to the
+// other workspace. The last product writes FP64 into out (layout lo).
+hipError_t chain_action(const mm_op* op, int j, int nvec, double* out, Layout lo, hipStream_t s) {
+  signed char* dig[2] = {op->vdig, op->vdig2};
+  int* ex[2] = {op->vexp, op->vexp2};
+  const int64_t dcap[2] = {op->vdig_len, op->vdig2_len}, ecap[2] = {op->vexp_len, op->vexp2_len};
+  const int mode = op->ctx->sliced_chain;
+  for (int mu = 0; mu < op->d; ++mu) {
+    const int cur = mu & 1;
+    const int n = op->n[mu], nf = op->n[(mu + 1) % op->d];
+    ChainArgs c{};
+    c.fdig = (const signed char*)factor_op(op, mu, j);
+    c.fexp = factor_exp(op, mu, j);
+    c.fplane = factor_slice_stride(op, n, n);
+    c.vdig = dig[cur];
+    c.vexp = ex[cur];
+    c.vcap = dcap[cur];
+    c.vexp_cap = ecap[cur];
+    c.M = c.K = n;
+    c.F = nf;
+    c.Gv = (int)(op->dof / ((int64_t)n * nf));
+    c.nvec = nvec;
+    c.slices = op->slices;
+    c.alpha = 1.0;
+    c.wide = mode == 3;
+    if (mu + 1 < op->d) {
+      c.odig = dig[cur ^ 1];
+      c.oexp = ex[cur ^ 1];
+      c.ocap = dcap[cur ^ 1];
+      c.oexp_cap = ecap[cur ^ 1];
+      c.Fn = op->n[(mu + 2) % op->d];   // the next product's fibers per group
+    } else {
+      c.out = out;
+      c.ldo = lo.ld;
+      c.ovs = lo.vs;
+    }
+    const double work = 2.0 * n * (double)op->dof * nvec;
+    const hipError_t e = timed_launch(op->ctx, mu == 0 ? MM_KIND_GEMM_K : MM_KIND_GEMM_N, work, s,
+                                      [&] { return launch_gemm_sliced_chain(c, s); });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+
 mm_status check_op(mm_ctx* ctx, const mm_op* op) {
   if (!ctx) return MM_EINVAL;
   if (!op) {
@@ -915,6 +986,8 @@ void mumode_destroy(mm_op* op) {
   for (int i = 0; i < 6; ++i) dev_free(op, op->buf[i]);
   dev_free(op, op->vdig);
   dev_free(op, op->vexp);
+  dev_free(op, op->vdig2);
+  dev_free(op, op->vexp2);
   dev_free(op, op->flag);
   if (op->gexec) hipGraphExecDestroy(op->gexec);
   delete op;
@@ -1442,10 +1515,28 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
       dig = std::max(dig, (dof / nl) * S * (int64_t)slice_ld((int)G * nl));
       ex = std::max(ex, dof / nl);
     }
+    // chained actions: the chain layout of every product's input, two stacked vectors,
+    // groups of 256 fibers (padded), in two workspaces
+    int64_t cdig = 0, cex = 0;
+    if (chain_capable(op)) {
+      for (int mu = 0; mu < op->d; ++mu) {
+        const int64_t groups = 2 * (dof / ((int64_t)op->n[mu] * op->n[(mu + 1) % op->d]));
+        cdig = std::max(cdig, groups * 256 * S * slice_ld(op->n[mu]));
+        cex = std::max(cex, groups * 256);
+      }
+    }
+    dig = std::max(dig, cdig);
+    ex = std::max(ex, cex);
     op->vdig_len = dig;
     op->vexp_len = ex;
     if ((rc = dev_alloc(op, &op->vdig, dig)) != MM_OK) return fail(rc);
     if ((rc = dev_alloc(op, &op->vexp, ex)) != MM_OK) return fail(rc);
+    if (cdig > 0) {
+      op->vdig2_len = cdig;
+      op->vexp2_len = cex;
+      if ((rc = dev_alloc(op, &op->vdig2, cdig)) != MM_OK) return fail(rc);
+      if ((rc = dev_alloc(op, &op->vexp2, cex)) != MM_OK) return fail(rc);
+    }
   }
   if (hipStreamSynchronize(st) != hipSuccess) {
     set_err(ctx, "setup failed on the device");
@@ -1591,15 +1682,19 @@ mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hi
       a.c0 = tau;
       a.ldo = op->ld1;
       const bool dg = stencil_digits(op);
-      if (dg)
+      if (dg) {
         set_stencil_digits(a, op, op->vdig, op->vexp, 1);
-      else if (mixed)
+        a.dchain = chain_active(op);
+      } else if (mixed)
         a.out0f = (float*)b0;
       else
         a.out0 = b0;
       HIPCHK(ctx, stencil(op, a, s));
-      HIPCHK(ctx, exp_action(op, 0, b0, mixed, u, 1, b1, b0, s, nullptr, 1.0, 1.0, staged(op), staged(op),
-                             natural(op), dg));
+      if (dg && chain_active(op))
+        HIPCHK(ctx, chain_action(op, 0, 1, u, natural(op), s));
+      else
+        HIPCHK(ctx, exp_action(op, 0, b0, mixed, u, 1, b1, b0, s, nullptr, 1.0, 1.0, staged(op), staged(op),
+                               natural(op), dg));
     } else if (op->scheme == MM_SLE) {
       // u+ = u + tau e^{tau A} F(u)
       StencilArgs f = stencil_args(op, u, true);
@@ -1650,6 +1745,7 @@ mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hi
       const bool dg = stencil_digits(op);
       if (dg) {
         set_stencil_digits(a, op, op->vdig, op->vexp, 2);
+        a.dchain = chain_active(op);
       } else if (mixed) {
         a.out0f = (float*)b0;
         a.out1f = (float*)b0 + dp;
@@ -1659,8 +1755,11 @@ mm_status enqueue_lawson(mm_ctx* ctx, const mm_op* op, double* u, int nsteps, hi
       }
       HIPCHK(ctx, stencil(op, a, s));
       double* res = (op->d == 3) ? b1 : b0;
-      HIPCHK(ctx, exp_action(op, 0, b0, mixed, res, 2, b1, b0, s, nullptr, 1.0, 1.0, staged(op), staged(op),
-                             staged(op), dg));
+      if (dg && chain_active(op))
+        HIPCHK(ctx, chain_action(op, 0, 2, res, staged(op), s));
+      else
+        HIPCHK(ctx, exp_action(op, 0, b0, mixed, res, 2, b1, b0, s, nullptr, 1.0, 1.0, staged(op), staged(op),
+                               staged(op), dg));
       StencilArgs c = stencil_args(op, res, false);
       c.base0 = res + dp;
       c.c0 = 0.5 * tau;
@@ -2219,6 +2318,16 @@ mm_status mm_timing_enable(mm_ctx* ctx, int enable) {
   if (!ctx) return MM_EINVAL;
   ctx->timing = enable != 0;
   ctx->timed_used = 0;
+  return MM_OK;
+}
+
+mm_status mm_set_sliced_chain(mm_ctx* ctx, int mode) {
+  if (!ctx) return MM_EINVAL;
+  if (mode < 0 || mode > 3) {
+    set_err(ctx, "sliced chain mode must be 0, 1, 2 or 3");
+    return MM_EINVAL;
+  }
+  ctx->sliced_chain = mode;
   return MM_OK;
 }
 

@@ -100,6 +100,9 @@ struct StencilArgs {
   int* dexp;
   int dS;
   int64_t dplane, drow1;
+  // with dig: write the chain layout of the chained mode products instead (operand row r
+  // is fiber r % n2 of group r / n2, exponent at (r / n2) 256 + r % n2; needs n2 <= 256)
+  int dchain;
 };
 // whether every x1 row of n1 points is covered by one wave of the stencil (the condition
 // of the digit output)
@@ -151,6 +154,38 @@ hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s);
 int choose_tile(const GemmArgs& g, int prec);
 // MM_SLICED mode product (64 x 64 tiles; factor operand as digit planes).
 hipError_t launch_gemm_sliced(GemmArgs& g, hipStream_t s);
+// MM_SLICED chained mode product: C (M x F per fiber group) = F_mu (M x K) . V^T, with the
+// grid operand V given as digit planes of whole fibers in the chain layout and one
+// exponent per fiber. Fiber group g = v Gv + gi of stacked vector v holds F <= 256 fibers.
+// A tile computes 32 factor rows against all fibers of one group, so every output row m
+// is a whole fiber of the next product: the epilogue writes it as that product's digits
+// (linear fiber (v M + m) Gv + gi, i.e. fiber lin % Fn of group lin / Fn with Fn that
+// product's fibers per group; positions j; exponent from the row's maximum: the definition
+// of the grid split) or, for the last mode, as FP64 values out[v ovs + (m Gv + gi) ldo + j].
+// The launcher refuses launches whose chain-layout input or output would not fit the
+// given workspace capacities.
+struct ChainArgs {
+  const signed char* fdig;   // factor digit planes (row stride slice_ld(K), fplane apart)
+  const int* fexp;           // factor row exponents
+  int64_t fplane;
+  const signed char* vdig;   // input fibers' digits in the chain layout (slice_digits.h),
+  const int* vexp;           // exponent of fiber j of group g at g 256 + j
+  int M, K, F, Gv, nvec;
+  int slices;
+  signed char* odig;         // digit output in the chain layout (null: FP64 output)
+  int* oexp;
+  int Fn;                    // fibers per group of the next product (digit output)
+  int64_t vcap, vexp_cap;    // bytes and exponents of the input workspace
+  int64_t ocap, oexp_cap;    // bytes and exponents of the output workspace
+  double* out;               // FP64 output
+  int ldo;
+  int64_t ovs;
+  double alpha;
+  int wide;                  // 0: eight waves of 32 fibers; 1: four waves of 64 fibers
+  // filled by the launcher
+  int tiles_m, total, per_xcd;
+};
+hipError_t launch_gemm_sliced_chain(ChainArgs& c, hipStream_t s);
 // Split rows x k (row stride lds) into S digit planes of row stride ldd (plane stride
 // rows*ldd bytes, zero for k <= c < ldd) and per-row exponents.
 hipError_t launch_slice_rows(signed char* dst, int* exps, const double* src, int rows, int k, int lds, int ldd,
@@ -250,6 +285,7 @@ struct mm_ctx {
   int gemm_tile = 0;              // 0 = automatic, else forced 64 or 128
   int graph_steps = 0;            // >0: step calls replay captured graphs of this many steps
   bool small_fused = true;        // small 2D Lawson solves as one-workgroup kernels
+  int sliced_chain = 1;           // MM_SLICED chained actions (mm_set_sliced_chain)
   hipStream_t capture = nullptr;  // private stream used only to record graphs
   std::vector<mm_timed> timed;
   size_t timed_used = 0;
@@ -309,6 +345,11 @@ struct mm_op {
   signed char* vdig = nullptr;
   int* vexp = nullptr;
   int64_t vdig_len = 0, vexp_len = 0;
+  // MM_SLICED Lawson steps: the second digit workspace of chained actions (the mode
+  // products alternate between the two)
+  signed char* vdig2 = nullptr;
+  int* vexp2 = nullptr;
+  int64_t vdig2_len = 0, vexp2_len = 0;
   int* flag = nullptr;                 // sticky non-finite flag
   int64_t bytes = 0;                   // device footprint
   // recorded step graph: `gsteps` steps on state `gu` (rebuilt when either changes)

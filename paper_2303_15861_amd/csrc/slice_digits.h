@@ -56,5 +56,15 @@ __device__ __forceinline__ void slice4(double v0, double v1, double v2, double v
   }
 }
 
+// Chain layout of S digit planes, the grid operand of the chained mode products: fibers
+// come in groups of at most 256 (fiber j of group g), positions k are padded to kp = 64 nch.
+// Per (32-fiber block, 64-k chunk, plane) one 2 KB block holds the 32 fibers' 64-byte
+// chunks one after another, so a writer of 16 consecutive positions of one fiber writes
+// within one 64-byte run, and a load of MFMA fragments (lane j % 32 + 32 h: the chunk
+// bytes [32 h + 16 ks, +16) at step ks) covers one 2 KB block. Offset of (g, j, k, s):
+__host__ __device__ inline int64_t chain_offset(int64_t g, int j, int k, int s, int nch, int S) {
+  return (((g * 8 + (j >> 5)) * nch + (k >> 6)) * S + s) * 2048 + (j & 31) * 64 + (k & 63);
+}
+
 }  // namespace digits
 }  // namespace mm

@@ -288,6 +288,273 @@ __global__ __launch_bounds__(TH, 2) void gemm_i8(GemmArgs p) {
   }
 }
 
+// ---------------------------------------------------------------- chained products
+// A tile: 32 factor rows (m) against the F <= 256 fibers of one fiber group (j), all K.
+// The factor digits are staged through LDS (shared by every wave); each wave streams the
+// digits of its own WN fibers straight from memory into MFMA fragment registers, one
+// 2 KB block per pair of load instructions (the chain layout of slice_digits.h). At MFMA
+// step ks of a 64-k chunk, lane half h supplies chunk bytes [32h + 16ks, +16) of both
+// operands (a fixed permutation of k; integer sums do not depend on the order).
+// The epilogue combines the digit levels in FP64 exactly as gemm_i8 does; for a middle
+// mode it stages the 32 x 256 result tile in LDS, takes each row's maximum (a whole fiber
+// of the next product) and writes the row's digit planes and exponent in the chain layout,
+// the digits that slice_grid would produce for the same values.
+// Workgroups are persistent (one per compute unit, each walking tiles of its XCD's range;
+// the eight factor-row tiles of a fiber group run side by side on one XCD and share its
+// digits in L2), and the last chunk of a tile already loads the next tile's first factor
+// chunk, grid fragments and exponents, so that their latency and the epilogue overlap.
+namespace {
+constexpr int CM = 32;        // factor rows per tile
+constexpr int CF = 256;       // fibers per tile
+constexpr int CPI = 80;       // LDS row pitch (bytes) of the staged factor digits
+constexpr int CPD = CF + 32;  // LDS row pitch (doubles) of the staged result tile: two
+                              // doubles of padding after every 16, so that the 16 lanes
+                              // reading one row's 16-value segments hit distinct banks
+constexpr int CSLOTS = 32;    // persistent workgroups per XCD (one per compute unit)
+__device__ __forceinline__ int cs_col(int j) { return j + 2 * (j >> 4); }
+}  // namespace
+
+template <int S, int WN>
+__global__ __launch_bounds__(64 * (CF / WN), 1) void gemm_i8_chain(ChainArgs p) {
+  constexpr int NW = CF / WN;      // waves
+  constexpr int NT = 64 * NW;      // threads
+  constexpr int NB = WN / 32;      // 32-fiber MFMA blocks per wave
+  const int xcd = blockIdx.x & 7, nslot = gridDim.x >> 3;
+  const int Pend = min(p.total, (xcd + 1) * p.per_xcd);
+  int P = xcd * p.per_xcd + (blockIdx.x >> 3);
+  if (P >= Pend) return;
+  const int M = p.M, K = p.K, F = p.F;
+  const int kp = slice_ld(K);
+  const int nch = kp / 64;
+
+  constexpr int ABYTES = 2 * S * CM * CPI;
+  __shared__ __attribute__((aligned(16))) unsigned char As[ABYTES];
+  __shared__ __attribute__((aligned(16))) double Cs[CM * CPD];
+  __shared__ __attribute__((aligned(16))) int Fe[2][CM];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5, rl = lane & 31;
+
+  // factor staging: piece q = (plane, row, 16-byte part) -> registers -> LDS
+  constexpr int APIECES = S * CM * 4;
+  constexpr int AREG = (APIECES + NT - 1) / NT;
+  i4 ra[AREG];
+  auto aload = [&](int m0, int c) {
+#pragma unroll
+    for (int i = 0; i < AREG; ++i) {
+      const int q = tid + i * NT;
+      if (q < APIECES) {
+        const int s = q / (4 * CM), r = (q >> 2) % CM, part = q & 3;
+        ra[i] = *reinterpret_cast<const i4*>(p.fdig + s * p.fplane + (int64_t)min(m0 + r, M - 1) * kp + c * 64 +
+                                             16 * part);
+      }
+    }
+  };
+  auto astore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < AREG; ++i) {
+      const int q = tid + i * NT;
+      if (q < APIECES) {
+        const int s = q / (4 * CM), r = (q >> 2) % CM, part = q & 3;
+        *reinterpret_cast<i4*>(As + ((buf * S + s) * CM + r) * CPI + 16 * part) = ra[i];
+      }
+    }
+  };
+
+  // grid fragments of the two MFMA steps of a chunk: slot ks holds step ks and is
+  // refilled with step ks of the next chunk (of this tile, else the next tile's first)
+  // right after that step's products
+  i4 bq[NB][S][2];
+  auto gbase = [&](int g, int b) {
+    return p.vdig + ((int64_t)(g * 8 + wave * NB + b) * nch) * (S * 2048) + rl * 64 + 32 * half;
+  };
+  auto bload = [&](const signed char* const (&base)[NB], int c, int ks) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+        bq[b][s][ks] = *reinterpret_cast<const i4*>(base[b] + (c * S + s) * 2048 + ks * 16);
+  };
+
+  // the first tile's prefetch
+  const signed char* vbn[NB];
+  int ve_n[NB], fe_n = 0;
+  {
+    const int g = P / p.tiles_m, m0 = (P % p.tiles_m) * CM;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) vbn[b] = gbase(g, b);
+    aload(m0, 0);
+    bload(vbn, 0, 0);
+    bload(vbn, 0, 1);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) ve_n[b] = p.vexp[g * 256 + wave * WN + 32 * b + rl];
+    if (tid < CM) fe_n = p.fexp[min(m0 + tid, M - 1)];
+  }
+
+  for (int it = 0;; ++it) {
+    const int m0 = (P % p.tiles_m) * CM, grp = P / p.tiles_m;
+    const int v = grp / p.Gv, gi = grp - v * p.Gv;
+    const int Pn = P + nslot;
+    const bool next = Pn < Pend;
+    const int m0n = next ? (Pn % p.tiles_m) * CM : m0, grpn = next ? Pn / p.tiles_m : grp;
+    const signed char* vb[NB];
+    int ve[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      vb[b] = vbn[b];
+      vbn[b] = gbase(grpn, b);
+      ve[b] = ve_n[b];
+    }
+    const int fe = it & 1;
+    if (tid < CM) Fe[fe][tid] = fe_n;
+    astore(0);
+
+    i16 acc[NB][S];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int l = 0; l < S; ++l)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[b][l][e] = 0;
+    __syncthreads();
+
+    for (int c = 0; c < nch; ++c) {
+      const int buf = c & 1;
+      const bool more = c + 1 < nch;
+      const bool pre = more || next;   // a chunk to prefetch (this tile's or the next's)
+      if (pre) aload(more ? m0 : m0n, more ? c + 1 : 0);
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        i4 af[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+          af[s] = *reinterpret_cast<const i4*>(As + ((buf * S + s) * CM + rl) * CPI + 32 * half + 16 * ks);
+        // round r: factor digit r against grid digit l - r for every level l >= r, the
+        // levels alternating direction between steps (as in gemm_i8), blocks innermost
+#pragma unroll
+        for (int r = 0; r < S; ++r)
+#pragma unroll
+          for (int i = 0; i < S - r; ++i) {
+            const int l = ks ? r + i : S - 1 - i;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+              acc[b][l] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[r], bq[b][l - r][ks], acc[b][l], 0, 0, 0);
+          }
+        if (pre) bload(more ? vb : vbn, more ? c + 1 : 0, ks);
+      }
+      if (more) astore(buf ^ 1);
+      __syncthreads();
+    }
+    if (next) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) ve_n[b] = p.vexp[grpn * 256 + wave * WN + 32 * b + rl];
+      if (tid < CM) fe_n = p.fexp[min(m0n + tid, M - 1)];
+    }
+
+    // accumulator element e of lane l: factor row 8(e/4) + 4(l/32) + e%4, fiber l%32 of
+    // the block; the factor-row exponents of four consecutive elements in one 16-byte read
+    const double alpha = p.alpha;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const i4 fq = *reinterpret_cast<const i4*>(&Fe[fe][8 * q + 4 * half]);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = wave * WN + 32 * b + rl;
+#pragma unroll
+        for (int e4 = 0; e4 < 4; ++e4) {
+          const int e = 4 * q + e4, ml = 8 * q + 4 * half + e4, m = m0 + ml;
+          double x = (double)acc[b][S - 1][e];
+#pragma unroll
+          for (int l = S - 2; l >= 0; --l) x = __builtin_fma(x, 0x1p-8, (double)acc[b][l][e]);
+          x = alpha * __builtin_ldexp(x, fq[e4] + ve[b] - 12);
+          if (!p.odig) {
+            if (m < M && j < F) p.out[(int64_t)v * p.ovs + ((int64_t)m * p.Gv + gi) * p.ldo + j] = x;
+          } else {
+            Cs[ml * CPD + cs_col(j)] = (m < M && j < F) ? x : 0.0;
+          }
+        }
+      }
+    }
+    if (p.odig) {
+      __syncthreads();
+      // row r of the tile in 16-value segments, one per thread; the 16 segments of a row
+      // are 16 consecutive lanes
+      const int kq = slice_ld(F), nchq = kq / 64;
+#pragma unroll
+      for (int itm = tid; itm < CM * 16; itm += NT) {
+        const int r = itm >> 4, sg = itm & 15;
+        double x[16];
+        double mx = 0.0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          x[i] = Cs[r * CPD + cs_col(16 * sg) + i];
+          mx = __builtin_fmax(mx, __builtin_fabs(x[i]));
+        }
+#pragma unroll
+        for (int off = 8; off >= 1; off >>= 1) mx = __builtin_fmax(mx, __shfl_xor(mx, off));
+        const int e = row_exponent(mx);
+        const int m = m0 + r;
+        if (m < M && 16 * sg < kq) {
+          // the next product's fiber: group go, fiber jn
+          const int64_t lin = ((int64_t)v * M + m) * p.Gv + gi;
+          const int64_t go = lin / p.Fn;
+          const int jn = (int)(lin - go * p.Fn);
+          unsigned pl[4][S];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            digits::slice4<S>(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3], e, pl[q]);
+          signed char* o = p.odig + digits::chain_offset(go, jn, 16 * sg, 0, nchq, S);
+#pragma unroll
+          for (int s = 0; s < S; ++s)
+            *reinterpret_cast<i4*>(o + s * 2048) = i4{(int)pl[0][s], (int)pl[1][s], (int)pl[2][s], (int)pl[3][s]};
+          if (sg == 0) p.oexp[go * 256 + jn] = e;
+        }
+      }
+    }
+    if (!next) break;
+    P = Pn;
+  }
+}
+
+hipError_t launch_gemm_sliced_chain(ChainArgs& c, hipStream_t s) {
+  if (c.M < 1 || c.K < 1 || c.F < 1 || c.F > CF || c.Gv < 1 || c.Gv > CF || c.nvec < 1) return hipErrorInvalidValue;
+  if ((int64_t)c.K * c.slices * 16384 >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  if (!c.fdig || !c.fexp || !c.vdig || !c.vexp || (c.odig ? !c.oexp : !c.out)) return hipErrorInvalidValue;
+  c.tiles_m = (c.M + CM - 1) / CM;
+  const int64_t total = (int64_t)c.tiles_m * c.Gv * c.nvec;
+  if (total >= ((int64_t)1 << 28)) return hipErrorInvalidValue;
+  // chain-layout extents: groups of 256 fibers, positions padded to 64
+  const int64_t gin = (int64_t)c.nvec * c.Gv;
+  if (gin * 256 * c.slices * slice_ld(c.K) > c.vcap || gin * 256 > c.vexp_cap) return hipErrorInvalidValue;
+  if (c.odig) {
+    const int64_t fibers = (int64_t)c.nvec * c.M * c.Gv;   // the next product's fibers
+    if (c.Fn < 1 || c.Fn > CF || fibers % c.Fn != 0) return hipErrorInvalidValue;
+    const int64_t gout = fibers / c.Fn;
+    if (gout * 256 * c.slices * slice_ld(c.F) > c.ocap || gout * 256 > c.oexp_cap) return hipErrorInvalidValue;
+  }
+  c.total = (int)total;
+  c.per_xcd = (c.total + 7) / 8;
+  // one workgroup per compute unit (eight XCDs of 32), fewer for small launches
+  const dim3 grid(8 * std::min(CSLOTS, c.per_xcd));
+#define MM_CHAIN_CASE(SS)                                                             \
+  case SS:                                                                            \
+    if (c.wide)                                                                       \
+      gemm_i8_chain<SS, 64><<<grid, dim3(256), 0, s>>>(c);                            \
+    else                                                                              \
+      gemm_i8_chain<SS, 32><<<grid, dim3(512), 0, s>>>(c);                            \
+    break;
+  switch (c.slices) {
+    MM_CHAIN_CASE(3)
+    MM_CHAIN_CASE(4)
+    MM_CHAIN_CASE(5)
+    MM_CHAIN_CASE(6)
+    MM_CHAIN_CASE(7)
+    default: return hipErrorInvalidValue;
+  }
+#undef MM_CHAIN_CASE
+  return hipGetLastError();
+}
+
 // Split `rows` rows of an FP64 matrix (row stride lds, k columns) into S digit planes of
 // row stride ldd (zero for k <= c < ldd) and per-row exponents. One workgroup per row.
 __global__ __launch_bounds__(TH) void slice_rows(signed char* dst, int* exps, const double* src, int rows, int k,

@@ -114,15 +114,21 @@ __device__ __forceinline__ void write_row_digits(const double (&v)[P], int cnt, 
   for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
   int e = 0;
   __builtin_frexp(m, &e);                            // m < 2^e (e = 0 for m = 0)
-  if ((threadIdx.x & 63) == 0) p.dexp[row] = e;
+  // row layout: plane t at t dplane, row r at r kp; chain layout (slice_digits.h): fiber
+  // r % n2 of group r / n2, the P values of a lane inside one 16-byte fragment, planes
+  // 2048 bytes apart
+  const int64_t g = p.dchain ? row / p.n2 : 0;
+  const int j = p.dchain ? (int)(row - g * p.n2) : 0;
+  if ((threadIdx.x & 63) == 0) p.dexp[p.dchain ? g * 256 + j : row] = e;
   if (x >= kp) return;
-  signed char* base = p.dig + row * kp + x;
+  signed char* base = p.dchain ? p.dig + digits::chain_offset(g, j, x, 0, kp / 64, S) : p.dig + row * kp + x;
+  const int64_t pstride = p.dchain ? 2048 : p.dplane;
   if constexpr (P == 4) {
     // four consecutive values: one 4-byte word per plane through the byte transpose
     unsigned pl[S];
     digits::slice4<S>(cnt > 0 ? v[0] : 0.0, cnt > 1 ? v[1] : 0.0, cnt > 2 ? v[2] : 0.0, cnt > 3 ? v[3] : 0.0, e, pl);
 #pragma unroll
-    for (int t = 0; t < S; ++t) *(unsigned*)(base + t * p.dplane) = pl[t];
+    for (int t = 0; t < S; ++t) *(unsigned*)(base + t * pstride) = pl[t];
   } else {
     unsigned lo[P], hi[P];
 #pragma unroll
@@ -134,9 +140,9 @@ __device__ __forceinline__ void write_row_digits(const double (&v)[P], int cnt, 
 #pragma unroll
       for (int k = 0; k < P; ++k) w |= (((i < 4 ? lo[k] >> (8 * i) : hi[k] >> (8 * (i - 4))) & 255u) << (8 * k));
       if constexpr (P == 2)
-        *(unsigned short*)(base + t * p.dplane) = (unsigned short)w;
+        *(unsigned short*)(base + t * pstride) = (unsigned short)w;
       else
-        *(base + t * p.dplane) = (signed char)w;
+        *(base + t * pstride) = (signed char)w;
     }
   }
 }
@@ -403,7 +409,8 @@ hipError_t launch_stencil_batch(int d, const StencilArgs* a, int count, hipStrea
       return hipErrorInvalidValue;
   for (int i = 0; i < count; ++i)
     if (a[i].dig && (!a[i].dexp || a[i].dS < kMinSlices || a[i].dS > kMaxSlices || !stencil_row_in_one_wave(a[i].n1) ||
-                     (a[i].base1 != a[i].u && a[i].base1 != nullptr && a[i].drow1)))
+                     (a[i].base1 != a[i].u && a[i].base1 != nullptr && a[i].drow1) ||
+                     (a[i].dchain && (a[i].n2 > 256 || (a[i].drow1 && a[i].drow1 % a[i].n2 != 0)))))
       return hipErrorInvalidValue;
   int P;
   StencilGrid sg;
