@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-at-T", action="store_true", help="skip the untimed runs to T")
-    ap.add_argument("--serve", default="fp64,sliced6",
+    ap.add_argument("--serve", default="fp64,sliced5",
                     help="precisions for the served-stream run ('' to skip)")
     ap.add_argument("--serve-count", type=int, default=512)
     ap.add_argument("--serve-active", type=int, default=32)

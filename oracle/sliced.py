@@ -8,15 +8,17 @@ used here to run the mu-mode products on integer matrix units.
 Definition (S digits, 3 <= S <= 7).
   * Every factor row and every fiber of the grid operand (the values along the
     contracted axis with all other indices fixed) gets the exponent e with
-    max|x| < 2^e (the frexp exponent of the maximum; e = 0 for an all-zero row).
-  * A value x becomes the integer Y = round_half_even(x 2^(8S - 2 - e)), so that
-    |Y| <= 2^(8S-2), written in balanced base 256: Y = sum_(i<S) b_i 256^i with every
-    b_i in [-128, 127] (unique; S balanced digits reach about 2^(8S-1), so every such
-    Y has one). Digit planes are kept most significant first, d_s = b_(S-1-s), so that
-        x ~ 2^(e+2) sum_s d_s 2^(-8(s+1)).
+    m (1 + 2^-7) < 2^e for its maximum m = max|x| (the frexp exponent of the FP64
+    product m * (1 + 2^-7); e = 0 for an all-zero row), so that max|x| < 0.993 2^e.
+  * A value x becomes the integer Y = round_half_even(x 2^(8S - 1 - e)), so that
+    |Y| < 0.4963 256^S, written in balanced base 256: Y = sum_(i<S) b_i 256^i with
+    every b_i in [-128, 127] (unique; S balanced digits cover [-0.502, 0.498] 256^S,
+    so every such Y has one). Digit planes are kept most significant first,
+    d_s = b_(S-1-s), so that
+        x ~ 2^(e+1) sum_s d_s 2^(-8(s+1)).
   * A factor row (exponent a, digits f_s) contracted with a fiber (exponent b,
     digits v_t) keeps the digit products with s + t < S:
-        sum_k f v ~ 2^(a + b - 12) sum_(l<S) 2^(-8 l) P_l,
+        sum_k f v ~ 2^(a + b - 14) sum_(l<S) 2^(-8 l) P_l,
         P_l = sum_(s+t=l) sum_k f_s[k] v_t[k]      (exact integers),
     combined from the top level down, v <- v 2^-8 + P_l, in FP64.
 The errors are the dropped levels s + t >= S and the rounding of Y, both of order
@@ -36,16 +38,16 @@ from .expo import axis_of
 
 
 def exponents(X: np.ndarray) -> np.ndarray:
-    """e with max|x| < 2^e along the last axis (0 for all-zero rows)."""
+    """e with max|x| (1 + 2^-7) < 2^e along the last axis (0 for all-zero rows)."""
     mx = np.max(np.abs(X), axis=-1)
-    _, e = np.frexp(mx)
+    _, e = np.frexp(mx * (1.0 + 2.0 ** -7))
     return e.astype(np.int64)
 
 
 def digits(X: np.ndarray, e: np.ndarray, S: int) -> np.ndarray:
     """Balanced base-256 digits (S, *X.shape), most significant first, of X relative to
     row exponents e (X.shape[:-1])."""
-    Y = np.rint(np.ldexp(X, (8 * S - 2 - e)[..., None])).astype(np.int64)
+    Y = np.rint(np.ldexp(X, (8 * S - 1 - e)[..., None])).astype(np.int64)
     out = np.empty((S,) + X.shape)
     for i in range(S):                          # least significant first
         b = ((Y + 128) & 255) - 128
@@ -68,7 +70,7 @@ def matmul_rows(A: np.ndarray, B: np.ndarray, S: int) -> np.ndarray:
     v = P[S - 1]
     for lvl in range(S - 2, -1, -1):
         v = v * 2.0 ** -8 + P[lvl]
-    return np.ldexp(v, ea[:, None] + eb[None, :] - 12)
+    return np.ldexp(v, ea[:, None] + eb[None, :] - 14)
 
 
 def mode_product(V: np.ndarray, M: np.ndarray, mu: int, S: int) -> np.ndarray:

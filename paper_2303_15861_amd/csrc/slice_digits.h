@@ -1,8 +1,9 @@
 // Exact-slice digits of FP64 values (device code shared by the grid split of the
 // exact-slice mode products and the stencil that can write its stage vectors as digit
-// planes). A value x with exponent e (|x| < 2^e for its whole row or fiber) becomes
-// Y = rint(x 2^(8S-2-e)), |Y| <= 2^(8S-2), written with S balanced base-256 digits in
-// [-128, 127]: the bytes of Y + 0x80..80, each minus 128 (an XOR with 0x80 per byte).
+// planes). A row or fiber with maximum m gets the exponent e of m (1 + 2^-7) (so that
+// m < 0.993 2^e); a value x becomes Y = rint(x 2^(8S-1-e)), |Y| < 0.4963 256^S, written
+// with S balanced base-256 digits in [-128, 127] (they cover [-0.502, 0.498] 256^S): the
+// bytes of Y + 0x80..80, each minus 128 (an XOR with 0x80 per byte).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,11 +11,18 @@
 namespace mm {
 namespace digits {
 
+// The exponent of a row or fiber with maximum m >= 0 (0 for m = 0).
+__device__ __forceinline__ int digit_exponent(double m) {
+  int e = 0;
+  __builtin_frexp(m * (1.0 + 0x1p-7), &e);
+  return e;
+}
+
 // Balanced base-256 digits of x relative to exponent e, packed: byte i of (lo, hi) is
 // b_i (least significant first) as a two's-complement int8.
 template <int S>
 __device__ __forceinline__ void slice_bytes(double x, int e, unsigned& lo, unsigned& hi) {
-  const double y = __builtin_rint(__builtin_ldexp(x, 8 * S - 2 - e));   // |y| <= 2^(8S-2)
+  const double y = __builtin_rint(__builtin_ldexp(x, 8 * S - 1 - e));   // |y| < 0.4963 2^(8S)
   const double hf = __builtin_floor(y * 0x1p-32);
   const unsigned l = (unsigned)__builtin_fma(-hf, 0x1p32, y);           // exact, in [0, 2^32)
   const int h = (int)hf;

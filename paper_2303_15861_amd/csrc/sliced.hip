@@ -1,12 +1,13 @@
 // Exact-slice mode products on the int8 matrix cores (v_mfma_i32_32x32x32_i8).
 //
 // Every operand row r (along the contracted index k) gets a power-of-two scale: e_r with
-// max_k |x_rk| < 2^e_r. A value becomes Y = round(x 2^(8S-2-e_r)) (|Y| <= 2^(8S-2))
-// written with S balanced base-256 digits b_i in [-128, 127] (int8 exactly):
-//     x ~ 2^(e_r + 2 - 8S) sum_i b_i 256^i.
+// max_k |x_rk| (1 + 2^-7) < 2^e_r. A value becomes Y = round(x 2^(8S-1-e_r))
+// (|Y| < 0.4963 256^S) written with S balanced base-256 digits b_i in [-128, 127] (int8
+// exactly; they cover [-0.502, 0.498] 256^S):
+//     x ~ 2^(e_r + 1 - 8S) sum_i b_i 256^i.
 // The digits are the bytes of Y + 0x80..80 each minus 128 (an XOR with 0x80 per byte),
 // so one 64-bit add and two XORs give all of them, packed. Then
-//     sum_k A_mk B'_nk ~= 2^(e_m + e_n - 12) sum_(l<S) 2^(-8l) P_l,
+//     sum_k A_mk B'_nk ~= 2^(e_m + e_n - 14) sum_(l<S) 2^(-8l) P_l,
 //     P_l = sum_(s+t=l) sum_k dA_s dB_t     (digit planes s, t most significant first),
 // where every partial sum of P_l is an integer below S 2^14 K < 2^31 (checked at launch),
 // so the int32 accumulation is exact; the levels are combined in FP64 in the epilogue.
@@ -26,6 +27,8 @@
 #include "mm_internal.h"
 #include "slice_digits.h"
 
+#include <type_traits>
+
 namespace mm {
 
 typedef int i4 __attribute__((ext_vector_type(4)));
@@ -40,11 +43,7 @@ constexpr int PI8 = 80;     // LDS row pitch in bytes (chosen so that 16 lanes o
                             // counter still counts conflicts on this kernel's LDS accesses)
 constexpr int TH = 256;
 
-__device__ __forceinline__ int row_exponent(double mx) {
-  int e = 0;
-  __builtin_frexp(mx, &e);                   // mx < 2^e (e = 0 for mx = 0)
-  return e;
-}
+__device__ __forceinline__ int row_exponent(double mx) { return digits::digit_exponent(mx); }
 
 }  // namespace
 
@@ -280,7 +279,7 @@ __global__ __launch_bounds__(TH, 2) void gemm_i8(GemmArgs p) {
       double v = (double)acc[S - 1][j];
 #pragma unroll
       for (int l = S - 2; l >= 0; --l) v = __builtin_fma(v, 0x1p-8, (double)acc[l][j]);
-      const int e = (BT ? Fe[ml] + Ve[nl] : Ve[ml] + Fe[nl]) - 12;
+      const int e = (BT ? Fe[ml] + Ve[nl] : Ve[ml] + Fe[nl]) - 14;
       double o = alpha * __builtin_ldexp(v, e);
       if (Cadd) o += beta * Cadd[m * p.ldc + n];
       C[m * p.ldc + n] = o;
@@ -331,6 +330,7 @@ __global__ __launch_bounds__(64 * (CF / WN), 1) void gemm_i8_chain(ChainArgs p) 
   __shared__ __attribute__((aligned(16))) unsigned char As[ABYTES];
   __shared__ __attribute__((aligned(16))) double Cs[CM * CPD];
   __shared__ __attribute__((aligned(16))) int Fe[2][CM];
+  __shared__ __attribute__((aligned(16))) int Junk[256];   // target of the L2 prefetch loads
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int half = lane >> 5, rl = lane & 31;
@@ -409,16 +409,31 @@ __global__ __launch_bounds__(64 * (CF / WN), 1) void gemm_i8_chain(ChainArgs p) 
     if (tid < CM) Fe[fe][tid] = fe_n;
     astore(0);
 
-    i16 acc[NB][S];
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int l = 0; l < S; ++l)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[b][l][e] = 0;
     __syncthreads();
 
-    for (int c = 0; c < nch; ++c) {
+    // the next tile's grid digits into L2 while this tile runs: its eight factor-row tiles
+    // run on eight compute units of this XCD, each of which brings one 32-fiber block (one
+    // contiguous run of nch S 2 KB) with loads straight into a junk LDS block (no
+    // registers; issued after the step loads they must not delay)
+    const int64_t pf_base = ((int64_t)grpn * 8 + (Pn % p.tiles_m)) * nch * (S * 2048);
+    const bool pf = next && (Pn % p.tiles_m) < 8;
+    auto prefetch = [&](int c) {
+      constexpr int Q = (S + 3) / 4;   // 1 KB units per wave and chunk: 8 nch Q >= 2 nch S
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int u = wave + 8 * (c * Q + q);
+        if (u < 2 * nch * S)
+          __builtin_amdgcn_global_load_lds(
+              (const __attribute__((address_space(1))) void*)(p.vdig + pf_base + (int64_t)u * 1024 + lane * 16),
+              (__attribute__((address_space(3))) void*)Junk, 16, 0, 0);
+      }
+    };
+
+    i16 acc[NB][S];
+    // one 64-k chunk: two MFMA steps; Z: the tile's first chunk, whose first product of
+    // every level starts from zero instead of an accumulator
+    auto chunk = [&](auto zinit, int c) {
+      constexpr bool Z = decltype(zinit)::value;
       const int buf = c & 1;
       const bool more = c + 1 < nch;
       const bool pre = more || next;   // a chunk to prefetch (this tile's or the next's)
@@ -437,14 +452,21 @@ __global__ __launch_bounds__(64 * (CF / WN), 1) void gemm_i8_chain(ChainArgs p) 
           for (int i = 0; i < S - r; ++i) {
             const int l = ks ? r + i : S - 1 - i;
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
-              acc[b][l] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[r], bq[b][l - r][ks], acc[b][l], 0, 0, 0);
+            for (int b = 0; b < NB; ++b) {
+              if (Z && ks == 0 && r == 0)
+                acc[b][l] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[r], bq[b][l - r][ks], i16{}, 0, 0, 0);
+              else
+                acc[b][l] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[r], bq[b][l - r][ks], acc[b][l], 0, 0, 0);
+            }
           }
         if (pre) bload(more ? vb : vbn, more ? c + 1 : 0, ks);
       }
+      if (pf && more) prefetch(c);
       if (more) astore(buf ^ 1);
       __syncthreads();
-    }
+    };
+    chunk(std::true_type{}, 0);
+    for (int c = 1; c < nch; ++c) chunk(std::false_type{}, c);
     if (next) {
 #pragma unroll
       for (int b = 0; b < NB; ++b) ve_n[b] = p.vexp[grpn * 256 + wave * WN + 32 * b + rl];
@@ -466,7 +488,7 @@ __global__ __launch_bounds__(64 * (CF / WN), 1) void gemm_i8_chain(ChainArgs p) 
           double x = (double)acc[b][S - 1][e];
 #pragma unroll
           for (int l = S - 2; l >= 0; --l) x = __builtin_fma(x, 0x1p-8, (double)acc[b][l][e]);
-          x = alpha * __builtin_ldexp(x, fq[e4] + ve[b] - 12);
+          x = alpha * __builtin_ldexp(x, fq[e4] + ve[b] - 14);
           if (!p.odig) {
             if (m < M && j < F) p.out[(int64_t)v * p.ovs + ((int64_t)m * p.Gv + gi) * p.ldo + j] = x;
           } else {
@@ -575,10 +597,10 @@ __global__ __launch_bounds__(TH) void slice_rows(signed char* dst, int* exps, co
   if (threadIdx.x == 0) exps[r] = e;
   const int64_t plane = (int64_t)rows * ldd;
   for (int c = threadIdx.x; c < ldd; c += TH) {
-    // Y = round(x 2^(8S-2-e)) as a 64-bit integer; its balanced base-256 digits follow
+    // Y = round(x 2^(8S-1-e)) as a 64-bit integer; its balanced base-256 digits follow
     // from the bytes of Y + 0x80..80
     const double x = (c < k) ? row[c] : 0.0;
-    const double y = __builtin_rint(__builtin_ldexp(x, 8 * S - 2 - e));
+    const double y = __builtin_rint(__builtin_ldexp(x, 8 * S - 1 - e));
     long long Y = (long long)__builtin_floor(y * 0x1p-32) * 4294967296ll +
                   (long long)(unsigned)__builtin_fma(-__builtin_floor(y * 0x1p-32), 0x1p32, y);
     const unsigned long long U = (unsigned long long)Y + (0x8080808080808080ull >> (64 - 8 * S));

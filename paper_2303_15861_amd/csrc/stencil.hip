@@ -98,8 +98,8 @@ __device__ __forceinline__ void store_row(float* __restrict__ base, int64_t off,
 }
 
 // The exact-slice split of one stage vector's row (sliced.hip defines it for the mode
-// products): the row's exponent e (max |v| < 2^e, from a wave maximum: the whole row is
-// in this wave) and, per value, Y = rint(v 2^(8S-2-e)) written with S balanced base-256
+// products): the row's exponent e (max |v| (1 + 2^-7) < 2^e, from a wave maximum: the whole
+// row is in this wave) and, per value, Y = rint(v 2^(8S-1-e)) written with S balanced base-256
 // digits in [-128, 127], the bytes of Y + 0x80..80 each minus 128. Plane t holds digit
 // S-1-t (most significant first) at row r, position x of a plane of rows kp bytes;
 // values past n1 are zero digits. Every lane of the wave takes part (the reduction).
@@ -112,8 +112,7 @@ __device__ __forceinline__ void write_row_digits(const double (&v)[P], int cnt, 
     if (k < cnt) m = fmax(m, fabs(v[k]));
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-  int e = 0;
-  __builtin_frexp(m, &e);                            // m < 2^e (e = 0 for m = 0)
+  const int e = digits::digit_exponent(m);
   // row layout: plane t at t dplane, row r at r kp; chain layout (slice_digits.h): fiber
   // r % n2 of group r / n2, the P values of a lane inside one 16-byte fragment, planes
   // 2048 bytes apart

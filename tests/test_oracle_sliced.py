@@ -12,7 +12,7 @@ from oracle import adr, expo, sliced
 
 def py_digits(x: float, e: int, S: int):
     """Balanced base-256 digits of x by exact integer arithmetic (MSB first)."""
-    Y = round(Fraction(x) * Fraction(2) ** (8 * S - 2 - e))     # halves to even
+    Y = round(Fraction(x) * Fraction(2) ** (8 * S - 1 - e))     # halves to even
     Y0 = Y
     ds = []
     for _ in range(S):
@@ -24,7 +24,9 @@ def py_digits(x: float, e: int, S: int):
 
 
 def py_exponent(row):
-    m = max(abs(v) for v in row)
+    """The least e with m (1 + 2^-7) < 2^e, m the row maximum and the product rounded to
+    FP64 (Python floats multiply in IEEE double)."""
+    m = float(max(abs(v) for v in row)) * (1.0 + 2.0 ** -7)
     if m == 0:
         return 0
     e = 0
@@ -42,7 +44,12 @@ def test_digits_round_trip_exact(S):
     X[1, 3] = 0.0
     X[2] = 0.0
     X[3, 4] = -np.max(np.abs(X[3]))                 # the row maximum with a negative sign
+    # maxima just below a power of two: 0.99 keeps e = 0 (Y near the top of the digit
+    # range), 0.9999 is lifted to e = 1 by the 1 + 2^-7 margin
+    X[0] *= 0.99 / np.max(np.abs(X[0]))
+    X[4] *= 0.9999 / np.max(np.abs(X[4]))
     e = sliced.exponents(X)
+    assert (e[0], e[4]) == (0, 1)
     D = sliced.digits(X, e, S)
     assert np.all(D >= -128) and np.all(D <= 127)
     for i in range(X.shape[0]):
@@ -53,8 +60,10 @@ def test_digits_round_trip_exact(S):
             # the digits represent x to half a unit of the last digit
             rep = sum(Fraction(d) * Fraction(256) ** (S - 1 - s) for s, d in enumerate(ds))
             assert rep == Y
-            err = abs(rep * Fraction(2) ** (int(e[i]) + 2 - 8 * S) - Fraction(X[i, k]))
-            assert err <= Fraction(2) ** (int(e[i]) + 1 - 8 * S)
+            # within the positive range of S balanced digits
+            assert -Fraction(128 * (256 ** S - 1), 255) <= Y <= Fraction(127 * (256 ** S - 1), 255)
+            err = abs(rep * Fraction(2) ** (int(e[i]) + 1 - 8 * S) - Fraction(X[i, k]))
+            assert err <= Fraction(2) ** (int(e[i]) - 8 * S)
 
 
 def py_matmul_rows(A, B, S):
@@ -74,7 +83,7 @@ def py_matmul_rows(A, B, S):
             v = float(P[S - 1])
             for lvl in range(S - 2, -1, -1):
                 v = v * 2.0 ** -8 + float(P[lvl])
-            out[i, j] = np.ldexp(v, a + b - 12)
+            out[i, j] = np.ldexp(v, a + b - 14)
     return out
 
 
@@ -88,9 +97,9 @@ def test_matmul_matches_pure_python_definition(S):
 
 
 def test_small_integers_are_exact():
-    """Rows of integers |x| <= 127 (max 127, e = 7) are exact in the top two digits
-    (Y = x 2^(8S-9)), so every product falls in levels s + t <= 2 < S and the result is
-    the exact integer product."""
+    """Rows of integers |x| <= 127 (max 127, e = 8 since 127 (1 + 2^-7) = 128) are exact
+    in the top two digits (Y = x 2^(8S-9)), so every product falls in levels s + t <= 2 < S
+    and the result is the exact integer product."""
     rng = np.random.default_rng(3)
     A = rng.integers(-127, 128, (6, 40)).astype(float)
     B = rng.integers(-127, 128, (7, 40)).astype(float)
@@ -102,8 +111,8 @@ def test_small_integers_are_exact():
 
 def test_error_bound_and_decay():
     """|C - A B^T| <= 2^(-8S) * 16 S * K * max|A_i| max|B_j| (each value is within
-    2^(e+1-8S) <= 4 2^(-8S) max of its digits, and the first dropped level holds S - 1
-    products of at most 2^14 * 2^(a+b+4-8S-16)), and each extra digit gains about 2^8."""
+    2^(e-8S) <= 2.02 2^(-8S) max of its digits, and the first dropped level holds S - 1
+    products of at most 2^14 * 2^(a+b+2-8S-16)), and each extra digit gains about 2^8."""
     rng = np.random.default_rng(4)
     K = 200
     A = rng.standard_normal((20, K))
