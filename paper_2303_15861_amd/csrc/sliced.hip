@@ -368,12 +368,14 @@ __global__ __launch_bounds__(64 * (CF / WN), 1) void gemm_i8_chain(ChainArgs p) 
   auto gbase = [&](int g, int b) {
     return p.vdig + ((int64_t)(g * 8 + wave * NB + b) * nch) * (S * 2048) + rl * 64 + 32 * half;
   };
-  auto bload = [&](const signed char* const (&base)[NB], int c, int ks) {
+  auto bload_plane = [&](const signed char* const (&base)[NB], int c, int ks, int s) {
 #pragma unroll
     for (int b = 0; b < NB; ++b)
+      bq[b][s][ks] = *reinterpret_cast<const i4*>(base[b] + (c * S + s) * 2048 + ks * 16);
+  };
+  auto bload = [&](const signed char* const (&base)[NB], int c, int ks) {
 #pragma unroll
-      for (int s = 0; s < S; ++s)
-        bq[b][s][ks] = *reinterpret_cast<const i4*>(base[b] + (c * S + s) * 2048 + ks * 16);
+    for (int s = 0; s < S; ++s) bload_plane(base, c, ks, s);
   };
 
   // the first tile's prefetch
@@ -444,22 +446,26 @@ __global__ __launch_bounds__(64 * (CF / WN), 1) void gemm_i8_chain(ChainArgs p) 
 #pragma unroll
         for (int s = 0; s < S; ++s)
           af[s] = *reinterpret_cast<const i4*>(As + ((buf * S + s) * CM + rl) * CPI + 32 * half + 16 * ks);
-        // round r: factor digit r against grid digit l - r for every level l >= r, the
-        // levels alternating direction between steps (as in gemm_i8), blocks innermost
+        // round t: grid digit t against factor digit s for every level l = s + t < S (the
+        // factor digits alternate direction between steps, blocks innermost, so that
+        // consecutive products update different accumulators). Grid plane t is read in
+        // round t only: right after it, the plane's slot is refilled with the same step
+        // of the next chunk, two steps ahead of its use.
 #pragma unroll
-        for (int r = 0; r < S; ++r)
+        for (int t = 0; t < S; ++t) {
 #pragma unroll
-          for (int i = 0; i < S - r; ++i) {
-            const int l = ks ? r + i : S - 1 - i;
+          for (int i = 0; i < S - t; ++i) {
+            const int sa = ks ? i : S - 1 - t - i, l = sa + t;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-              if (Z && ks == 0 && r == 0)
-                acc[b][l] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[r], bq[b][l - r][ks], i16{}, 0, 0, 0);
+              if (Z && ks == 0 && t == 0)
+                acc[b][l] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[sa], bq[b][t][ks], i16{}, 0, 0, 0);
               else
-                acc[b][l] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[r], bq[b][l - r][ks], acc[b][l], 0, 0, 0);
+                acc[b][l] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[sa], bq[b][t][ks], acc[b][l], 0, 0, 0);
             }
           }
-        if (pre) bload(more ? vb : vbn, more ? c + 1 : 0, ks);
+          if (pre) bload_plane(more ? vb : vbn, more ? c + 1 : 0, ks, t);
+        }
       }
       if (pf && more) prefetch(c);
       if (more) astore(buf ^ 1);
