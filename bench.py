@@ -220,10 +220,15 @@ def roofline(kern, prec, p):
         roof = {"bound": "hbm", "achieved": 32.0 * k["work"] / secs / 1e9, "peak": HBM_PEAK / 1e9,
                 "unit": "GB/s"}
     elif prec.startswith("sliced"):
-        # int8 digit products executed, S(S+1)/2 per algorithmic multiply-add; the launch
-        # time includes the pass that splits the grid operand into digits
+        # int8 digit products executed, S(S+1)/2 per algorithmic multiply-add. Chained
+        # Lawson steps (every axis of 129..256 points under the default chain mode): each
+        # product's epilogue writes the next mode's digits; otherwise the launch time also
+        # includes the pass that splits the grid operand into digits
+        chained = p.scheme in ("le", "l2b") and all(128 < m <= 256 for m in p.n)
         roof = {"bound": "mfma", "achieved": k["work"] * slice_products(prec) / secs / 1e12,
-                "peak": PEAK["int8"] / 1e12, "unit": "TOP/s", "includes": "grid split + int8 product"}
+                "peak": PEAK["int8"] / 1e12, "unit": "TOP/s",
+                "includes": ("chained int8 product (its epilogue writes the next mode's digit planes)" if chained
+                             else "grid split + int8 product")}
     elif prec in ("bf16x3", "bf16x6"):
         # split-BF16 contractions are bound by HBM: 16 B per grid point per pass
         bytes_ = 16.0 * k["work"] / (2.0 * p.n[0])

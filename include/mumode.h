@@ -175,12 +175,13 @@ const char* mm_version(void);
  * theta_j for MM_ERK), plus the FP32, BF16-slice or digit-plane forms the precision
  * needs. Returns after the setup has finished. quad_nodes (q) is 1..7 for MM_ERK and
  * ignored for MM_LAWSON; q = 0 selects exact phi1 through the eigenbasis (FP64 only;
- * Dirichlet or periodic axes; Dirichlet axes need |beta_bar_mu| h_mu < 2 lambda a_max
- * so that the eigenvalues are real), and the op then also stores R_mu and L_mu. slices: digit count of MM_SLICED (0 = 6,
+ * Dirichlet axes need |beta_bar_mu| h_mu < 2 lambda a_max so that the eigenvalues are
+ * real, axes with a zero normal derivative at x = 1 need beta_bar_mu = 0, periodic axes
+ * take any beta_bar_mu), and the op then also stores R_mu and L_mu. slices: digit count of MM_SLICED (0 = 6,
  * else 3..7), ignored by the other precisions. `a` must be complete when the call is
  * made (the copy runs on the context's own stream, which does not wait for others).
  * Errors: MM_EINVAL (d, n < 1, tau <= 0 or not finite, unknown family/scheme/prec/bc/form,
- * exact phi1 with a Neumann axis,
+ * exact phi1 with beta_bar_mu != 0 on an axis with a zero normal derivative,
  * slices out of range, exact phi1 with another precision or complex eigenvalues,
  * a == NULL), MM_ENOMEM, MM_EDEVICE. */
 mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int family, int scheme,

@@ -27,10 +27,14 @@ The 1D matrices A_mu follow from the same ghost rule (the Neumann row reads
 with scipy.linalg.expm on the dense matrices. All-Dirichlet flux-form problems reduce
 to oracle.adr, which is written separately: the two agree (a pin).
 
+Exact phi functions (problems with q = 0) go through numpy's dense eigen-decomposition of
+every A_mu.
+
 Pins: tests/test_oracle_adr3d.py (the printed errors of Figure fig:adr3d_diffl for
 LE, SLE, L2a and SL2 at both advection speeds; the closed-form eigenpairs of the
 Dirichlet-Neumann second difference; agreement with oracle.adr on all-Dirichlet
-flux-form problems; F = A u + g).
+flux-form problems; F = A u + g; phi1 and phi2 of the Kronecker sum against the
+augmented-matrix exponential identities on small mixed grids).
 """
 from __future__ import annotations
 
@@ -148,6 +152,8 @@ class Backend:
         self.A = [operator_1d(prob.n[mu], self.bcs[mu], prob.lam * self.a_max, prob.beta_bar[mu])
                   for mu in range(prob.d)]
         self._E = {}
+        self._eigs = None
+        self.phi = "exact" if prob.q == 0 else "quad"
 
     def factors(self, c: float):
         if c not in self._E:
@@ -165,8 +171,38 @@ class Backend:
         p = self.p
         return full_rhs(v, p.a, p.beta, p.r, self.bcs, self.form)
 
+    def eigen(self):
+        """A_mu = V_mu diag(lam_mu) V_mu^-1 for every axis, from numpy's general dense
+        eigensolver (a different route from the closed forms the GPU path uses); the
+        spectra are real for the problems here (|beta_bar| h < 2 lam a_max)."""
+        if self._eigs is None:
+            self._eigs = []
+            for A in self.A:
+                lam, V = np.linalg.eig(A)
+                if np.max(np.abs(lam.imag)) > 1e-10 * max(1.0, float(np.max(np.abs(lam)))):
+                    raise ValueError("complex spectrum: no real eigenbasis for exact phi functions")
+                self._eigs.append((lam.real, V.real, np.linalg.inv(V.real)))
+        return self._eigs
+
+    def funv(self, f, v):
+        """f(tau A) v for the Kronecker sum A = A_d + ... + A_1: transform with V_mu^-1 along
+        every axis, scale by f(tau (lam_1 + ... + lam_d)), transform back with V_mu."""
+        eigs = self.eigen()
+        d = v.ndim
+        W = tucker(v, [e[2] for e in eigs])
+        total = np.zeros(W.shape)
+        for mu in range(d):
+            shape = [1] * d
+            shape[_axis(mu, d)] = eigs[mu][0].size
+            total = total + eigs[mu][0].reshape(shape)
+        return tucker(W * f(self.p.tau * total), [e[1] for e in eigs])
+
     def phi1v(self, v):
-        """The q-point Gauss-Legendre phi1: sum_j w_j exp(theta_j tau A) v."""
+        """phi1(tau A) v: exact (funv) for a problem without quadrature nodes (q = 0), else
+        the q-point Gauss-Legendre rule sum_j w_j exp(theta_j tau A) v."""
+        if self.phi == "exact":
+            from .expo import phi1
+            return self.funv(phi1, v)
         from .expo import gauss_legendre_01
         th, w = gauss_legendre_01(self.p.q)
         out = np.zeros_like(v)
@@ -174,12 +210,16 @@ class Backend:
             out += wj * self.expv(tj, v)
         return out
 
+    def phi2v(self, v):
+        from .expo import phi2
+        return self.funv(phi2, v)
+
 
 def solve(prob, steps=None, scheme=None) -> np.ndarray:
-    """prob.scheme from prob.u0 (Lawson schemes, or ETD2RK / ERK2P1 with quadrature
-    phi1)."""
+    """prob.scheme from prob.u0: Lawson schemes; ETD2RK / ERK2P1 with quadrature phi1
+    (q > 0) or exact phi1 (q = 0); EE and erk2p2 (exact phi functions, q = 0)."""
     from .schemes import integrate
     sch = scheme or prob.scheme
-    if sch not in ("le", "l2b", "sle", "l2a", "sl2", "etd2rk", "erk2p1f"):
-        raise ValueError("no exact phi functions for mixed boundary data")
+    if sch in ("ee", "erk2p2", "erk2p1") and prob.q != 0:
+        raise ValueError(f"{sch} needs exact phi functions (q = 0)")
     return integrate(prob.u0, Backend(prob), prob.tau, prob.steps if steps is None else steps, sch)

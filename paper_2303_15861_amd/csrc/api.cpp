@@ -780,6 +780,35 @@ bool eigen_closed_form(int n, double s, double delta, double t, std::vector<doub
   return true;
 }
 
+// The same for A = diff T_N on an axis with a zero normal derivative at x = 1: T_N is the
+// second difference whose last row, through the mirror ghost, reads [.., 2, -2] (just -2
+// for n = 1). With D = diag(1, .., 1, 1/sqrt(2)), D T_N D^-1 is symmetric, with the
+// orthonormal eigenvectors Q[j][k] = sqrt(2/n) D_jj sin((2k+1)(j+1) pi/(2n)) (the
+// sine modes that vanish at x = 0 and are flat at x = 1) and the eigenvalues
+// -4 sin^2((2k+1) pi/(4n)). Hence A = L diag(ev) R with L = D^-1 Q and R = Q^T D.
+void eigen_closed_form_neumann(int n, double diff, std::vector<double>& ev, std::vector<double>& R,
+                               std::vector<double>& L) {
+  const double pi = 3.14159265358979323846;
+  const double c = std::sqrt(2.0 / n);
+  const int64_t per = 4 * (int64_t)n;                    // sin(m pi/(2n)) has period 4n in m
+  ev.resize(n);
+  R.resize((size_t)n * n);
+  L.resize((size_t)n * n);
+  for (int k = 0; k < n; ++k) {
+    const double h = std::sin((2 * k + 1) * pi / (4.0 * n));
+    ev[k] = -4.0 * diff * h * h;
+  }
+  for (int j = 0; j < n; ++j) {
+    const double w = (j == n - 1) ? std::sqrt(0.5) : 1.0;   // D_jj
+    for (int k = 0; k < n; ++k) {
+      const int64_t m = ((int64_t)(2 * k + 1) * (j + 1)) % per;   // exact argument reduction
+      const double q = c * w * std::sin(m * pi / (2.0 * n));
+      L[(size_t)j * n + k] = q / w;                             // (D^-1 Q)[j][k]
+      R[(size_t)k * n + j] = q * w;                             // (Q^T D)[k][j]
+    }
+  }
+}
+
 // MM_SLICED Lawson steps: the first stencil pass writes its stage vectors (nvec of them,
 // stacked as operand rows) straight into the digit workspace of the mode-1 product, so
 // that product skips its split pass. Needs rows that one stencil wave covers.
@@ -1064,8 +1093,9 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
   }
   if (family == MM_ERK && quad_nodes == 0)
     for (int mu = 0; mu < prob->d; ++mu)
-      if (prob->bc[mu] == MM_BC_NEUMANN) {
-        set_err(ctx, "exact phi1 (quad_nodes = 0) needs Dirichlet or periodic axes (closed-form eigenbasis)");
+      if (prob->bc[mu] == MM_BC_NEUMANN && prob->beta_bar[mu] != 0.0) {
+        set_err(ctx, "exact phi1 (quad_nodes = 0) on an axis with a zero normal derivative needs beta_bar = 0 there "
+                     "(closed-form eigenbasis)");
         return MM_EINVAL;
       }
   if (prec < MM_FP64 || prec > MM_SLICED) {
@@ -1364,11 +1394,13 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
     // closed-form eigen-decomposition of every 1D operator (uploaded next to E(1))
     for (int mu = 0; mu < op->d; ++mu) {
       const int n = op->n[mu];
-      const double h = 1.0 / (n + 1);
+      const double h = mesh_h(op, mu);
       const double diff = op->lam * op->a_max / (h * h);
       const double adv = op->beta_bar[mu] / (2.0 * h);
       std::vector<double> ev, R, L;
-      if (!eigen_closed_form(n, diff - adv, -2.0 * diff, diff + adv, ev, R, L)) {
+      if (op->bc[mu] == MM_BC_NEUMANN)
+        eigen_closed_form_neumann(n, diff, ev, R, L);   // beta_bar = 0 there (checked)
+      else if (!eigen_closed_form(n, diff - adv, -2.0 * diff, diff + adv, ev, R, L)) {
         set_err(ctx, "exact phi1 needs |beta_bar| h < 2 lambda a_max on every axis (real eigenvalues)");
         return fail(MM_EINVAL);
       }

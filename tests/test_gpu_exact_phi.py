@@ -137,3 +137,59 @@ def test_exact_rejections(mm, ctx):
     with pytest.raises(mm.MumodeError):
         mm.setup_problem(ctx, q)
     assert "eigenvalues" in ctx.error()
+
+
+def paper3d_exact(N, scheme, steps, lam=0.5, b=-1.0):
+    """The problem of Sec. 5.2 with the advection left in g (beta_bar = 0, which the
+    closed-form eigenbasis of an axis with a zero normal derivative needs)."""
+    p = synth.paper3d_problem(N, b, lam, scheme=scheme, steps=steps)
+    p.beta_bar = (0.0, 0.0, 0.0)
+    p.q = 0
+    return p
+
+
+@pytest.mark.parametrize("n,bc,bb", [((16, 16, 16), (1, 1, 1), (0.0, 0.0, 0.0)),
+                                     ((17, 12, 9), (1, 0, 1), (0.0, 2.0, 0.0)),
+                                     ((30, 21), (0, 1), (-3.0, 0.0))])
+def test_neumann_transforms_invert_and_phi1(mm, ctx, n, bc, bb):
+    """Axes with a zero normal derivative at x = 1 (the closed-form eigenvectors
+    sin((2k+1) pi x/2)), next to Dirichlet axes with advection in A: R then L is the
+    identity, and phi1 matches the oracle's dense eigen-decomposition phi1."""
+    from oracle import adr3d
+    p = synth.smooth_problem(n, 31, tau=1e-3, scheme="etd2rk", q=0, beta_bar=bb, lam=0.8)
+    p.bc = bc
+    V = np.random.default_rng(32).standard_normal(p.shape)
+    op = mm.setup_problem(ctx, p)
+    x, y, z = dev(V), dev(np.zeros(p.shape)), dev(np.zeros(p.shape))
+    mm.mumode_expv(op, x, y, j=1)
+    mm.mumode_expv(op, y, z, j=2)
+    back = host(z)
+    w = dev(np.zeros(p.shape))
+    mm.mumode_phi1v(op, x, w)
+    got = host(w)
+    op.close()
+    assert relerr(back, V) <= 1e-13
+    assert relerr(got, adr3d.Backend(p).phi1v(V)) <= FP64_TOL
+
+
+@pytest.mark.parametrize("scheme,N,steps", [("ee", 16, 12), ("erk2p2", 16, 12), ("etd2rk", 20, 10), ("erk2p1f", 12, 8)])
+def test_neumann_exact_solves_paper3d(mm, ctx, scheme, N, steps):
+    """EE, erk2p2, ETD2RK and the Appendix ERK2P1 with exact phi on the problem of Sec. 5.2
+    (Dirichlet at 0, zero normal derivative at 1 on every axis, a Lap u)."""
+    from oracle import adr3d
+    p = paper3d_exact(N, scheme, steps)
+    op = mm.setup_problem(ctx, p)
+    u = dev(p.u0)
+    mm.step(op, u, p.steps)
+    assert mm.mm_check(op) == mm.MM_OK
+    got = host(u)
+    op.close()
+    assert relerr(got, adr3d.solve(p)) <= FP64_TOL
+
+
+def test_neumann_exact_rejects_advection_in_A(mm, ctx):
+    p = synth.paper3d_problem(12, -1.0, 0.5, scheme="etd2rk", steps=2)
+    p.q = 0                                   # beta_bar = b on every (Neumann) axis
+    with pytest.raises(mm.MumodeError):
+        mm.setup_problem(ctx, p)
+    assert "normal derivative" in ctx.error()

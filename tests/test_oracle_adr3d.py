@@ -104,3 +104,59 @@ def test_neumann_laplacian_second_order():
         lap = adr3d.full_rhs(u, a, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0, 0.0), (1, 1, 1), "nondiv")
         errs.append(np.max(np.abs(lap + 0.75 * np.pi ** 2 * u)))
     assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
+
+
+def _kron_sum(mats):
+    """The dense Kronecker sum A_d (+) ... (+) A_1 on C-ordered grid vectors (x1 fastest)."""
+    K = np.zeros((1, 1))
+    for A in reversed(mats):          # build from the slowest axis (the last) inwards
+        K = np.kron(K, np.eye(A.shape[0])) + np.kron(np.eye(K.shape[0]), A)
+    return K
+
+
+@pytest.mark.parametrize("bc,beta_bar", [((1, 0, 1), (0.0, 0.6, 0.0)), ((1, 1), (1.5, -2.0)), ((0, 1, 1), (2.0, -1.0, 0.3))])
+def test_exact_phi_against_augmented_exponentials(bc, beta_bar):
+    """phi1 and phi2 of the Kronecker sum through the 1D eigenbases, against the exponential
+    of the augmented matrices [[tau K, v, 0], [0, 0, 1], [0, 0, 0]], whose last column holds
+    phi1(tau K) v and phi2(tau K) v (Saad 1992; Al-Mohy and Higham 2011), on small mixed
+    Dirichlet/Neumann grids with advection in A."""
+    import scipy.linalg
+    n = (5, 4, 3)[: len(bc)]
+    p = synth.smooth_problem(n, 12, tau=3e-3, beta_bar=beta_bar, q=0)
+    p.bc = bc
+    be = adr3d.Backend(p)
+    K = _kron_sum(be.A)
+    v = np.random.default_rng(13).standard_normal(p.shape)
+    N = K.shape[0]
+    M = np.zeros((N + 2, N + 2))
+    M[:N, :N] = p.tau * K
+    M[:N, N] = v.ravel()
+    M[N, N + 1] = 1.0
+    E = scipy.linalg.expm(M)
+    ref1, ref2 = E[:N, N].reshape(p.shape), E[:N, N + 1].reshape(p.shape)
+    from oracle import expo as X
+    assert np.max(np.abs(be.funv(X.phi1, v) - ref1)) <= 1e-12 * np.max(np.abs(ref1))
+    assert np.max(np.abs(be.phi1v(v) - ref1)) <= 1e-12 * np.max(np.abs(ref1))
+    assert np.max(np.abs(be.phi2v(v) - ref2)) <= 1e-12 * np.max(np.abs(ref2))
+    # the same identity through the all-Dirichlet oracle (a different code path) on a
+    # Dirichlet grid, so that the augmented construction itself is checked
+    pd = synth.smooth_problem(n, 12, tau=3e-3, beta_bar=beta_bar, q=0)
+    op = X.KronOperator(pd.n, adr.extracted_amax(pd.a), pd.lam, pd.beta_bar, pd.tau)
+    bd = adr3d.Backend(pd)
+    assert np.max(np.abs(bd.phi2v(v) - op.phi2v_exact(v))) <= 1e-12 * np.max(np.abs(op.phi2v_exact(v)))
+
+
+def test_exact_phi_schemes_converge_on_mixed_data():
+    """EE (order 1) and erk2p2, ETD2RK with exact phi1 (order 2) on the Sec. 5.2 problem at
+    N = 8 with the advection left in g (beta_bar = 0), against a small-step Lawson2b
+    reference: observed orders within 0.2 of the classical ones."""
+    def prob(scheme, m):
+        p = synth.paper3d_problem(8, -1.0, 0.5, scheme=scheme, steps=m)
+        p.beta_bar = (0.0, 0.0, 0.0)
+        p.q = 0
+        return p
+    ref = adr3d.solve(prob("l2b", 2 ** 12))
+    for sch, order in (("ee", 1), ("erk2p2", 2), ("etd2rk", 2)):
+        e = [Sch.rel_inf_error(adr3d.solve(prob(sch, m)), ref) for m in (32, 64, 128)]
+        rates = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+        assert np.all(np.abs(rates - order) < 0.2), (sch, e, rates)
