@@ -56,8 +56,8 @@ WORKLOAD = "3d_n255_l2b"
 # stated error targets of the contraction modes at T (FP32; split / sliced modes)
 TARGET = {"fp32": 1e-6, "bf16x3": 1e-9, "bf16x6": 1e-9}
 # other workloads: (name, timed steps or None for the whole solve, precisions)
-CONFIGS = [("2d_n63_le", None, ("fp64",)), ("3d_n127_l2b", None, ("fp64", "sliced6")),
-           ("3d_n127_etd2rk", None, ("fp64",)), ("3d_n383_etd2rk", 5, ("fp64", "sliced6"))]
+CONFIGS = [("2d_n63_le", None, ("fp64",)), ("3d_n127_l2b", None, ("fp64", "sliced5")),
+           ("3d_n127_etd2rk", None, ("fp64",)), ("3d_n383_etd2rk", 5, ("fp64", "sliced5"))]
 
 
 def parse():
@@ -385,24 +385,32 @@ def cpu_baselines():
 
 
 def config_lines(mm, ctx, warmup):
-    """One line per other workload: ms/step, Mdof*steps/s and the dominant kernel's roofline."""
+    """One line per other workload: ms/step, Mdof*steps/s and the dominant kernel's roofline;
+    a mixed precision also states its error against the FP64 path after the same timed
+    steps from the same initial state."""
     import synth
     out = {}
     for name, steps, precs in CONFIGS:
         p = synth.workload(name)
         nsteps = steps or p.steps
+        ref = None
         for prec in precs:
             print(f"[bench] config {name} {prec}: {nsteps} timed steps", file=sys.stderr, flush=True)
             try:
-                op, _, dt, kern, status = time_mode(mm, ctx, p, prec, nsteps, min(warmup, 2))
+                op, state, dt, kern, status = time_mode(mm, ctx, p, prec, nsteps, min(warmup, 2))
             except mm.MumodeError as exc:
                 print(f"[bench] config {name} {prec}: {exc}", file=sys.stderr, flush=True)
                 continue
             op.close()
             roof, _ = roofline(kern, prec, p)
-            out[f"{name}_{prec}"] = {"workload": DESCRIPTION.get(name, name), "ms_per_step": 1e3 * dt / nsteps,
-                                     "value": p.dof * nsteps / dt / 1e6, "unit": "Mdof*steps/s",
-                                     "steps": nsteps, "status": mm.STATUS.get(status, status), "roofline": roof}
+            entry = {"workload": DESCRIPTION.get(name, name), "ms_per_step": 1e3 * dt / nsteps,
+                     "value": p.dof * nsteps / dt / 1e6, "unit": "Mdof*steps/s",
+                     "steps": nsteps, "status": mm.STATUS.get(status, status), "roofline": roof}
+            if prec == "fp64":
+                ref = state
+            elif ref is not None:
+                entry["err_vs_fp64_after_steps"] = float(np.max(np.abs(state - ref)) / np.max(np.abs(ref)))
+            out[f"{name}_{prec}"] = entry
     return out
 
 

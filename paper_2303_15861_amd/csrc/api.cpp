@@ -876,7 +876,6 @@ hipError_t chain_action(const mm_op* op, int j, int nvec, double* out, Layout lo
     c.Gv = (int)(op->dof / ((int64_t)n * nf));
     c.nvec = nvec;
     c.slices = op->slices;
-    c.alpha = 1.0;
     c.wide = mode == 3;
     if (mu + 1 < op->d) {
       c.odig = dig[cur ^ 1];

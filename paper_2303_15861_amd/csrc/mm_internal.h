@@ -180,7 +180,6 @@ struct ChainArgs {
   double* out;               // FP64 output
   int ldo;
   int64_t ovs;
-  double alpha;
   int wide;                  // 0: eight waves of 32 fibers; 1: four waves of 64 fibers
   // filled by the launcher
   int tiles_m, total, per_xcd;

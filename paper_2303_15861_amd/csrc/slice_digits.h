@@ -22,12 +22,22 @@ __device__ __forceinline__ int digit_exponent(double m) {
 // b_i (least significant first) as a two's-complement int8.
 template <int S>
 __device__ __forceinline__ void slice_bytes(double x, int e, unsigned& lo, unsigned& hi) {
-  const double y = __builtin_rint(__builtin_ldexp(x, 8 * S - 1 - e));   // |y| < 0.4963 2^(8S)
-  const double hf = __builtin_floor(y * 0x1p-32);
-  const unsigned l = (unsigned)__builtin_fma(-hf, 0x1p32, y);           // exact, in [0, 2^32)
-  const int h = (int)hf;
   constexpr unsigned long long C = 0x8080808080808080ull >> (64 - 8 * S);
-  const unsigned long long Y = ((((unsigned long long)(unsigned)h) << 32) | l) + C;
+  unsigned long long Y;   // round(x 2^(8S-1-e)) + C
+  if constexpr (S <= 6) {
+    // z = x 2^(8S-1-e), |z| < 0.4963 2^(8S) <= 2^47. Adding the integer 2^52 + C (exact
+    // in FP64) rounds z to the nearest integer, ties to even (the sum lies in
+    // [2^52, 2^53), where FP64 values are the integers, and 2^52 + C is even), and
+    // leaves round(z) + C in [0, 2^48) in the significand field.
+    const double d = __builtin_ldexp(x, 8 * S - 1 - e) + (double)((1ull << 52) + C);
+    Y = __builtin_bit_cast(unsigned long long, d) & ((1ull << 52) - 1);
+  } else {
+    const double y = __builtin_rint(__builtin_ldexp(x, 8 * S - 1 - e));   // |y| < 0.4963 2^(8S)
+    const double hf = __builtin_floor(y * 0x1p-32);
+    const unsigned l = (unsigned)__builtin_fma(-hf, 0x1p32, y);           // exact, in [0, 2^32)
+    const int h = (int)hf;
+    Y = ((((unsigned long long)(unsigned)h) << 32) | l) + C;
+  }
   lo = (unsigned)Y ^ 0x80808080u;
   hi = (unsigned)(Y >> 32) ^ 0x80808080u;
 }

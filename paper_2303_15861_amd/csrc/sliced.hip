@@ -297,7 +297,8 @@ __global__ __launch_bounds__(TH, 2) void gemm_i8(GemmArgs p) {
 // The epilogue combines the digit levels in FP64 exactly as gemm_i8 does; for a middle
 // mode it stages the 32 x 256 result tile in LDS, takes each row's maximum (a whole fiber
 // of the next product) and writes the row's digit planes and exponent in the chain layout,
-// the digits that slice_grid would produce for the same values.
+// the digits that slice_grid would produce for the same values. Its stores are
+// nontemporal: their reader is the next launch, and L2 is kept for the digits being read.
 // Workgroups are persistent (one per compute unit, each walking tiles of its XCD's range;
 // the eight factor-row tiles of a fiber group run side by side on one XCD and share its
 // digits in L2), and the last chunk of a tile already loads the next tile's first factor
@@ -481,7 +482,6 @@ __global__ __launch_bounds__(64 * (CF / WN), 1) void gemm_i8_chain(ChainArgs p) 
 
     // accumulator element e of lane l: factor row 8(e/4) + 4(l/32) + e%4, fiber l%32 of
     // the block; the factor-row exponents of four consecutive elements in one 16-byte read
-    const double alpha = p.alpha;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const i4 fq = *reinterpret_cast<const i4*>(&Fe[fe][8 * q + 4 * half]);
@@ -494,9 +494,10 @@ __global__ __launch_bounds__(64 * (CF / WN), 1) void gemm_i8_chain(ChainArgs p) 
           double x = (double)acc[b][S - 1][e];
 #pragma unroll
           for (int l = S - 2; l >= 0; --l) x = __builtin_fma(x, 0x1p-8, (double)acc[b][l][e]);
-          x = alpha * __builtin_ldexp(x, fq[e4] + ve[b] - 14);
+          x = __builtin_ldexp(x, fq[e4] + ve[b] - 14);
           if (!p.odig) {
-            if (m < M && j < F) p.out[(int64_t)v * p.ovs + ((int64_t)m * p.Gv + gi) * p.ldo + j] = x;
+            if (m < M && j < F)
+              __builtin_nontemporal_store(x, p.out + (int64_t)v * p.ovs + ((int64_t)m * p.Gv + gi) * p.ldo + j);
           } else {
             Cs[ml * CPD + cs_col(j)] = (m < M && j < F) ? x : 0.0;
           }
@@ -534,8 +535,9 @@ __global__ __launch_bounds__(64 * (CF / WN), 1) void gemm_i8_chain(ChainArgs p) 
           signed char* o = p.odig + digits::chain_offset(go, jn, 16 * sg, 0, nchq, S);
 #pragma unroll
           for (int s = 0; s < S; ++s)
-            *reinterpret_cast<i4*>(o + s * 2048) = i4{(int)pl[0][s], (int)pl[1][s], (int)pl[2][s], (int)pl[3][s]};
-          if (sg == 0) p.oexp[go * 256 + jn] = e;
+            __builtin_nontemporal_store(i4{(int)pl[0][s], (int)pl[1][s], (int)pl[2][s], (int)pl[3][s]},
+                                        reinterpret_cast<i4*>(o + s * 2048));
+          if (sg == 0) __builtin_nontemporal_store(e, p.oexp + go * 256 + jn);
         }
       }
     }
