@@ -26,6 +26,7 @@
 // accumulator per digit level.
 #include "mm_internal.h"
 #include "slice_digits.h"
+#include "wave_ops.h"
 
 #include <type_traits>
 
@@ -73,8 +74,7 @@ __global__ __launch_bounds__(TH) void slice_grid(GemmArgs p, int fblocks) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         if (k0 + i < K) mx = __builtin_fmax(mx, __builtin_fabs(vr[k0 + i]));
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) mx = __builtin_fmax(mx, __shfl_xor(mx, off));
+    mx = wave::wave_max(mx);
     const int e = row_exponent(mx);
     if (lane == 0) X[row] = e;
     signed char* __restrict__ dr = D + (int64_t)row * kp;
@@ -519,8 +519,7 @@ __global__ __launch_bounds__(64 * (CF / WN), 1) void gemm_i8_chain(ChainArgs p) 
           x[i] = Cs[r * CPD + cs_col(16 * sg) + i];
           mx = __builtin_fmax(mx, __builtin_fabs(x[i]));
         }
-#pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) mx = __builtin_fmax(mx, __shfl_xor(mx, off));
+        mx = wave::row16_max(mx);
         const int e = row_exponent(mx);
         const int m = m0 + r;
         if (m < M && 16 * sg < kq) {

@@ -15,6 +15,7 @@
 
 #include "mm_internal.h"
 #include "slice_digits.h"
+#include "wave_ops.h"
 
 namespace mm {
 
@@ -110,8 +111,7 @@ __device__ __forceinline__ void write_row_digits(const double (&v)[P], int cnt, 
 #pragma unroll
   for (int k = 0; k < P; ++k)
     if (k < cnt) m = fmax(m, fabs(v[k]));
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  m = wave::wave_max(m);
   const int e = digits::digit_exponent(m);
   // row layout: plane t at t dplane, row r at r kp; chain layout (slice_digits.h): fiber
   // r % n2 of group r / n2, the P values of a lane inside one 16-byte fragment, planes
@@ -216,8 +216,8 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
       const double* uc = uu[y][z];
       const double* ac = aa[y][z];
       // x1 neighbours across lanes (every lane takes part), then the segment ends
-      double ul = __shfl_up(uc[P - 1], 1), ur = __shfl_down(uc[0], 1);
-      double al = __shfl_up(ac[P - 1], 1), ar = __shfl_down(ac[0], 1);
+      double ul = wave::from_prev(uc[P - 1]), ur = wave::from_next(uc[0]);
+      double al = wave::from_prev(ac[P - 1]), ar = wave::from_next(ac[0]);
       if (edge) {
         const double ue = (useg && live_row && xe >= 0 && xe < n1) ? u[urow + xe] : 0.0;
         const double ae = (live_row && xe >= -1 && xe <= n1) ? a[arow + xe + 1] : 0.0;
@@ -336,7 +336,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
 // whether it ran alone or in a group (two instantiations of the body may contract
 // multiply-adds differently, which changes last bits).
 template <int D, int P, int S>
-__global__ __launch_bounds__(64 * SW) void stencil_batch_kernel(StencilBatch b, StencilGrid sg) {
+__global__ __launch_bounds__(64 * SW, 3) void stencil_batch_kernel(StencilBatch b, StencilGrid sg) {
   stencil_body<D, P, S>(b.a[blockIdx.y], sg);
 }
 
