@@ -482,24 +482,42 @@ __global__ __launch_bounds__(64 * (CF / WN), 1) void gemm_i8_chain(ChainArgs p) 
 
     // accumulator element e of lane l: factor row 8(e/4) + 4(l/32) + e%4, fiber l%32 of
     // the block; the factor-row exponents of four consecutive elements in one 16-byte read
+    auto value = [&](int b, int e, int ex) {
+      double x = (double)acc[b][S - 1][e];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const i4 fq = *reinterpret_cast<const i4*>(&Fe[fe][8 * q + 4 * half]);
+      for (int l = S - 2; l >= 0; --l) x = __builtin_fma(x, 0x1p-8, (double)acc[b][l][e]);
+      return __builtin_ldexp(x, ex - 14);
+    };
+    if (!p.odig) {
+      // FP64 rows m0 + 4 half + 8 q + e4 of output row block (v, gi): element offsets from
+      // the lane's first row by multiples of the row stride Gv ldo
+      const int64_t rs = (int64_t)p.Gv * p.ldo;
+      double* const ob = p.out + (int64_t)v * p.ovs + ((int64_t)(m0 + 4 * half) * p.Gv + gi) * p.ldo;
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int j = wave * WN + 32 * b + rl;
+      for (int q = 0; q < 4; ++q) {
+        const i4 fq = *reinterpret_cast<const i4*>(&Fe[fe][8 * q + 4 * half]);
 #pragma unroll
-        for (int e4 = 0; e4 < 4; ++e4) {
-          const int e = 4 * q + e4, ml = 8 * q + 4 * half + e4, m = m0 + ml;
-          double x = (double)acc[b][S - 1][e];
+        for (int b = 0; b < NB; ++b) {
+          const int j = wave * WN + 32 * b + rl;
 #pragma unroll
-          for (int l = S - 2; l >= 0; --l) x = __builtin_fma(x, 0x1p-8, (double)acc[b][l][e]);
-          x = __builtin_ldexp(x, fq[e4] + ve[b] - 14);
-          if (!p.odig) {
-            if (m < M && j < F)
-              __builtin_nontemporal_store(x, p.out + (int64_t)v * p.ovs + ((int64_t)m * p.Gv + gi) * p.ldo + j);
-          } else {
-            Cs[ml * CPD + cs_col(j)] = (m < M && j < F) ? x : 0.0;
+          for (int e4 = 0; e4 < 4; ++e4) {
+            const double x = value(b, 4 * q + e4, fq[e4] + ve[b]);
+            if (m0 + 4 * half + 8 * q + e4 < M && j < F) __builtin_nontemporal_store(x, ob + (8 * q + e4) * rs + j);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const i4 fq = *reinterpret_cast<const i4*>(&Fe[fe][8 * q + 4 * half]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int j = wave * WN + 32 * b + rl;
+#pragma unroll
+          for (int e4 = 0; e4 < 4; ++e4) {
+            const int ml = 8 * q + 4 * half + e4;
+            const double x = value(b, 4 * q + e4, fq[e4] + ve[b]);
+            Cs[ml * CPD + cs_col(j)] = (m0 + ml < M && j < F) ? x : 0.0;
           }
         }
       }
@@ -523,9 +541,10 @@ __global__ __launch_bounds__(64 * (CF / WN), 1) void gemm_i8_chain(ChainArgs p) 
         const int e = row_exponent(mx);
         const int m = m0 + r;
         if (m < M && 16 * sg < kq) {
-          // the next product's fiber: group go, fiber jn
-          const int64_t lin = ((int64_t)v * M + m) * p.Gv + gi;
-          const int64_t go = lin / p.Fn;
+          // the next product's fiber: group go, fiber jn (fewer than 2^31 fibers: checked
+          // at launch)
+          const unsigned lin = ((unsigned)v * M + m) * p.Gv + gi;
+          const unsigned go = lin / (unsigned)p.Fn;
           const int jn = (int)(lin - go * p.Fn);
           unsigned pl[4][S];
 #pragma unroll
@@ -536,7 +555,7 @@ __global__ __launch_bounds__(64 * (CF / WN), 1) void gemm_i8_chain(ChainArgs p) 
           for (int s = 0; s < S; ++s)
             __builtin_nontemporal_store(i4{(int)pl[0][s], (int)pl[1][s], (int)pl[2][s], (int)pl[3][s]},
                                         reinterpret_cast<i4*>(o + s * 2048));
-          if (sg == 0) __builtin_nontemporal_store(e, p.oexp + go * 256 + jn);
+          if (sg == 0) __builtin_nontemporal_store(e, p.oexp + (int64_t)go * 256 + jn);
         }
       }
     }
@@ -557,7 +576,7 @@ hipError_t launch_gemm_sliced_chain(ChainArgs& c, hipStream_t s) {
   if (gin * 256 * c.slices * slice_ld(c.K) > c.vcap || gin * 256 > c.vexp_cap) return hipErrorInvalidValue;
   if (c.odig) {
     const int64_t fibers = (int64_t)c.nvec * c.M * c.Gv;   // the next product's fibers
-    if (c.Fn < 1 || c.Fn > CF || fibers % c.Fn != 0) return hipErrorInvalidValue;
+    if (c.Fn < 1 || c.Fn > CF || fibers % c.Fn != 0 || fibers >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
     const int64_t gout = fibers / c.Fn;
     if (gout * 256 * c.slices * slice_ld(c.F) > c.ocap || gout * 256 > c.oexp_cap) return hipErrorInvalidValue;
   }
