@@ -25,7 +25,9 @@ namespace mm {
 // the neighbouring lanes by shuffles; only the two ends of the segment need a load
 // (lanes 0 and 63 together, one instruction per row). Each lane also keeps a YT (x2)
 // x ZT (x3) patch of such rows with a one-row halo in registers (no corners), so the
-// x2/x3 neighbours are loaded once per patch. The cost of this kernel is the number
+// x2/x3 neighbours are loaded once per patch: 1 x 2 in 3D, 2 x 1 in 2D, and 1 x 1 for the
+// 3D digit output, whose extra live values would otherwise cost a wave per SIMD (255^3:
+// 144 us per pass at four waves per SIMD against 159 at three with the 1 x 2 patch). The cost of this kernel is the number
 // of vector memory instructions per point more than its HBM bytes; this layout
 // needs about 3 per point plus the stage operands, against 12 for one point per lane.
 // Blocks are four waves stacked along x2 and are numbered x1 segment fastest, then x2,
@@ -149,7 +151,7 @@ __device__ __forceinline__ void write_row_digits(const double (&v)[P], int cnt, 
 template <int D, int P, int S>
 __device__ __forceinline__ void stencil_body(const StencilArgs& p, const StencilGrid& sg) {
   constexpr int YT = (D == 3) ? 1 : 2;   // rows per lane along x2
-  constexpr int ZT = (D == 3) ? 2 : 1;   // rows per lane along x3
+  constexpr int ZT = (D == 3 && S == 0) ? 2 : 1;   // rows per lane along x3
   constexpr int YH = YT + 2;             // with the x2 halo
   constexpr int ZH = (D == 3) ? ZT + 2 : 1;
   const int L = blockIdx.x;
@@ -382,11 +384,11 @@ static void launch_batch_d(int P, const StencilBatch& b, int count, StencilGrid 
 }
 
 // Work decomposition of one grid (blocks of four waves); false if it does not fit a grid.
-static bool stencil_grid(int d, int n1, int n2, int n3, int& P, StencilGrid& sg, int64_t& blocks) {
+static bool stencil_grid(int d, int n1, int n2, int n3, bool dig, int& P, StencilGrid& sg, int64_t& blocks) {
   if (n1 < 1 || n2 < 1 || n3 < 1) return false;
   P = points_per_lane(n1);
   sg.nxs = (n1 + 64 * P - 1) / (64 * P);
-  const int yt = (d == 3) ? 1 : 2, zt = (d == 3) ? 2 : 1;
+  const int yt = (d == 3) ? 1 : 2, zt = (d == 3 && !dig) ? 2 : 1;
   sg.nyb = (n2 + SW * yt - 1) / (SW * yt);
   sg.nzb = (d == 3) ? (n3 + zt - 1) / zt : 1;
   blocks = (int64_t)sg.nxs * sg.nyb * sg.nzb;
@@ -414,7 +416,7 @@ hipError_t launch_stencil_batch(int d, const StencilArgs* a, int count, hipStrea
   int P;
   StencilGrid sg;
   int64_t blocks;
-  if (!stencil_grid(d, a[0].n1, a[0].n2, a[0].n3, P, sg, blocks)) return hipErrorInvalidValue;
+  if (!stencil_grid(d, a[0].n1, a[0].n2, a[0].n3, a[0].dig != nullptr, P, sg, blocks)) return hipErrorInvalidValue;
   StencilBatch b;
   for (int i = 0; i < count; ++i) b.a[i] = a[i];
   if (d == 3)
