@@ -306,6 +306,16 @@ mm_status mm_set_small_fused(mm_ctx* ctx, int enable);
  * MM_EINVAL. */
 mm_status mm_set_sliced_chain(mm_ctx* ctx, int mode);
 
+/* FP64 mode products along axes whose extracted operator is a symmetric Toeplitz matrix
+ * (zero Dirichlet data at both ends, beta_bar_mu = 0, Sec. 2, eq. (eq:linop)): there
+ * every factor exp(c tau A_mu) is centrosymmetric (E_ij = E_{n-1-i,n-1-j}), so a product
+ * y = E x splits into the sums and differences of mirrored entries of x and two products
+ * with half-size factors, at half the multiply-adds; the results agree with the plain
+ * product to rounding. Applies to the exp actions of the Lawson and ERK steps and of
+ * mumode_expv (not to stacked quadrature factors). mode = 0: off; 1 (default): on for
+ * launches that fill the chip; 2: always. Other modes: MM_EINVAL. */
+mm_status mm_set_fold(mm_ctx* ctx, int mode);
+
 /* Step replay through HIP graphs (launch-bound small problems). steps = 0 (default):
  * lawson_step / erk_step launch their kernels one by one. steps = G > 0: a call with
  * nsteps >= G records G steps on that state buffer into a graph once (kept by the op and

@@ -53,7 +53,8 @@ EXPORTS = ("mm_ctx_create", "mm_ctx_destroy", "mm_last_error", "mm_version", "mu
            "mm_server_destroy", "solve_submit", "solve_poll", "mm_server_clock", "mm_timing_enable",
            "mm_timing_read", "mm_synchronize", "mm_set_gemm_tile",
            "mm_set_graph_steps", "mm_set_small_fused", "lawson_step_batch",
-           "mm_server_read_counters", "mumode_expv_noalloc", "mm_set_sliced_chain")
+           "mm_server_read_counters", "mumode_expv_noalloc", "mm_set_sliced_chain",
+           "mm_set_fold")
 MM_KIND_STENCIL, MM_KIND_GEMM_K, MM_KIND_GEMM_N, MM_KIND_FUSED = 0, 1, 2, 3
 
 
@@ -149,6 +150,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mm_set_graph_steps": (i, [vp, i]),
         "mm_set_small_fused": (i, [vp, i]),
         "mm_set_sliced_chain": (i, [vp, i]),
+        "mm_set_fold": (i, [vp, i]),
         "mm_timing_read": (i, [vp, i, POINTER(c_int64), POINTER(c_double), POINTER(c_double)]),
     }
     for name, (res, args) in sig.items():
@@ -267,6 +269,11 @@ class Context:
         """Chained exact-slice actions of Lawson steps: 0 off, 1 automatic (default; every
         axis longer than 128), 2 wherever possible, 3 as 2 with four-wave workgroups."""
         self.check(lib().mm_set_sliced_chain(self._h, int(mode)), "mm_set_sliced_chain")
+
+    def set_fold(self, mode: int):
+        """FP64 folded mode products on centrosymmetric axes: 0 off, 1 on for launches that
+        fill the chip (default), 2 always."""
+        self.check(lib().mm_set_fold(self._h, int(mode)), "mm_set_fold")
 
     def set_graph_steps(self, steps: int):
         """0: launch step kernels one by one; G > 0: replay recorded graphs of G steps."""

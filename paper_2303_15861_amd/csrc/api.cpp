@@ -389,6 +389,19 @@ const int* factor_exp(const mm_op* op, int mu, int j) {
   return op->fac_exp[mu] + (int64_t)j * op->n[mu];
 }
 
+// the folded form [Es; Ed] of exp factor j of axis mu (FP64 centrosymmetric axes), else
+// null; rows of n_mu - n_mu/2 values
+const double* folded(const mm_op* op, int mu, int j) {
+  if (op->prec != MM_FP64 || mu >= (int)op->ffold.size() || !op->ffold[mu] || j < 0 || j >= op->nfold) return nullptr;
+  const int64_t f = op->n[mu] - op->n[mu] / 2;
+  return op->ffold[mu] + (int64_t)j * 2 * f * f;
+}
+
+void set_fold(const mm_op* op, GemmArgs& g, int mu) {
+  g.ldf = op->n[mu] - op->n[mu] / 2;
+  g.fold = op->ctx ? op->ctx->fold : 1;
+}
+
 // the stacked last-axis factor of an ERK stage in the op's precision
 const void* stacked(const mm_op* op, int which) {
   if (op->prec == MM_FP64) return which == 1 ? op->f3_stage1 : which == 2 ? op->f3_stage2 : op->f3_phi;
@@ -419,6 +432,7 @@ hipError_t pass_mode1(const mm_op* op, int groups, const void* const* in, const 
   for (int i = 0; i < groups; ++i) {
     g.A[i] = in[i];
     g.B[i] = factor_op(op, 0, fidx[i]);
+    g.Ff[i] = folded(op, 0, fidx[i]);
     g.fexp[i] = factor_exp(op, 0, fidx[i]);
     g.galpha[i] = galpha ? galpha[i] : 0.0;
     g.C[i] = out[i];
@@ -440,6 +454,7 @@ hipError_t pass_mode1(const mm_op* op, int groups, const void* const* in, const 
   g.out_f32 = io.out_f32;
   g.fac_slice = factor_slice_stride(op, n1, n1);
   g.vready = io.ready;
+  set_fold(op, g, 0);
   return gemm(op, g, s);
 }
 
@@ -450,6 +465,7 @@ hipError_t pass_mode2(const mm_op* op, int groups, const int* fidx, const void* 
   GemmArgs g{};
   for (int i = 0; i < groups; ++i) {
     g.A[i] = factor_op(op, 1, fidx[i]);
+    g.Ff[i] = folded(op, 1, fidx[i]);
     g.fexp[i] = factor_exp(op, 1, fidx[i]);
     g.B[i] = in[i];
     g.C[i] = out[i];
@@ -473,6 +489,7 @@ hipError_t pass_mode2(const mm_op* op, int groups, const int* fidx, const void* 
   g.in_f32 = io.in_f32;
   g.out_f32 = io.out_f32;
   g.fac_slice = factor_slice_stride(op, op->n[1], op->n[1]);
+  set_fold(op, g, 1);
   return gemm(op, g, s);
 }
 
@@ -485,13 +502,15 @@ hipError_t pass_mode2(const mm_op* op, int groups, const int* fidx, const void* 
 // input and output layouts that differ take one launch per vector, batched over x2.
 hipError_t pass_last(const mm_op* op, const void* F, const int* Fexp, int kmul, const void* in, void* out,
                      const double* add, double alpha, double beta, int inner, PassIO io, hipStream_t s,
-                     Layout li = Layout{0, 0}, Layout lo = Layout{0, 0}) {
+                     Layout li = Layout{0, 0}, Layout lo = Layout{0, 0}, const double* Ffold = nullptr) {
   const int nl = op->n[last_axis(op)];
   const int P = (int)(op->dof / nl);
   if (li.ld && lo.ld && (li.ld != op->n[0] || lo.ld != op->n[0])) {
     const size_t ib = io.in_f32 ? 4 : 8, ob = io.out_f32 ? 4 : 8;
     GemmArgs g{};
     g.A[0] = F;
+    g.Ff[0] = kmul == 1 ? Ffold : nullptr;
+    set_fold(op, g, last_axis(op));
     g.fexp[0] = Fexp;
     g.slices = op->slices;
     g.Cadd[0] = nullptr;
@@ -538,6 +557,8 @@ hipError_t pass_last(const mm_op* op, const void* F, const int* Fexp, int kmul, 
   }
   GemmArgs g{};
   g.A[0] = F;
+  g.Ff[0] = kmul == 1 ? Ffold : nullptr;
+  set_fold(op, g, last_axis(op));
   g.fexp[0] = Fexp;
   g.slices = op->slices;
   g.B[0] = in;
@@ -590,12 +611,13 @@ hipError_t exp_action(const mm_op* op, int j, const void* in, bool in_f32, doubl
     void* o2[1] = {t1};
     e = pass_mode2(op, 1, fj, i2, o2, op->n[2] * nvec, mid, s, lt, lt);
     if (e != hipSuccess) return e;
-    return pass_last(op, Fl, Fe, 1, t1, out, add, alpha, add ? beta : 0.0, nvec, last_io, s, lt, lo);
+    return pass_last(op, Fl, Fe, 1, t1, out, add, alpha, add ? beta : 0.0, nvec, last_io, s, lt, lo,
+                     folded(op, la, j));
   }
   hipError_t e = pass_mode1(op, 1, i1, fj, o1, (int)(op->dof / op->n[0]) * nvec, first, s, nullptr, li, lt);
   if (e != hipSuccess) return e;
   PassIO l2{mixed, false};
-  return pass_last(op, Fl, Fe, 1, t0, out, add, alpha, add ? beta : 0.0, nvec, l2, s, lt, lo);
+  return pass_last(op, Fl, Fe, 1, t0, out, add, alpha, add ? beta : 0.0, nvec, l2, s, lt, lo, folded(op, la, j));
 }
 
 // out = stacked-last-factor contraction over G groups: group g applies modes 1..d-1 with
@@ -988,6 +1010,8 @@ void mumode_destroy(mm_op* op) {
   dev_free(op, op->a);
   for (size_t i = 0; i < op->fac.size(); ++i)
     if (op->fac_owned[i]) dev_free(op, op->fac[i]);
+  for (size_t i = 0; i < op->ffold.size(); ++i)
+    if (op->ffold_owned[i]) dev_free(op, op->ffold[i]);
   dev_free(op, op->f3_stage1);
   dev_free(op, op->f3_stage2);
   dev_free(op, op->f3_phi);
@@ -1449,6 +1473,29 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
       for (int j = 0; j < nf; ++j)
         HIPCHK(ctx, convert(dst + j * per, prec == MM_SLICED ? op->fac_exp[mu] + j * n : nullptr,
                             op->fac[mu] + (int64_t)j * n * n, n, n, n));
+    }
+  }
+
+  // FP64 axes whose operator is a symmetric Toeplitz matrix (zero Dirichlet data at both
+  // ends, no advection moved into A): every exp(c tau A_mu) is centrosymmetric, and the
+  // mode products of the exp actions can run folded, at half the multiply-adds
+  op->ffold.assign(op->d, nullptr);
+  op->ffold_owned.assign(op->d, false);
+  op->nfold = nf;
+  if (prec == MM_FP64 && !periodic) {
+    for (int mu = 0; mu < op->d; ++mu) {
+      if (op->bc[mu] != MM_BC_DIRICHLET || op->beta_bar[mu] != 0.0) continue;
+      int same = -1;
+      for (int nu = 0; nu < mu; ++nu)
+        if (op->fac[nu] == op->fac[mu] && op->ffold[nu]) same = nu;
+      if (same >= 0) {
+        op->ffold[mu] = op->ffold[same];
+        continue;
+      }
+      const int n = op->n[mu], f = n - n / 2;
+      if ((rc = dev_alloc(op, &op->ffold[mu], (int64_t)nf * 2 * f * f)) != MM_OK) return fail(rc);
+      op->ffold_owned[mu] = true;
+      HIPCHK(ctx, launch_fold_factor(op->ffold[mu], op->fac[mu], n, nf, st));
     }
   }
 
@@ -2359,6 +2406,16 @@ mm_status mm_set_sliced_chain(mm_ctx* ctx, int mode) {
     return MM_EINVAL;
   }
   ctx->sliced_chain = mode;
+  return MM_OK;
+}
+
+mm_status mm_set_fold(mm_ctx* ctx, int mode) {
+  if (!ctx) return MM_EINVAL;
+  if (mode < 0 || mode > 2) {
+    set_err(ctx, "fold mode must be 0, 1 or 2");
+    return MM_EINVAL;
+  }
+  ctx->fold = mode;
   return MM_OK;
 }
 

@@ -26,6 +26,7 @@
 // written as FP32 (intermediate passes) or FP64 (last pass of an action).
 #include "mm_internal.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace mm {
@@ -218,6 +219,216 @@ __global__ __launch_bounds__(64 * f64_waves<T>(), 4) void gemm_f64(GemmArgs p) {
         const int n = n0 + wn + 16 * j + lr;
         if (m < M && n < N) store_out<double>(C, Cadd, m * p.ldc + n, alpha * acc[i][j][t], beta);
       }
+}
+
+// ------------------------------------------------------------------------------------
+// FP64 mode products with a centrosymmetric factor (E = J E J with J the exchange matrix:
+// exp(c tau A) of a symmetric Toeplitz A, i.e. Dirichlet ends and no advection in A).
+// Along the contracted axis of n points (m = n/2 mirror pairs, f = n - m folded positions)
+// a fiber x gives s_r = x_r + x_{n-1-r} and d_r = x_r - x_{n-1-r} for r < m (odd n: s_m =
+// x_m, d_m = 0), and y = E x follows from the two f x f products a = Es s and b = Ed d:
+// y_i = a_i + b_i and y_{n-1-i} = a_i - b_i (i < m; launch_fold_factor defines Es and
+// Ed). This is half the multiply-adds of the plain product. A workgroup covers 128 grid
+// rows (mode 1) or columns (modes 2/3) against 64 folded positions of both halves, with
+// eight waves; k runs in chunks of 8 (two MFMA steps: lane group g supplies k = 2g + s at
+// step s, in both operands) through double-buffered LDS tiles: the factor rows [Es; Ed]
+// as [row][k], the grid's s and d tiles as [row][k] (mode 1) or [k][n] (modes 2/3).
+// Each wave accumulates the Es and the Ed products of the same outputs, so the epilogue
+// combines a and b in registers and writes both mirror rows (or columns).
+// ------------------------------------------------------------------------------------
+constexpr int KF = 8;          // folded k per chunk
+constexpr int PF = KF + 2;     // [row][k] pitch in doubles (80 B: 16-byte aligned rows)
+constexpr int PFN = 128 + 4;   // [k][n] pitch of the modes-2/3 grid tiles
+
+template <int BT>
+__global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
+  const int L = blockIdx.x;
+  const int P = (L & 7) * p.per_xcd + (L >> 3);
+  if (P >= p.total) return;
+  const int tiles = p.tiles_m * p.tiles_n;
+  const int gb = P / tiles, t = P - gb * tiles;
+  const int g = gb / p.inner, b = gb - g * p.inner;
+  int tm, tn;
+  if (BT) {   // neighbouring ids share the grid tile
+    tm = t % p.tiles_m;
+    tn = t / p.tiles_m;
+  } else {
+    tn = t % p.tiles_n;
+    tm = t / p.tiles_n;
+  }
+  const int n = p.K, m = n >> 1, f = n - m;
+  // BT: rows are folded positions (64 per tile), columns grid columns (128);
+  // !BT: rows are grid rows (128), columns folded positions (64)
+  const int r0 = tm * (BT ? 64 : 128), c0 = tn * (BT ? 128 : 64);
+  const int fo = BT ? r0 : c0;   // first folded position of the tile
+  const double* __restrict__ X = (const double*)(BT ? p.B[g] : p.A[g]) + b * (BT ? p.sB : p.sA);
+  const double* __restrict__ Fq = p.Ff[g];
+  double* __restrict__ C = (double*)p.C[g] + b * p.sC;
+  const double* __restrict__ Cadd = p.Cadd[g] ? p.Cadd[g] + b * p.sC : nullptr;
+  const int M = p.M, N = p.N, ldx = BT ? p.ldb : p.lda, ldf = p.ldf;
+
+  __shared__ __attribute__((aligned(16))) double Fs[2][128 * PF];
+  __shared__ __attribute__((aligned(16))) double Gs[2][2][BT ? KF * PFN : 128 * PF];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int lg = lane >> 4, lr = lane & 15;
+
+  d4 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  // chunk staging, two elements of each kind per thread: element e = 512 i + tid.
+  // Factor: row e/8 of the tile's [Es; Ed] rows (rows past f clamped: they feed masked
+  // outputs), k = e%8. Grid pairs: mode 1 row e/8, k = e%8; modes 2/3 k = e/128,
+  // column e%128 (columns past N clamped).
+  double rf[2], rs[2], rd[2];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int e = 512 * i + tid;
+      const int fr = e >> 3, kf = e & 7;
+      const int frow = min(fo + (fr & 63), f - 1) + (fr >> 6) * f;
+      const int r = k0 + kf;
+      rf[i] = r < f ? Fq[frow * ldf + r] : 0.0;
+      const int kk = BT ? (e >> 7) : kf;
+      const int rr = k0 + kk;
+      const int rc = min(rr, f - 1);   // mirror partner n-1-rc >= rc, both inside the axis
+      double v1, v2;
+      if (BT) {
+        const int col = min(c0 + (e & 127), N - 1);
+        v1 = X[rc * ldx + col];
+        v2 = X[(n - 1 - rc) * ldx + col];
+      } else {
+        const int row = min(r0 + (e >> 3), M - 1);
+        v1 = X[row * ldx + rc];
+        v2 = X[row * ldx + n - 1 - rc];
+      }
+      rs[i] = rr < m ? v1 + v2 : rr < f ? v1 : 0.0;
+      rd[i] = rr < m ? v1 - v2 : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int e = 512 * i + tid;
+      Fs[buf][(e >> 3) * PF + (e & 7)] = rf[i];
+      const int gi = BT ? (e >> 7) * PFN + (e & 127) : (e >> 3) * PF + (e & 7);
+      Gs[buf][0][gi] = rs[i];
+      Gs[buf][1][gi] = rd[i];
+    }
+  };
+
+  const int nch = (f + KF - 1) / KF;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int cur = c & 1;
+    if (c + 1 < nch) load((c + 1) * KF);
+    const double* fs = Fs[cur];
+    const double* gs = Gs[cur][0];
+    const double* gd = Gs[cur][1];
+    if (BT) {
+      // wave: folded rows 16 wr + [0, 16) of Es and of Ed, columns 64 wc + [0, 64)
+      const d2 as = *reinterpret_cast<const d2*>(fs + (16 * wr + lr) * PF + 2 * lg);
+      const d2 ad = *reinterpret_cast<const d2*>(fs + (64 + 16 * wr + lr) * PF + 2 * lg);
+      d2 bs[4], bd[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = 64 * wc + 16 * j + lr;
+        bs[j] = d2{gs[(2 * lg) * PFN + col], gs[(2 * lg + 1) * PFN + col]};
+        bd[j] = d2{gd[(2 * lg) * PFN + col], gd[(2 * lg + 1) * PFN + col]};
+      }
+#pragma unroll
+      for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[0][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[st], bs[j][st], acc[0][j], 0, 0, 0);
+          acc[1][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[st], bd[j][st], acc[1][j], 0, 0, 0);
+        }
+    } else {
+      // wave: grid rows 32 wr + [0, 32), folded columns 32 wc + [0, 32) of Es (j = 0, 1)
+      // and of Ed (j = 2, 3)
+      d2 as[2], ad[2], bf[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        as[i] = *reinterpret_cast<const d2*>(gs + (32 * wr + 16 * i + lr) * PF + 2 * lg);
+        ad[i] = *reinterpret_cast<const d2*>(gd + (32 * wr + 16 * i + lr) * PF + 2 * lg);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        bf[j] = *reinterpret_cast<const d2*>(fs + ((j >> 1) * 64 + 32 * wc + 16 * (j & 1) + lr) * PF + 2 * lg);
+#pragma unroll
+      for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(j < 2 ? as[i][st] : ad[i][st], bf[j][st], acc[i][j], 0,
+                                                             0, 0);
+    }
+    if (c + 1 < nch) store(cur ^ 1);
+    __syncthreads();
+  }
+  // f64 16x16 layout: lane l, element t holds row 4t + l/16, column l%16
+  const double alpha = p.alpha, beta = p.beta;
+  auto put = [&](int row, int col, double v) {
+    const int idx = row * p.ldc + col;
+    if (Cadd) v += beta * Cadd[idx];
+    C[idx] = v;
+  };
+#pragma unroll
+  for (int t4 = 0; t4 < 4; ++t4) {
+    if (BT) {
+      const int fr = r0 + 16 * wr + 4 * t4 + lg;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = c0 + 64 * wc + 16 * j + lr;
+        if (fr < f && col < N) {
+          const double a = acc[0][j][t4], bb = acc[1][j][t4];
+          put(fr, col, alpha * (a + bb));
+          if (fr < m) put(n - 1 - fr, col, alpha * (a - bb));
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int row = r0 + 32 * wr + 16 * i + 4 * t4 + lg;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int fc = c0 + 32 * wc + 16 * j + lr;
+          if (row < M && fc < f) {
+            const double a = acc[i][j][t4], bb = acc[i][j + 2][t4];
+            put(row, fc, alpha * (a + bb));
+            if (fc < m) put(row, n - 1 - fc, alpha * (a - bb));
+          }
+        }
+      }
+    }
+  }
+}
+
+__global__ void fold_factor(double* __restrict__ Ff, const double* __restrict__ E, int n) {
+  const int m = n >> 1, f = n - m;
+  const int64_t q = (int64_t)blockIdx.y;
+  const double* Eq = E + q * n * n;
+  double* Fq = Ff + q * 2 * f * f;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < f * f; e += gridDim.x * blockDim.x) {
+    const int i = e / f, r = e - i * f;
+    const double x = Eq[i * n + r], y = Eq[i * n + n - 1 - r];
+    Fq[i * f + r] = r < m ? 0.5 * (x + y) : x;
+    Fq[(f + i) * f + r] = r < m ? 0.5 * (x - y) : 0.0;
+  }
+}
+
+hipError_t launch_fold_factor(double* Ff, const double* E, int n, int count, hipStream_t s) {
+  if (!Ff || !E || n < 1 || count < 1 || count > 65535) return hipErrorInvalidValue;
+  const int f = n - n / 2;
+  const int blocks = std::min(1024, (f * f + 255) / 256);
+  fold_factor<<<dim3(blocks, count), dim3(256), 0, s>>>(Ff, E, n);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------
@@ -610,9 +821,41 @@ int choose_tile(const GemmArgs& g, int prec) {
   return prec == MM_FP64 && t64 < kComputeUnits ? 32 : 64;
 }
 
+// Folded FP64 launch: 128 x 64 tiles (grid x folded positions).
+hipError_t launch_fold(GemmArgs& g, hipStream_t s) {
+  const int f = g.K - g.K / 2;
+  g.tiles_m = g.b_trans ? (f + 63) / 64 : (g.M + 127) / 128;
+  g.tiles_n = g.b_trans ? (g.N + 127) / 128 : (f + 63) / 64;
+  const int64_t total = (int64_t)g.tiles_m * g.tiles_n * g.inner * g.groups;
+  if (total >= ((int64_t)1 << 28)) return hipErrorInvalidValue;
+  g.total = (int)total;
+  g.per_xcd = (g.total + 7) / 8;
+  const dim3 grid(8 * g.per_xcd), block(512);
+  if (g.b_trans)
+    gemm_f64_fold<1><<<grid, block, 0, s>>>(g);
+  else
+    gemm_f64_fold<0><<<grid, block, 0, s>>>(g);
+  return hipGetLastError();
+}
+
+// Whether g runs folded: FP64, every group with a folded factor, a square factor, and
+// (fold = 1) enough 128 x 64 tiles to give every workgroup slot of the chip one.
+bool use_fold(const GemmArgs& g, int prec) {
+  if (prec != MM_FP64 || g.fold == 0 || g.in_f32 || g.out_f32) return false;
+  if ((g.b_trans ? g.M : g.N) != g.K) return false;
+  for (int i = 0; i < g.groups; ++i)
+    if (!g.Ff[i]) return false;
+  if (g.fold == 2) return true;
+  const int f = g.K - g.K / 2;
+  const int64_t tiles = (int64_t)(g.b_trans ? (f + 63) / 64 * ((g.N + 127) / 128) : (g.M + 127) / 128 * ((f + 63) / 64)) *
+                        g.inner * g.groups;
+  return tiles >= kFillSlots;
+}
+
 hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.inner <= 0 || g.groups <= 0 || g.groups > kMaxGroups)
     return hipErrorInvalidValue;
+  if (g.fold < 0 || g.fold > 2) return hipErrorInvalidValue;
   if (g.tile != 0 && g.tile != 32 && g.tile != 64 && g.tile != 128) return hipErrorInvalidValue;
   if (prec == MM_SLICED && (g.in_f32 || g.out_f32)) return hipErrorInvalidValue;
   // in-batch offsets are 32-bit
@@ -629,6 +872,11 @@ hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s) {
     for (int i = 0; i < g.groups; ++i)
       if (!g.fexp[i]) return hipErrorInvalidValue;
     return launch_gemm_sliced(g, s);
+  }
+  if (use_fold(g, prec)) {
+    const int f = g.K - g.K / 2;
+    if (g.ldf < f || (int64_t)2 * f * g.ldf >= lim) return hipErrorInvalidValue;
+    return launch_fold(g, s);
   }
   if (prec != MM_FP64) {
     // the pre-converted factor must have its padded row stride

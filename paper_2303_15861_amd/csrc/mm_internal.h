@@ -50,6 +50,12 @@ struct GemmArgs {
   int* vexp;
   int64_t vdig_cap, vexp_cap;
   int vready;
+  // FP64 with a centrosymmetric factor (every group's factor E = J E J): Ff[g] is the
+  // folded factor [Es; Ed] of fold_factor (2f rows of f = K - K/2 values, row stride
+  // ldf); fold: 0 plain product, 1 folded when the launch fills the chip, 2 folded always
+  const double* Ff[kMaxGroups];
+  int ldf;
+  int fold;
   // filled by the launcher
   int tiles_m, tiles_n, total, per_xcd;
 };
@@ -148,6 +154,11 @@ struct SmallBatch {
 hipError_t launch_lawson_small2d_batch(const SmallArgs* a, int count, bool l2b, hipStream_t s);
 
 hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s);
+// Folded factor of a centrosymmetric n x n matrix E (row-major, row stride n) into Ff:
+// rows 0..f-1 Es, rows f..2f-1 Ed, each of f = n - n/2 values (row stride f), with
+// m = n/2: Es_ir = (E_ir + E_i,n-1-r)/2 and Ed_ir = (E_ir - E_i,n-1-r)/2 for r < m, and for
+// odd n Es_im = E_im, Ed_im = 0. `count` matrices n^2 apart in E, 2 f^2 apart in Ff.
+hipError_t launch_fold_factor(double* Ff, const double* E, int n, int count, hipStream_t s);
 // Tile size the launcher takes for g in precision prec (g.tile if set, else 64 when
 // 128-tiles would not fill the chip once, and in FP64 32 when 64-tiles would not give
 // every compute unit one).
@@ -285,6 +296,7 @@ struct mm_ctx {
   int graph_steps = 0;            // >0: step calls replay captured graphs of this many steps
   bool small_fused = true;        // small 2D Lawson solves as one-workgroup kernels
   int sliced_chain = 1;           // MM_SLICED chained actions (mm_set_sliced_chain)
+  int fold = 1;                   // FP64 folded mode products (mm_set_fold)
   hipStream_t capture = nullptr;  // private stream used only to record graphs
   std::vector<mm_timed> timed;
   size_t timed_used = 0;
@@ -321,6 +333,11 @@ struct mm_op {
   double* a = nullptr;                 // nodal coefficient copy
   std::vector<double*> fac;            // fac[mu] = (1 + q) stacked n_mu x n_mu FP64 factors
   std::vector<bool> fac_owned;
+  // FP64 centrosymmetric axes: the first nfold factors of fac[mu] folded ([Es; Ed], rows of
+  // f = n_mu - n_mu/2, 2 f^2 values each; launch_fold_factor), null on other axes
+  std::vector<double*> ffold;
+  std::vector<bool> ffold_owned;
+  int nfold = 0;
   double* f3_stage1 = nullptr;         // ERK: [E3(1) | tau w_j E3(theta_j)] or [tau w_j E3]
   double* f3_stage2 = nullptr;         // ERK: [tau/2 w_j E3(theta_j)]
   double* f3_phi = nullptr;            // [w_j E3(theta_j)] for mumode_phi1v

@@ -115,6 +115,7 @@ def test_entry_points_reject_null_handles_before_any_device_call():
     assert lib.mm_set_graph_steps(None, 1) == EINVAL
     assert lib.mm_set_small_fused(None, 1) == EINVAL
     assert lib.mm_set_sliced_chain(None, 1) == EINVAL
+    assert lib.mm_set_fold(None, 1) == EINVAL
     assert lib.mm_timing_read(None, 0, None, None, None) == EINVAL
     lib.mumode_destroy(None)
     srv = ctypes.c_void_p(123)
