@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--tile", type=int, default=0, help="force the mode-product workgroup tile (64 or 128)")
     ap.add_argument("--sliced-chain", type=int, default=1,
                     help="chained exact-slice actions: 0 off, 1 automatic, 2 always, 3 four-wave workgroups")
+    ap.add_argument("--fold", type=int, default=1,
+                    help="FP64 folded mode products on centrosymmetric axes: 0 off, 1 automatic, 2 always")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-at-T", action="store_true", help="skip the untimed runs to T")
@@ -236,6 +238,14 @@ def roofline(kern, prec, p):
     else:
         roof = {"bound": "mfma", "achieved": k["work"] / secs / 1e12, "peak": PEAK[prec] / 1e12,
                 "unit": "TFLOP/s"}
+        if prec == "fp64" and p.scheme in ("le", "l2b") and kname in ("gemm_k", "gemm_n"):
+            # folded products (centrosymmetric factors) execute about half the FP64 work of
+            # the plain product 2 n_mu dof per vector; the library reports the executed work
+            nmu = p.n[0] if kname == "gemm_k" else p.n[-1]
+            plain = k["launches"] * 2.0 * nmu * float(np.prod(p.n)) * (2 if p.scheme == "l2b" else 1)
+            if k["work"] < 0.75 * plain:
+                roof["folded"] = True
+                roof["plain_equivalent_tflops"] = plain / secs / 1e12
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = {"gemm_k": "gemm (mode 1)", "gemm_n": "gemm (modes 2, 3)", "stencil": "stencil",
                       "fused": "whole small-2D solve in one workgroup (one compute unit)"}[kname]
@@ -438,6 +448,7 @@ def main():
     ctx.set_graph_steps(args.graph_steps)
     ctx.set_gemm_tile(args.tile)
     ctx.set_sliced_chain(args.sliced_chain)
+    ctx.set_fold(args.fold)
     modes = [m for m in args.modes.split(",") if m]
     if "fp64" not in modes:
         modes = ["fp64"] + modes
@@ -510,7 +521,7 @@ def main():
         "config": {"workload": DESCRIPTION.get(args.workload, args.workload),
                    "dof": p.dof, "scheme": p.scheme, "headline_mode": args.headline,
                    "graph_steps": args.graph_steps, "tile": args.tile or "auto",
-                   "sliced_chain": args.sliced_chain,
+                   "sliced_chain": args.sliced_chain, "fold": args.fold,
                    "warmup_min_seconds": WARMUP_MIN_S},
         "latency": head.get("latency"),
         "modes": {m: {kk: vv for kk, vv in e.items() if kk != "kernels"} for m, e in res.items()},

@@ -228,7 +228,13 @@ hipError_t timed_launch(mm_ctx* ctx, int kind, double work, hipStream_t s, F&& l
 }
 
 hipError_t gemm(const mm_op* op, GemmArgs& g, hipStream_t s) {
-  const double work = 2.0 * g.M * (double)g.N * g.K * g.inner * g.groups;
+  // floating-point operations of the launch: 2 M N K, or for a folded product the two
+  // half-size products (2 f x f factors against the grid's other dimension)
+  double work = 2.0 * g.M * (double)g.N * g.K * g.inner * g.groups;
+  if (use_fold(g, op->prec)) {
+    const double f = g.K - g.K / 2;
+    work = 4.0 * f * f * (g.b_trans ? (double)g.N : (double)g.M) * g.inner * g.groups;
+  }
   g.tile = op->ctx ? op->ctx->gemm_tile : 0;
   g.vdig = op->vdig;
   g.vexp = op->vexp;

@@ -236,12 +236,15 @@ __global__ __launch_bounds__(64 * f64_waves<T>(), 4) void gemm_f64(GemmArgs p) {
 // Each wave accumulates the Es and the Ed products of the same outputs, so the epilogue
 // combines a and b in registers and writes both mirror rows (or columns).
 // ------------------------------------------------------------------------------------
-constexpr int KF = 8;          // folded k per chunk
-constexpr int PF = KF + 2;     // [row][k] pitch in doubles (80 B: 16-byte aligned rows)
 constexpr int PFN = 128 + 4;   // [k][n] pitch of the modes-2/3 grid tiles
 
-template <int BT>
-__global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
+// KC: folded k per chunk (8: two workgroups per compute unit; 16: one, twice the MFMA
+// work per barrier)
+template <int BT, int KC>
+__global__ __launch_bounds__(512, KC == 8 ? 4 : 2) void gemm_f64_fold(GemmArgs p) {
+  constexpr int PF = KC + 2;   // [row][k] pitch in doubles (16-byte aligned rows)
+  constexpr int NE = KC / 4;   // staged elements of each kind per thread and chunk
+  constexpr int LK = KC == 8 ? 3 : 4;
   const int L = blockIdx.x;
   const int P = (L & 7) * p.per_xcd + (L >> 3);
   if (P >= p.total) return;
@@ -268,7 +271,7 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
   const int M = p.M, N = p.N, ldx = BT ? p.ldb : p.lda, ldf = p.ldf;
 
   __shared__ __attribute__((aligned(16))) double Fs[2][128 * PF];
-  __shared__ __attribute__((aligned(16))) double Gs[2][2][BT ? KF * PFN : 128 * PF];
+  __shared__ __attribute__((aligned(16))) double Gs[2][2][BT ? KC * PFN : 128 * PF];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int lg = lane >> 4, lr = lane & 15;
@@ -279,16 +282,16 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  // chunk staging, two elements of each kind per thread: element e = 512 i + tid.
-  // Factor: row e/8 of the tile's [Es; Ed] rows (rows past f clamped: they feed masked
-  // outputs), k = e%8. Grid pairs: mode 1 row e/8, k = e%8; modes 2/3 k = e/128,
+  // chunk staging, NE elements of each kind per thread: element e = 512 i + tid.
+  // Factor: row e/KC of the tile's [Es; Ed] rows (rows past f clamped: they feed masked
+  // outputs), k = e%KC. Grid pairs: mode 1 row e/KC, k = e%KC; modes 2/3 k = e/128,
   // column e%128 (columns past N clamped).
-  double rf[2], rs[2], rd[2];
+  double rf[NE], rs[NE], rd[NE];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < NE; ++i) {
       const int e = 512 * i + tid;
-      const int fr = e >> 3, kf = e & 7;
+      const int fr = e >> LK, kf = e & (KC - 1);
       const int frow = min(fo + (fr & 63), f - 1) + (fr >> 6) * f;
       const int r = k0 + kf;
       rf[i] = r < f ? Fq[frow * ldf + r] : 0.0;
@@ -301,7 +304,7 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
         v1 = X[rc * ldx + col];
         v2 = X[(n - 1 - rc) * ldx + col];
       } else {
-        const int row = min(r0 + (e >> 3), M - 1);
+        const int row = min(r0 + (e >> LK), M - 1);
         v1 = X[row * ldx + rc];
         v2 = X[row * ldx + n - 1 - rc];
       }
@@ -311,63 +314,67 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < NE; ++i) {
       const int e = 512 * i + tid;
-      Fs[buf][(e >> 3) * PF + (e & 7)] = rf[i];
-      const int gi = BT ? (e >> 7) * PFN + (e & 127) : (e >> 3) * PF + (e & 7);
+      Fs[buf][(e >> LK) * PF + (e & (KC - 1))] = rf[i];
+      const int gi = BT ? (e >> 7) * PFN + (e & 127) : (e >> LK) * PF + (e & (KC - 1));
       Gs[buf][0][gi] = rs[i];
       Gs[buf][1][gi] = rd[i];
     }
   };
 
-  const int nch = (f + KF - 1) / KF;
+  const int nch = (f + KC - 1) / KC;
   load(0);
   store(0);
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     const int cur = c & 1;
-    if (c + 1 < nch) load((c + 1) * KF);
+    if (c + 1 < nch) load((c + 1) * KC);
     const double* fs = Fs[cur];
     const double* gs = Gs[cur][0];
     const double* gd = Gs[cur][1];
-    if (BT) {
-      // wave: folded rows 16 wr + [0, 16) of Es and of Ed, columns 64 wc + [0, 64)
-      const d2 as = *reinterpret_cast<const d2*>(fs + (16 * wr + lr) * PF + 2 * lg);
-      const d2 ad = *reinterpret_cast<const d2*>(fs + (64 + 16 * wr + lr) * PF + 2 * lg);
-      d2 bs[4], bd[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int col = 64 * wc + 16 * j + lr;
-        bs[j] = d2{gs[(2 * lg) * PFN + col], gs[(2 * lg + 1) * PFN + col]};
-        bd[j] = d2{gd[(2 * lg) * PFN + col], gd[(2 * lg + 1) * PFN + col]};
-      }
-#pragma unroll
-      for (int st = 0; st < 2; ++st)
+    for (int h = 0; h < KC / 8; ++h) {   // k = (KC/4) g + 2 h + s at MFMA step (h, s)
+      const int kb = (KC / 4) * lg + 2 * h;
+      if (BT) {
+        // wave: folded rows 16 wr + [0, 16) of Es and of Ed, columns 64 wc + [0, 64)
+        const d2 as = *reinterpret_cast<const d2*>(fs + (16 * wr + lr) * PF + kb);
+        const d2 ad = *reinterpret_cast<const d2*>(fs + (64 + 16 * wr + lr) * PF + kb);
+        d2 bs[4], bd[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          acc[0][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[st], bs[j][st], acc[0][j], 0, 0, 0);
-          acc[1][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[st], bd[j][st], acc[1][j], 0, 0, 0);
+          const int col = 64 * wc + 16 * j + lr;
+          bs[j] = d2{gs[kb * PFN + col], gs[(kb + 1) * PFN + col]};
+          bd[j] = d2{gd[kb * PFN + col], gd[(kb + 1) * PFN + col]};
         }
-    } else {
-      // wave: grid rows 32 wr + [0, 32), folded columns 32 wc + [0, 32) of Es (j = 0, 1)
-      // and of Ed (j = 2, 3)
-      d2 as[2], ad[2], bf[4];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        as[i] = *reinterpret_cast<const d2*>(gs + (32 * wr + 16 * i + lr) * PF + 2 * lg);
-        ad[i] = *reinterpret_cast<const d2*>(gd + (32 * wr + 16 * i + lr) * PF + 2 * lg);
+        for (int st = 0; st < 2; ++st)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            acc[0][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[st], bs[j][st], acc[0][j], 0, 0, 0);
+            acc[1][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[st], bd[j][st], acc[1][j], 0, 0, 0);
+          }
+      } else {
+        // wave: grid rows 32 wr + [0, 32), folded columns 32 wc + [0, 32) of Es (j = 0, 1)
+        // and of Ed (j = 2, 3)
+        d2 as[2], ad[2], bf[4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          as[i] = *reinterpret_cast<const d2*>(gs + (32 * wr + 16 * i + lr) * PF + kb);
+          ad[i] = *reinterpret_cast<const d2*>(gd + (32 * wr + 16 * i + lr) * PF + kb);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          bf[j] = *reinterpret_cast<const d2*>(fs + ((j >> 1) * 64 + 32 * wc + 16 * (j & 1) + lr) * PF + kb);
+#pragma unroll
+        for (int st = 0; st < 2; ++st)
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(j < 2 ? as[i][st] : ad[i][st], bf[j][st], acc[i][j], 0,
+                                                               0, 0);
       }
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        bf[j] = *reinterpret_cast<const d2*>(fs + ((j >> 1) * 64 + 32 * wc + 16 * (j & 1) + lr) * PF + 2 * lg);
-#pragma unroll
-      for (int st = 0; st < 2; ++st)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(j < 2 ? as[i][st] : ad[i][st], bf[j][st], acc[i][j], 0,
-                                                             0, 0);
     }
     if (c + 1 < nch) store(cur ^ 1);
     __syncthreads();
@@ -822,6 +829,7 @@ int choose_tile(const GemmArgs& g, int prec) {
 }
 
 // Folded FP64 launch: 128 x 64 tiles (grid x folded positions).
+constexpr int kFoldChunk = 8;
 hipError_t launch_fold(GemmArgs& g, hipStream_t s) {
   const int f = g.K - g.K / 2;
   g.tiles_m = g.b_trans ? (f + 63) / 64 : (g.M + 127) / 128;
@@ -832,9 +840,9 @@ hipError_t launch_fold(GemmArgs& g, hipStream_t s) {
   g.per_xcd = (g.total + 7) / 8;
   const dim3 grid(8 * g.per_xcd), block(512);
   if (g.b_trans)
-    gemm_f64_fold<1><<<grid, block, 0, s>>>(g);
+    gemm_f64_fold<1, kFoldChunk><<<grid, block, 0, s>>>(g);
   else
-    gemm_f64_fold<0><<<grid, block, 0, s>>>(g);
+    gemm_f64_fold<0, kFoldChunk><<<grid, block, 0, s>>>(g);
   return hipGetLastError();
 }
 

@@ -159,6 +159,9 @@ hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s);
 // m = n/2: Es_ir = (E_ir + E_i,n-1-r)/2 and Ed_ir = (E_ir - E_i,n-1-r)/2 for r < m, and for
 // odd n Es_im = E_im, Ed_im = 0. `count` matrices n^2 apart in E, 2 f^2 apart in Ff.
 hipError_t launch_fold_factor(double* Ff, const double* E, int n, int count, hipStream_t s);
+// Whether launch_gemm runs g as a folded product (FP64, a folded factor for every group,
+// a square factor, and fold = 2 or enough tiles to fill the chip).
+bool use_fold(const GemmArgs& g, int prec);
 // Tile size the launcher takes for g in precision prec (g.tile if set, else 64 when
 // 128-tiles would not fill the chip once, and in FP64 32 when 64-tiles would not give
 // every compute unit one).
