@@ -227,14 +227,18 @@ hipError_t timed_launch(mm_ctx* ctx, int kind, double work, hipStream_t s, F&& l
   return hipEventRecord(t.stop, s);
 }
 
-hipError_t gemm(const mm_op* op, GemmArgs& g, hipStream_t s) {
-  // floating-point operations of the launch: 2 M N K, or for a folded product the two
-  // half-size products (2 f x f factors against the grid's other dimension)
-  double work = 2.0 * g.M * (double)g.N * g.K * g.inner * g.groups;
-  if (use_fold(g, op->prec)) {
+// Floating-point operations of a mode-product launch: 2 M N K, or for a folded product the
+// two half-size products (2 f x f factor values against the grid's other dimension).
+double gemm_work(const GemmArgs& g, int prec) {
+  if (use_fold(g, prec)) {
     const double f = g.K - g.K / 2;
-    work = 4.0 * f * f * (g.b_trans ? (double)g.N : (double)g.M) * g.inner * g.groups;
+    return 4.0 * f * f * (g.b_trans ? (double)g.N : (double)g.M) * g.inner * g.groups;
   }
+  return 2.0 * g.M * (double)g.N * g.K * g.inner * g.groups;
+}
+
+hipError_t gemm(const mm_op* op, GemmArgs& g, hipStream_t s) {
+  const double work = gemm_work(g, op->prec);
   g.tile = op->ctx ? op->ctx->gemm_tile : 0;
   g.vdig = op->vdig;
   g.vexp = op->vexp;
@@ -2023,6 +2027,7 @@ hipError_t group_pass(mm_ctx* ctx, const mm_op* const* ops, int count, int mu, i
   GemmArgs g{};
   for (int i = 0; i < count; ++i) {
     const void* F = factor_op(ops[i], mu, 0);
+    g.Ff[i] = folded(ops[i], mu, 0);
     g.fexp[i] = factor_exp(ops[i], mu, 0);
     g.galpha[i] = 0.0;
     g.Cadd[i] = nullptr;
@@ -2044,6 +2049,8 @@ hipError_t group_pass(mm_ctx* ctx, const mm_op* const* ops, int count, int mu, i
   g.fac_slice = factor_slice_stride(o0, n, n);
   g.tile = ctx->gemm_tile;
   g.vready = io.ready;
+  g.ldf = n - n / 2;
+  g.fold = ctx->fold;
   if (ws) {
     g.vdig = ws->vdig;
     g.vexp = ws->vexp;
@@ -2051,7 +2058,7 @@ hipError_t group_pass(mm_ctx* ctx, const mm_op* const* ops, int count, int mu, i
     g.vexp_cap = ws->vexp_cap;
   }
   auto launch = [&]() {
-    const double work = 2.0 * g.M * (double)g.N * g.K * g.inner * g.groups;
+    const double work = gemm_work(g, o0->prec);
     return timed_launch(ctx, g.b_trans ? MM_KIND_GEMM_N : MM_KIND_GEMM_K, work, s,
                         [&] { return launch_gemm(o0->prec, g, s); });
   };

@@ -847,7 +847,10 @@ hipError_t launch_fold(GemmArgs& g, hipStream_t s) {
 }
 
 // Whether g runs folded: FP64, every group with a folded factor, a square factor, and
-// (fold = 1) enough 128 x 64 tiles to give every workgroup slot of the chip one.
+// (fold = 1) enough 128 x 64 tiles per group to give every workgroup slot of the chip one.
+// The count excludes the group count, so that a problem's products take the same form
+// alone and in a grouped launch with other problems (folded and plain products round
+// differently).
 bool use_fold(const GemmArgs& g, int prec) {
   if (prec != MM_FP64 || g.fold == 0 || g.in_f32 || g.out_f32) return false;
   if ((g.b_trans ? g.M : g.N) != g.K) return false;
@@ -855,8 +858,8 @@ bool use_fold(const GemmArgs& g, int prec) {
     if (!g.Ff[i]) return false;
   if (g.fold == 2) return true;
   const int f = g.K - g.K / 2;
-  const int64_t tiles = (int64_t)(g.b_trans ? (f + 63) / 64 * ((g.N + 127) / 128) : (g.M + 127) / 128 * ((f + 63) / 64)) *
-                        g.inner * g.groups;
+  const int64_t tiles =
+      (int64_t)(g.b_trans ? (f + 63) / 64 * ((g.N + 127) / 128) : (g.M + 127) / 128 * ((f + 63) / 64)) * g.inner;
   return tiles >= kFillSlots;
 }
 
