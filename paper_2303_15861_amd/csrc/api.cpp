@@ -404,11 +404,11 @@ const int* factor_exp(const mm_op* op, int mu, int j) {
 const double* folded(const mm_op* op, int mu, int j) {
   if (op->prec != MM_FP64 || mu >= (int)op->ffold.size() || !op->ffold[mu] || j < 0 || j >= op->nfold) return nullptr;
   const int64_t f = op->n[mu] - op->n[mu] / 2;
-  return op->ffold[mu] + (int64_t)j * 2 * f * f;
+  return op->ffold[mu] + (int64_t)j * 2 * f * fold_ld(op->n[mu]);
 }
 
 void set_fold(const mm_op* op, GemmArgs& g, int mu) {
-  g.ldf = op->n[mu] - op->n[mu] / 2;
+  g.ldf = fold_ld(op->n[mu]);
   g.fold = op->ctx ? op->ctx->fold : 1;
 }
 
@@ -1503,7 +1503,7 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
         continue;
       }
       const int n = op->n[mu], f = n - n / 2;
-      if ((rc = dev_alloc(op, &op->ffold[mu], (int64_t)nf * 2 * f * f)) != MM_OK) return fail(rc);
+      if ((rc = dev_alloc(op, &op->ffold[mu], (int64_t)nf * 2 * f * fold_ld(n))) != MM_OK) return fail(rc);
       op->ffold_owned[mu] = true;
       HIPCHK(ctx, launch_fold_factor(op->ffold[mu], op->fac[mu], n, nf, st));
     }
@@ -2049,7 +2049,7 @@ hipError_t group_pass(mm_ctx* ctx, const mm_op* const* ops, int count, int mu, i
   g.fac_slice = factor_slice_stride(o0, n, n);
   g.tile = ctx->gemm_tile;
   g.vready = io.ready;
-  g.ldf = n - n / 2;
+  g.ldf = fold_ld(n);
   g.fold = ctx->fold;
   if (ws) {
     g.vdig = ws->vdig;

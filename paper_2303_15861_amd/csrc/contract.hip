@@ -33,6 +33,7 @@ namespace mm {
 
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));   // 8-byte aligned pair
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
@@ -238,13 +239,10 @@ __global__ __launch_bounds__(64 * f64_waves<T>(), 4) void gemm_f64(GemmArgs p) {
 // ------------------------------------------------------------------------------------
 constexpr int PFN = 128 + 4;   // [k][n] pitch of the modes-2/3 grid tiles
 
-// KC: folded k per chunk (8: two workgroups per compute unit; 16: one, twice the MFMA
-// work per barrier)
-template <int BT, int KC>
-__global__ __launch_bounds__(512, KC == 8 ? 4 : 2) void gemm_f64_fold(GemmArgs p) {
+template <int BT>
+__global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
+  constexpr int KC = 8;        // folded k per chunk
   constexpr int PF = KC + 2;   // [row][k] pitch in doubles (16-byte aligned rows)
-  constexpr int NE = KC / 4;   // staged elements of each kind per thread and chunk
-  constexpr int LK = KC == 8 ? 3 : 4;
   const int L = blockIdx.x;
   const int P = (L & 7) * p.per_xcd + (L >> 3);
   if (P >= p.total) return;
@@ -282,54 +280,83 @@ __global__ __launch_bounds__(512, KC == 8 ? 4 : 2) void gemm_f64_fold(GemmArgs p
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  // chunk staging, NE elements of each kind per thread: element e = 512 i + tid.
-  // Factor: row e/KC of the tile's [Es; Ed] rows (rows past f clamped: they feed masked
-  // outputs), k = e%KC. Grid pairs: mode 1 row e/KC, k = e%KC; modes 2/3 k = e/128,
-  // column e%128 (columns past N clamped).
-  double rf[NE], rs[NE], rd[NE];
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int i = 0; i < NE; ++i) {
-      const int e = 512 * i + tid;
-      const int fr = e >> LK, kf = e & (KC - 1);
-      const int frow = min(fo + (fr & 63), f - 1) + (fr >> 6) * f;
-      const int r = k0 + kf;
-      rf[i] = r < f ? Fq[frow * ldf + r] : 0.0;
-      const int kk = BT ? (e >> 7) : kf;
-      const int rr = k0 + kk;
-      const int rc = min(rr, f - 1);   // mirror partner n-1-rc >= rc, both inside the axis
-      double v1, v2;
-      if (BT) {
-        const int col = min(c0 + (e & 127), N - 1);
-        v1 = X[rc * ldx + col];
-        v2 = X[(n - 1 - rc) * ldx + col];
+  // Chunk staging: every thread moves two consecutive values of each kind with 16-byte
+  // accesses. Factor: row tid/4 of the tile's [Es; Ed] rows (rows past f clamped: they
+  // feed masked outputs), k pair 2 (tid%4). Grid: modes 2/3 k = tid/64 and the column pair
+  // 2 (tid%64) with the mirror row; mode 1 row tid/4 (rows past M clamped) and the k pair
+  // 2 (tid%4) with its mirror pair (whose two values come in reverse order). Chunks whose
+  // positions are all below m (every chunk but the last for odd n) need no clamping or
+  // zeroing; the tail chunk takes the elementwise path.
+  const int fr = tid >> 2, kq = 2 * (tid & 3);
+  const double* fbase = Fq + (min(fo + (fr & 63), f - 1) + (fr >> 6) * f) * ldf + kq;
+  const int gk = BT ? (tid >> 6) : kq;                          // grid k within the chunk
+  const int gcol = BT ? c0 + 2 * (tid & 63) : 0;                // modes 2/3: first column
+  const int grow = BT ? 0 : min(r0 + (tid >> 2), M - 1);        // mode 1: grid row
+  const bool gpair = BT ? gcol + 1 < N : true;                  // both columns inside
+  const int gc0 = min(gcol, N - 1), gc1 = min(gcol + 1, N - 1);
+  d2 rf, rs, rd;
+  auto load = [&](int k0, auto tail) {
+    constexpr bool T = decltype(tail)::value;
+    if (!T) {
+      rf = *reinterpret_cast<const d2*>(fbase + k0);
+    } else {
+      rf.x = k0 + kq < f ? fbase[k0] : 0.0;
+      rf.y = k0 + kq + 1 < f ? fbase[k0 + 1] : 0.0;
+    }
+    if (BT) {
+      if (!T && gpair) {
+        const int r = k0 + gk;
+        const d2 v1 = *reinterpret_cast<const d2u*>(X + r * ldx + gcol);
+        const d2 v2 = *reinterpret_cast<const d2u*>(X + (n - 1 - r) * ldx + gcol);
+        rs = v1 + v2;
+        rd = v1 - v2;
       } else {
-        const int row = min(r0 + (e >> LK), M - 1);
-        v1 = X[row * ldx + rc];
-        v2 = X[row * ldx + n - 1 - rc];
+        const int rr = k0 + gk, rc = min(rr, f - 1);   // mirror partner n-1-rc >= rc
+        const double a0 = X[rc * ldx + gc0], a1 = X[rc * ldx + gc1];
+        const double b0 = X[(n - 1 - rc) * ldx + gc0], b1 = X[(n - 1 - rc) * ldx + gc1];
+        rs = rr < m ? d2{a0 + b0, a1 + b1} : rr < f ? d2{a0, a1} : d2{0.0, 0.0};
+        rd = rr < m ? d2{a0 - b0, a1 - b1} : d2{0.0, 0.0};
       }
-      rs[i] = rr < m ? v1 + v2 : rr < f ? v1 : 0.0;
-      rd[i] = rr < m ? v1 - v2 : 0.0;
+    } else {
+      const double* xr = X + grow * ldx;
+      if (!T) {
+        const int r = k0 + kq;
+        const d2 v1 = *reinterpret_cast<const d2u*>(xr + r);
+        const d2 w = *reinterpret_cast<const d2u*>(xr + n - 2 - r);   // x[n-2-r], x[n-1-r]
+        rs = d2{v1.x + w.y, v1.y + w.x};
+        rd = d2{v1.x - w.y, v1.y - w.x};
+      } else {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int rr = k0 + kq + q, rc = min(rr, f - 1);
+          const double a0 = xr[rc], b0 = xr[n - 1 - rc];
+          rs[q] = rr < m ? a0 + b0 : rr < f ? a0 : 0.0;
+          rd[q] = rr < m ? a0 - b0 : 0.0;
+        }
+      }
     }
   };
   auto store = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < NE; ++i) {
-      const int e = 512 * i + tid;
-      Fs[buf][(e >> LK) * PF + (e & (KC - 1))] = rf[i];
-      const int gi = BT ? (e >> 7) * PFN + (e & 127) : (e >> LK) * PF + (e & (KC - 1));
-      Gs[buf][0][gi] = rs[i];
-      Gs[buf][1][gi] = rd[i];
-    }
+    *reinterpret_cast<d2*>(&Fs[buf][fr * PF + kq]) = rf;
+    const int gi = BT ? gk * PFN + 2 * (tid & 63) : (tid >> 2) * PF + kq;
+    *reinterpret_cast<d2*>(&Gs[buf][0][gi]) = rs;
+    *reinterpret_cast<d2*>(&Gs[buf][1][gi]) = rd;
   };
+  using Tail = std::true_type;
+  using Body = std::false_type;
 
   const int nch = (f + KC - 1) / KC;
-  load(0);
+  if (KC <= m) load(0, Body());
+  else load(0, Tail());
   store(0);
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     const int cur = c & 1;
-    if (c + 1 < nch) load((c + 1) * KC);
+    if (c + 1 < nch) {
+      const int k1 = (c + 1) * KC;
+      if (k1 + KC <= m) load(k1, Body());
+      else load(k1, Tail());
+    }
     const double* fs = Fs[cur];
     const double* gs = Gs[cur][0];
     const double* gd = Gs[cur][1];
@@ -418,22 +445,27 @@ __global__ __launch_bounds__(512, KC == 8 ? 4 : 2) void gemm_f64_fold(GemmArgs p
 }
 
 __global__ void fold_factor(double* __restrict__ Ff, const double* __restrict__ E, int n) {
-  const int m = n >> 1, f = n - m;
+  const int m = n >> 1, f = n - m, ld = fold_ld(n);
   const int64_t q = (int64_t)blockIdx.y;
   const double* Eq = E + q * n * n;
-  double* Fq = Ff + q * 2 * f * f;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < f * f; e += gridDim.x * blockDim.x) {
-    const int i = e / f, r = e - i * f;
+  double* Fq = Ff + q * 2 * f * ld;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < f * ld; e += gridDim.x * blockDim.x) {
+    const int i = e / ld, r = e - i * ld;
+    if (r >= f) {   // row padding
+      Fq[i * ld + r] = 0.0;
+      Fq[(f + i) * ld + r] = 0.0;
+      continue;
+    }
     const double x = Eq[i * n + r], y = Eq[i * n + n - 1 - r];
-    Fq[i * f + r] = r < m ? 0.5 * (x + y) : x;
-    Fq[(f + i) * f + r] = r < m ? 0.5 * (x - y) : 0.0;
+    Fq[i * ld + r] = r < m ? 0.5 * (x + y) : x;
+    Fq[(f + i) * ld + r] = r < m ? 0.5 * (x - y) : 0.0;
   }
 }
 
 hipError_t launch_fold_factor(double* Ff, const double* E, int n, int count, hipStream_t s) {
   if (!Ff || !E || n < 1 || count < 1 || count > 65535) return hipErrorInvalidValue;
   const int f = n - n / 2;
-  const int blocks = std::min(1024, (f * f + 255) / 256);
+  const int blocks = std::min(1024, (f * fold_ld(n) + 255) / 256);
   fold_factor<<<dim3(blocks, count), dim3(256), 0, s>>>(Ff, E, n);
   return hipGetLastError();
 }
@@ -829,7 +861,6 @@ int choose_tile(const GemmArgs& g, int prec) {
 }
 
 // Folded FP64 launch: 128 x 64 tiles (grid x folded positions).
-constexpr int kFoldChunk = 8;
 hipError_t launch_fold(GemmArgs& g, hipStream_t s) {
   const int f = g.K - g.K / 2;
   g.tiles_m = g.b_trans ? (f + 63) / 64 : (g.M + 127) / 128;
@@ -840,9 +871,9 @@ hipError_t launch_fold(GemmArgs& g, hipStream_t s) {
   g.per_xcd = (g.total + 7) / 8;
   const dim3 grid(8 * g.per_xcd), block(512);
   if (g.b_trans)
-    gemm_f64_fold<1, kFoldChunk><<<grid, block, 0, s>>>(g);
+    gemm_f64_fold<1><<<grid, block, 0, s>>>(g);
   else
-    gemm_f64_fold<0, kFoldChunk><<<grid, block, 0, s>>>(g);
+    gemm_f64_fold<0><<<grid, block, 0, s>>>(g);
   return hipGetLastError();
 }
 
@@ -886,7 +917,7 @@ hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s) {
   }
   if (use_fold(g, prec)) {
     const int f = g.K - g.K / 2;
-    if (g.ldf < f || (int64_t)2 * f * g.ldf >= lim) return hipErrorInvalidValue;
+    if (g.ldf < f || g.ldf % 2 != 0 || (int64_t)2 * f * g.ldf >= lim) return hipErrorInvalidValue;
     return launch_fold(g, s);
   }
   if (prec != MM_FP64) {

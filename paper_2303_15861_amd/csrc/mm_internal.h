@@ -51,8 +51,8 @@ struct GemmArgs {
   int64_t vdig_cap, vexp_cap;
   int vready;
   // FP64 with a centrosymmetric factor (every group's factor E = J E J): Ff[g] is the
-  // folded factor [Es; Ed] of fold_factor (2f rows of f = K - K/2 values, row stride
-  // ldf); fold: 0 plain product, 1 folded when the launch fills the chip, 2 folded always
+  // folded factor [Es; Ed] of launch_fold_factor (2f rows of f = K - K/2 values, row
+  // stride ldf = fold_ld(K)); fold: 0 plain product, 1 folded when the launch fills the chip, 2 folded always
   const double* Ff[kMaxGroups];
   int ldf;
   int fold;
@@ -154,10 +154,16 @@ struct SmallBatch {
 hipError_t launch_lawson_small2d_batch(const SmallArgs* a, int count, bool l2b, hipStream_t s);
 
 hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s);
+// Row stride of a folded factor: f = n - n/2 rounded up to even (16-byte aligned pairs).
+__host__ __device__ inline int fold_ld(int n) {
+  const int f = n - n / 2;
+  return f + (f & 1);
+}
 // Folded factor of a centrosymmetric n x n matrix E (row-major, row stride n) into Ff:
-// rows 0..f-1 Es, rows f..2f-1 Ed, each of f = n - n/2 values (row stride f), with
+// rows 0..f-1 Es, rows f..2f-1 Ed, each of f = n - n/2 values (row stride fold_ld(n),
+// padding zero), with
 // m = n/2: Es_ir = (E_ir + E_i,n-1-r)/2 and Ed_ir = (E_ir - E_i,n-1-r)/2 for r < m, and for
-// odd n Es_im = E_im, Ed_im = 0. `count` matrices n^2 apart in E, 2 f^2 apart in Ff.
+// odd n Es_im = E_im, Ed_im = 0. `count` matrices n^2 apart in E, 2 f fold_ld(n) apart in Ff.
 hipError_t launch_fold_factor(double* Ff, const double* E, int n, int count, hipStream_t s);
 // Whether launch_gemm runs g as a folded product (FP64, a folded factor for every group,
 // a square factor, and fold = 2 or enough tiles to fill the chip).
@@ -336,8 +342,8 @@ struct mm_op {
   double* a = nullptr;                 // nodal coefficient copy
   std::vector<double*> fac;            // fac[mu] = (1 + q) stacked n_mu x n_mu FP64 factors
   std::vector<bool> fac_owned;
-  // FP64 centrosymmetric axes: the first nfold factors of fac[mu] folded ([Es; Ed], rows of
-  // f = n_mu - n_mu/2, 2 f^2 values each; launch_fold_factor), null on other axes
+  // FP64 centrosymmetric axes: the first nfold factors of fac[mu] folded ([Es; Ed], 2f rows
+  // of stride fold_ld(n_mu), f = n_mu - n_mu/2; launch_fold_factor), null on other axes
   std::vector<double*> ffold;
   std::vector<bool> ffold_owned;
   int nfold = 0;
