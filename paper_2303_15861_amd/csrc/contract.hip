@@ -408,40 +408,49 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
   }
   // f64 16x16 layout: lane l, element t holds row 4t + l/16, column l%16
   const double alpha = p.alpha, beta = p.beta;
-  auto put = [&](int row, int col, double v) {
-    const int idx = row * p.ldc + col;
-    if (Cadd) v += beta * Cadd[idx];
-    C[idx] = v;
-  };
+  // (one loop without and one with the added term, so that the common case carries no
+  // per-element test of Cadd)
+  auto epilogue = [&](auto with_add) {
+    constexpr bool ADD = decltype(with_add)::value;
+    auto put = [&](int row, int col, double v) {
+      const int idx = row * p.ldc + col;
+      if (ADD) v += beta * Cadd[idx];
+      C[idx] = v;
+    };
 #pragma unroll
-  for (int t4 = 0; t4 < 4; ++t4) {
-    if (BT) {
-      const int fr = r0 + 16 * wr + 4 * t4 + lg;
+    for (int t4 = 0; t4 < 4; ++t4) {
+      if (BT) {
+        const int fr = r0 + 16 * wr + 4 * t4 + lg;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int col = c0 + 64 * wc + 16 * j + lr;
-        if (fr < f && col < N) {
-          const double a = acc[0][j][t4], bb = acc[1][j][t4];
-          put(fr, col, alpha * (a + bb));
-          if (fr < m) put(n - 1 - fr, col, alpha * (a - bb));
+        for (int j = 0; j < 4; ++j) {
+          const int col = c0 + 64 * wc + 16 * j + lr;
+          if (fr < f && col < N) {
+            const double a = acc[0][j][t4], bb = acc[1][j][t4];
+            put(fr, col, alpha * (a + bb));
+            if (fr < m) put(n - 1 - fr, col, alpha * (a - bb));
+          }
         }
-      }
-    } else {
+      } else {
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int row = r0 + 32 * wr + 16 * i + 4 * t4 + lg;
+        for (int i = 0; i < 2; ++i) {
+          const int row = r0 + 32 * wr + 16 * i + 4 * t4 + lg;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int fc = c0 + 32 * wc + 16 * j + lr;
-          if (row < M && fc < f) {
-            const double a = acc[i][j][t4], bb = acc[i][j + 2][t4];
-            put(row, fc, alpha * (a + bb));
-            if (fc < m) put(row, n - 1 - fc, alpha * (a - bb));
+          for (int j = 0; j < 2; ++j) {
+            const int fc = c0 + 32 * wc + 16 * j + lr;
+            if (row < M && fc < f) {
+              const double a = acc[i][j][t4], bb = acc[i][j + 2][t4];
+              put(row, fc, alpha * (a + bb));
+              if (fc < m) put(row, n - 1 - fc, alpha * (a - bb));
+            }
           }
         }
       }
     }
-  }
+  };
+  if (Cadd)
+    epilogue(std::true_type{});
+  else
+    epilogue(std::false_type{});
 }
 
 __global__ void fold_factor(double* __restrict__ Ff, const double* __restrict__ E, int n) {
