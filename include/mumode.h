@@ -313,7 +313,10 @@ mm_status mm_set_sliced_chain(mm_ctx* ctx, int mode);
  * with half-size factors, at half the multiply-adds; the results agree with the plain
  * product to rounding. Applies to the exp actions of the Lawson and ERK steps and of
  * mumode_expv (not to stacked quadrature factors). mode = 0: off; 1 (default): on for
- * launches that fill the chip; 2: always. Other modes: MM_EINVAL. */
+ * products with at least 192 folded tiles (128 grid rows or columns x 64 folded
+ * positions) per problem, smaller ones keep the plain kernel's smaller tiles; 2: always.
+ * The decision does not depend on how many problems share a launch. Other modes:
+ * MM_EINVAL. */
 mm_status mm_set_fold(mm_ctx* ctx, int mode);
 
 /* Step replay through HIP graphs (launch-bound small problems). steps = 0 (default):

@@ -271,8 +271,8 @@ class Context:
         self.check(lib().mm_set_sliced_chain(self._h, int(mode)), "mm_set_sliced_chain")
 
     def set_fold(self, mode: int):
-        """FP64 folded mode products on centrosymmetric axes: 0 off, 1 on for launches that
-        fill the chip (default), 2 always."""
+        """FP64 folded mode products on centrosymmetric axes: 0 off, 1 on for products of at
+        least 192 folded tiles per problem (default), 2 always."""
         self.check(lib().mm_set_fold(self._h, int(mode)), "mm_set_fold")
 
     def set_graph_steps(self, steps: int):

@@ -886,21 +886,28 @@ hipError_t launch_fold(GemmArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Folded launches take over from the plain ones from this many 128 x 64 tiles per group:
+// at 127^3 Lawson2b (254 tiles per pass) the folded step runs 109 against 121 us, while a
+// single 127^3 vector (127 tiles) runs faster on the plain kernel's 64-tiles, which spread
+// it over more compute units.
+constexpr int64_t kFoldMinTiles = 192;
+
 // Whether g runs folded: FP64, every group with a folded factor, a square factor, and
-// (fold = 1) enough 128 x 64 tiles per group to give every workgroup slot of the chip one.
+// (fold = 1) at least kFoldMinTiles tiles per group.
 // The count excludes the group count, so that a problem's products take the same form
 // alone and in a grouped launch with other problems (folded and plain products round
 // differently).
+int64_t fold_tiles(const GemmArgs& g) {
+  const int f = g.K - g.K / 2;
+  return (int64_t)(g.b_trans ? (f + 63) / 64 * ((g.N + 127) / 128) : (g.M + 127) / 128 * ((f + 63) / 64)) * g.inner;
+}
+
 bool use_fold(const GemmArgs& g, int prec) {
   if (prec != MM_FP64 || g.fold == 0 || g.in_f32 || g.out_f32) return false;
   if ((g.b_trans ? g.M : g.N) != g.K) return false;
   for (int i = 0; i < g.groups; ++i)
     if (!g.Ff[i]) return false;
-  if (g.fold == 2) return true;
-  const int f = g.K - g.K / 2;
-  const int64_t tiles =
-      (int64_t)(g.b_trans ? (f + 63) / 64 * ((g.N + 127) / 128) : (g.M + 127) / 128 * ((f + 63) / 64)) * g.inner;
-  return tiles >= kFillSlots;
+  return g.fold == 2 || fold_tiles(g) >= kFoldMinTiles;
 }
 
 hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s) {

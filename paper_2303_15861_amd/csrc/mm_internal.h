@@ -52,7 +52,7 @@ struct GemmArgs {
   int vready;
   // FP64 with a centrosymmetric factor (every group's factor E = J E J): Ff[g] is the
   // folded factor [Es; Ed] of launch_fold_factor (2f rows of f = K - K/2 values, row
-  // stride ldf = fold_ld(K)); fold: 0 plain product, 1 folded when the launch fills the chip, 2 folded always
+  // stride ldf = fold_ld(K)); fold: 0 plain product, 1 folded from 192 tiles per group, 2 always
   const double* Ff[kMaxGroups];
   int ldf;
   int fold;
@@ -168,6 +168,8 @@ hipError_t launch_fold_factor(double* Ff, const double* E, int n, int count, hip
 // Whether launch_gemm runs g as a folded product (FP64, a folded factor for every group,
 // a square factor, and fold = 2 or enough tiles to fill the chip).
 bool use_fold(const GemmArgs& g, int prec);
+// 128 x 64 folded tiles of one group of g.
+int64_t fold_tiles(const GemmArgs& g);
 // Tile size the launcher takes for g in precision prec (g.tile if set, else 64 when
 // 128-tiles would not fill the chip once, and in FP64 32 when 64-tiles would not give
 // every compute unit one).
