@@ -284,60 +284,77 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
   // accesses. Factor: row tid/4 of the tile's [Es; Ed] rows (rows past f clamped: they
   // feed masked outputs), k pair 2 (tid%4). Grid: modes 2/3 k = tid/64 and the column pair
   // 2 (tid%64) with the mirror row; mode 1 row tid/4 (rows past M clamped) and the k pair
-  // 2 (tid%4) with its mirror pair (whose two values come in reverse order). Chunks whose
-  // positions are all below m (every chunk but the last for odd n) need no clamping or
-  // zeroing; the tail chunk takes the elementwise path.
+  // 2 (tid%4) with its mirror pair (whose two values come in reverse order). The loads
+  // only fill registers; the sums, differences and zeroing happen when the chunk is
+  // written to LDS, after the current chunk's products, so that no wait for the loads
+  // stands in front of them. Chunks whose positions are all below m (every chunk but the
+  // last for odd n) need no clamping or zeroing; the tail chunk takes the elementwise path.
   const int fr = tid >> 2, kq = 2 * (tid & 3);
-  const double* fbase = Fq + (min(fo + (fr & 63), f - 1) + (fr >> 6) * f) * ldf + kq;
+  const double* fbase = Fq + (min(fo + (fr & 63), f - 1) + (fr >> 6) * f) * ldf;
   const int gk = BT ? (tid >> 6) : kq;                          // grid k within the chunk
   const int gcol = BT ? c0 + 2 * (tid & 63) : 0;                // modes 2/3: first column
   const int grow = BT ? 0 : min(r0 + (tid >> 2), M - 1);        // mode 1: grid row
   const bool gpair = BT ? gcol + 1 < N : true;                  // both columns inside
   const int gc0 = min(gcol, N - 1), gc1 = min(gcol + 1, N - 1);
-  d2 rf, rs, rd;
+  d2 rf, q1, q2;   // raw factor pair; grid values and their mirror partners
   auto load = [&](int k0, auto tail) {
     constexpr bool T = decltype(tail)::value;
-    if (!T) {
-      rf = *reinterpret_cast<const d2*>(fbase + k0);
-    } else {
-      rf.x = k0 + kq < f ? fbase[k0] : 0.0;
-      rf.y = k0 + kq + 1 < f ? fbase[k0 + 1] : 0.0;
-    }
+    // (an index past the factor row is clamped; its values are zeroed when stored)
+    rf = *reinterpret_cast<const d2*>(fbase + (T ? min(k0 + kq, ldf - 2) : k0 + kq));
     if (BT) {
       if (!T && gpair) {
         const int r = k0 + gk;
-        const d2 v1 = *reinterpret_cast<const d2u*>(X + r * ldx + gcol);
-        const d2 v2 = *reinterpret_cast<const d2u*>(X + (n - 1 - r) * ldx + gcol);
-        rs = v1 + v2;
-        rd = v1 - v2;
+        q1 = *reinterpret_cast<const d2u*>(X + r * ldx + gcol);
+        q2 = *reinterpret_cast<const d2u*>(X + (n - 1 - r) * ldx + gcol);
       } else {
-        const int rr = k0 + gk, rc = min(rr, f - 1);   // mirror partner n-1-rc >= rc
-        const double a0 = X[rc * ldx + gc0], a1 = X[rc * ldx + gc1];
-        const double b0 = X[(n - 1 - rc) * ldx + gc0], b1 = X[(n - 1 - rc) * ldx + gc1];
-        rs = rr < m ? d2{a0 + b0, a1 + b1} : rr < f ? d2{a0, a1} : d2{0.0, 0.0};
-        rd = rr < m ? d2{a0 - b0, a1 - b1} : d2{0.0, 0.0};
+        const int rc = min(k0 + gk, f - 1);   // mirror partner n-1-rc >= rc
+        q1 = d2{X[rc * ldx + gc0], X[rc * ldx + gc1]};
+        q2 = d2{X[(n - 1 - rc) * ldx + gc0], X[(n - 1 - rc) * ldx + gc1]};
       }
     } else {
       const double* xr = X + grow * ldx;
       if (!T) {
         const int r = k0 + kq;
-        const d2 v1 = *reinterpret_cast<const d2u*>(xr + r);
-        const d2 w = *reinterpret_cast<const d2u*>(xr + n - 2 - r);   // x[n-2-r], x[n-1-r]
-        rs = d2{v1.x + w.y, v1.y + w.x};
-        rd = d2{v1.x - w.y, v1.y - w.x};
+        q1 = *reinterpret_cast<const d2u*>(xr + r);
+        q2 = *reinterpret_cast<const d2u*>(xr + n - 2 - r);   // x[n-2-r], x[n-1-r]
       } else {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          const int rr = k0 + kq + q, rc = min(rr, f - 1);
-          const double a0 = xr[rc], b0 = xr[n - 1 - rc];
-          rs[q] = rr < m ? a0 + b0 : rr < f ? a0 : 0.0;
-          rd[q] = rr < m ? a0 - b0 : 0.0;
+          const int rc = min(k0 + kq + q, f - 1);
+          q1[q] = xr[rc];
+          q2[q] = xr[n - 1 - rc];
         }
       }
     }
   };
-  auto store = [&](int buf) {
-    *reinterpret_cast<d2*>(&Fs[buf][fr * PF + kq]) = rf;
+  auto store = [&](int buf, int k0, auto tail) {
+    constexpr bool T = decltype(tail)::value;
+    d2 sf = rf, rs, rd;
+    if (T) {
+      sf.x = k0 + kq < f ? rf.x : 0.0;
+      sf.y = k0 + kq + 1 < f ? rf.y : 0.0;
+    }
+    if (BT) {
+      const int rr = k0 + gk;
+      if (!T || rr < m) {
+        rs = q1 + q2;
+        rd = q1 - q2;
+      } else {
+        rs = rr < f ? q1 : d2{0.0, 0.0};
+        rd = d2{0.0, 0.0};
+      }
+    } else if (!T) {
+      rs = d2{q1.x + q2.y, q1.y + q2.x};
+      rd = d2{q1.x - q2.y, q1.y - q2.x};
+    } else {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int rr = k0 + kq + q;
+        rs[q] = rr < m ? q1[q] + q2[q] : rr < f ? q1[q] : 0.0;
+        rd[q] = rr < m ? q1[q] - q2[q] : 0.0;
+      }
+    }
+    *reinterpret_cast<d2*>(&Fs[buf][fr * PF + kq]) = sf;
     const int gi = BT ? gk * PFN + 2 * (tid & 63) : (tid >> 2) * PF + kq;
     *reinterpret_cast<d2*>(&Gs[buf][0][gi]) = rs;
     *reinterpret_cast<d2*>(&Gs[buf][1][gi]) = rd;
@@ -346,15 +363,20 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
   using Body = std::false_type;
 
   const int nch = (f + KC - 1) / KC;
-  if (KC <= m) load(0, Body());
-  else load(0, Tail());
-  store(0);
+  if (KC <= m) {
+    load(0, Body());
+    store(0, 0, Body());
+  } else {
+    load(0, Tail());
+    store(0, 0, Tail());
+  }
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     const int cur = c & 1;
+    const int k1 = (c + 1) * KC;
+    const bool body1 = k1 + KC <= m;   // the next chunk needs no clamping
     if (c + 1 < nch) {
-      const int k1 = (c + 1) * KC;
-      if (k1 + KC <= m) load(k1, Body());
+      if (body1) load(k1, Body());
       else load(k1, Tail());
     }
     const double* fs = Fs[cur];
@@ -403,7 +425,10 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
                                                                0, 0);
       }
     }
-    if (c + 1 < nch) store(cur ^ 1);
+    if (c + 1 < nch) {
+      if (body1) store(cur ^ 1, k1, Body());
+      else store(cur ^ 1, k1, Tail());
+    }
     __syncthreads();
   }
   // f64 16x16 layout: lane l, element t holds row 4t + l/16, column l%16
