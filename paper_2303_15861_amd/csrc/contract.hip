@@ -389,20 +389,23 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
         // wave: folded rows 16 wr + [0, 16) of Es and of Ed, columns 64 wc + [0, 64)
         const d2 as = *reinterpret_cast<const d2*>(fs + (16 * wr + lr) * PF + kb);
         const d2 ad = *reinterpret_cast<const d2*>(fs + (64 + 16 * wr + lr) * PF + kb);
-        d2 bs[4], bd[4];
+        // the Es products against the s tile, then the Ed products against the d tile (one
+        // set of grid fragments live at a time)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int col = 64 * wc + 16 * j + lr;
-          bs[j] = d2{gs[kb * PFN + col], gs[(kb + 1) * PFN + col]};
-          bd[j] = d2{gd[kb * PFN + col], gd[(kb + 1) * PFN + col]};
-        }
-#pragma unroll
-        for (int st = 0; st < 2; ++st)
+        for (int h2 = 0; h2 < 2; ++h2) {
+          const double* gt = h2 ? gd : gs;
+          d2 bf[4];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            acc[0][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[st], bs[j][st], acc[0][j], 0, 0, 0);
-            acc[1][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[st], bd[j][st], acc[1][j], 0, 0, 0);
+            const int col = 64 * wc + 16 * j + lr;
+            bf[j] = d2{gt[kb * PFN + col], gt[(kb + 1) * PFN + col]};
           }
+#pragma unroll
+          for (int st = 0; st < 2; ++st)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              acc[h2][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(h2 ? ad[st] : as[st], bf[j][st], acc[h2][j], 0, 0, 0);
+        }
       } else {
         // wave: grid rows 32 wr + [0, 32), folded columns 32 wc + [0, 32) of Es (j = 0, 1)
         // and of Ed (j = 2, 3)
