@@ -498,6 +498,20 @@ def main():
               + (f", err at T {entry['err_at_T']:.2e} (target {entry['target']:.0e})" if "err_at_T" in entry else ""),
               file=sys.stderr, flush=True)
 
+    if args.fold != 0:
+        # the plain FP64 products on the same workload (timed steps only): the form the
+        # mixed precisions are compared with besides the folded default
+        print(f"[bench] fp64 plain products: {args.steps} timed steps", file=sys.stderr, flush=True)
+        ctx.set_fold(0)
+        op, _, dt, kern, status = time_mode(mm, ctx, p, "fp64", args.steps, args.warmup, args.graph_steps)
+        op.close()
+        ctx.set_fold(args.fold)
+        res["fp64_plain"] = {"ms_per_step": 1e3 * dt / args.steps, "value": p.dof * args.steps / dt / 1e6,
+                             "kernels": kern, "status": mm.STATUS.get(status, status),
+                             "roofline": roofline(kern, "fp64", p)[0]}
+        print(f"[bench] fp64 plain products: {res['fp64_plain']['ms_per_step']:.3f} ms/step", file=sys.stderr,
+              flush=True)
+
     head = res[args.headline]
     roof, kname = roofline(head["kernels"], args.headline, p)
     roof["traffic"] = measured_traffic() if (kname == "gemm_n" and args.headline == "fp64"
@@ -528,6 +542,8 @@ def main():
         "fastest_mode_meeting_target": fastest_accurate,
         "speedup_of_that_mode_over_fp64": (res["fp64"]["ms_per_step"] / res[fastest_accurate]["ms_per_step"]
                                            if fastest_accurate else None),
+        "speedup_of_that_mode_over_plain_fp64": (res["fp64_plain"]["ms_per_step"] / res[fastest_accurate]["ms_per_step"]
+                                                 if fastest_accurate and "fp64_plain" in res else None),
         "kernels": {m: e["kernels"] for m, e in res.items()},
         "roofline": roof,
     }
