@@ -414,7 +414,7 @@ const double* folded(const mm_op* op, int mu, int j) {
 // grouped launches (group_pass) keep the per-problem rule: theirs must not depend on the
 // group count.
 void set_fold(const mm_op* op, GemmArgs& g, int mu) {
-  g.ldf = fold_ld(op->n[mu]);
+  g.ldf = (g.fold_blocks > 1 ? g.fold_blocks : 1) * fold_ld(op->n[mu]);
   g.fold = op->ctx ? op->ctx->fold : 1;
   if (g.fold == 1 && g.groups > 1) g.fold = fold_tiles(g) * g.groups >= 512 ? 2 : 0;
 }
@@ -526,7 +526,8 @@ hipError_t pass_last(const mm_op* op, const void* F, const int* Fexp, int kmul, 
     const size_t ib = io.in_f32 ? 4 : 8, ob = io.out_f32 ? 4 : 8;
     GemmArgs g{};
     g.A[0] = F;
-    g.Ff[0] = kmul == 1 ? Ffold : nullptr;
+    g.Ff[0] = Ffold;
+    g.fold_blocks = kmul;
     set_fold(op, g, last_axis(op));
     g.fexp[0] = Fexp;
     g.slices = op->slices;
@@ -574,7 +575,8 @@ hipError_t pass_last(const mm_op* op, const void* F, const int* Fexp, int kmul, 
   }
   GemmArgs g{};
   g.A[0] = F;
-  g.Ff[0] = kmul == 1 ? Ffold : nullptr;
+  g.Ff[0] = Ffold;
+  g.fold_blocks = kmul;
   set_fold(op, g, last_axis(op));
   g.fexp[0] = Fexp;
   g.slices = op->slices;
@@ -646,6 +648,11 @@ hipError_t grouped_action(const mm_op* op, int G, const double* const* ins, cons
                           hipStream_t s, const double* w1 = nullptr) {
   const bool mixed = lowp(op);
   const int64_t esz = mixed ? 4 : 8;
+  // the folded form of the stacked factor, when it has one
+  const double* F3fold = F3 == op->f3_stage1 ? op->f3_stage1_fold
+                         : F3 == op->f3_stage2 ? op->f3_stage2_fold
+                         : F3 == op->f3_phi    ? op->f3_phi_fold
+                                               : nullptr;
   const void* in1[kMaxGroups];
   void* o1[kMaxGroups];
   for (int g = 0; g < G; ++g) {
@@ -663,9 +670,11 @@ hipError_t grouped_action(const mm_op* op, int G, const double* const* ins, cons
     }
     e = pass_mode2(op, G, fidx, i2, o2, op->n[2], PassIO{mixed, mixed}, s);
     if (e != hipSuccess) return e;
-    return pass_last(op, F3, F3exp, G, t1, out, add, 1.0, beta, 1, PassIO{mixed, false}, s);
+    return pass_last(op, F3, F3exp, G, t1, out, add, 1.0, beta, 1, PassIO{mixed, false}, s, Layout{0, 0},
+                     Layout{0, 0}, F3fold);
   }
-  return pass_last(op, F3, F3exp, G, t0, out, add, 1.0, beta, 1, PassIO{mixed, false}, s);
+  return pass_last(op, F3, F3exp, G, t0, out, add, 1.0, beta, 1, PassIO{mixed, false}, s, Layout{0, 0},
+                   Layout{0, 0}, F3fold);
 }
 
 // Sliced mode keeps the stacked last-axis blocks unweighted (so that one row exponent
@@ -1032,6 +1041,9 @@ void mumode_destroy(mm_op* op) {
   dev_free(op, op->f3_stage1);
   dev_free(op, op->f3_stage2);
   dev_free(op, op->f3_phi);
+  dev_free(op, op->f3_stage1_fold);
+  dev_free(op, op->f3_stage2_fold);
+  dev_free(op, op->f3_phi_fold);
   for (size_t i = 0; i < op->fac_lp.size(); ++i)
     if (op->fac_owned[i]) dev_free(op, op->fac_lp[i]);
   dev_free(op, op->f3_stage1_lp);
@@ -1547,6 +1559,17 @@ mm_status mumode_setup(mm_ctx* ctx, const mm_problem* prob, double tau, int fami
                                       unit ? 1.0 : 0.5 * tau * op->weight[j], st));
       HIPCHK(ctx, launch_place_scaled(op->f3_phi, q * nl, (j - 1) * nl, factor(op, la, j), nl,
                                       unit ? 1.0 : op->weight[j], st));
+    }
+    // the stacked factors' blocks are weighted exp factors of the last axis: they fold
+    // where that axis's factors do
+    if (prec == MM_FP64 && op->ffold[la]) {
+      const int64_t fb = (int64_t)2 * (nl - nl / 2) * fold_ld(nl);
+      if ((rc = dev_alloc(op, &op->f3_stage1_fold, fb * g1)) != MM_OK) return fail(rc);
+      if ((rc = dev_alloc(op, &op->f3_stage2_fold, fb * q)) != MM_OK) return fail(rc);
+      if ((rc = dev_alloc(op, &op->f3_phi_fold, fb * q)) != MM_OK) return fail(rc);
+      HIPCHK(ctx, launch_fold_stacked(op->f3_stage1_fold, op->f3_stage1, nl, g1, st));
+      HIPCHK(ctx, launch_fold_stacked(op->f3_stage2_fold, op->f3_stage2, nl, q, st));
+      HIPCHK(ctx, launch_fold_stacked(op->f3_phi_fold, op->f3_phi, nl, q, st));
     }
     if (prec != MM_FP64) {
       const int64_t s1 = op_bytes(nl, g1 * nl), s2 = op_bytes(nl, q * nl);

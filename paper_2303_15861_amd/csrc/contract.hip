@@ -257,7 +257,10 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
     tn = t % p.tiles_n;
     tm = t / p.tiles_n;
   }
-  const int n = p.K, m = n >> 1, f = n - m;
+  // G = fold_blocks stacked factors along k (the grid operand's k axis holds G vectors of
+  // n): folded position kk = g fl + r (fl = fold_ld(n); pad positions f <= r < fl are zero
+  // in the folded factor)
+  const int G = p.fold_blocks, n = p.K / G, m = n >> 1, f = n - m, fl = fold_ld(n), kf = G * fl;
   // BT: rows are folded positions (64 per tile), columns grid columns (128);
   // !BT: rows are grid rows (128), columns folded positions (64)
   const int r0 = tm * (BT ? 64 : 128), c0 = tn * (BT ? 128 : 64);
@@ -297,19 +300,26 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
   const bool gpair = BT ? gcol + 1 < N : true;                  // both columns inside
   const int gc0 = min(gcol, N - 1), gc1 = min(gcol + 1, N - 1);
   d2 rf, q1, q2;   // raw factor pair; grid values and their mirror partners
+  // the block and in-block position of folded position kk (past the end: the last block)
+  auto split = [&](int kk, int& g0, int& r) {
+    g0 = min(kk / fl, G - 1);
+    r = kk - g0 * fl;
+  };
   auto load = [&](int k0, auto tail) {
     constexpr bool T = decltype(tail)::value;
     // (an index past the factor row is clamped; its values are zeroed when stored)
-    rf = *reinterpret_cast<const d2*>(fbase + (T ? min(k0 + kq, ldf - 2) : k0 + kq));
+    rf = *reinterpret_cast<const d2*>(fbase + (T ? min(k0 + kq, kf - 2) : k0 + kq));
     if (BT) {
+      int g0, r;
+      split(k0 + gk, g0, r);
+      const int base = g0 * n;
       if (!T && gpair) {
-        const int r = k0 + gk;
-        q1 = *reinterpret_cast<const d2u*>(X + r * ldx + gcol);
-        q2 = *reinterpret_cast<const d2u*>(X + (n - 1 - r) * ldx + gcol);
+        q1 = *reinterpret_cast<const d2u*>(X + (base + r) * ldx + gcol);
+        q2 = *reinterpret_cast<const d2u*>(X + (base + n - 1 - r) * ldx + gcol);
       } else {
-        const int rc = min(k0 + gk, f - 1);   // mirror partner n-1-rc >= rc
+        const int rc = base + min(r, f - 1), rm = base + n - 1 - min(r, f - 1);   // rm >= rc
         q1 = d2{X[rc * ldx + gc0], X[rc * ldx + gc1]};
-        q2 = d2{X[(n - 1 - rc) * ldx + gc0], X[(n - 1 - rc) * ldx + gc1]};
+        q2 = d2{X[rm * ldx + gc0], X[rm * ldx + gc1]};
       }
     } else {
       const double* xr = X + grow * ldx;
@@ -331,16 +341,18 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
     constexpr bool T = decltype(tail)::value;
     d2 sf = rf, rs, rd;
     if (T) {
-      sf.x = k0 + kq < f ? rf.x : 0.0;
-      sf.y = k0 + kq + 1 < f ? rf.y : 0.0;
+      sf.x = k0 + kq < kf ? rf.x : 0.0;
+      sf.y = k0 + kq + 1 < kf ? rf.y : 0.0;
     }
     if (BT) {
-      const int rr = k0 + gk;
-      if (!T || rr < m) {
+      int g0, rr;
+      split(k0 + gk, g0, rr);
+      const bool live = k0 + gk < kf;
+      if (!T || (live && rr < m)) {
         rs = q1 + q2;
         rd = q1 - q2;
       } else {
-        rs = rr < f ? q1 : d2{0.0, 0.0};
+        rs = live && rr < f ? q1 : d2{0.0, 0.0};
         rd = d2{0.0, 0.0};
       }
     } else if (!T) {
@@ -362,8 +374,10 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
   using Tail = std::true_type;
   using Body = std::false_type;
 
-  const int nch = (f + KC - 1) / KC;
-  if (KC <= m) {
+  // a chunk needs no clamping or zeroing when its positions lie in one block, below m
+  auto body_chunk = [&](int k0) { return (k0 % fl) + KC <= m; };
+  const int nch = (kf + KC - 1) / KC;
+  if (body_chunk(0)) {
     load(0, Body());
     store(0, 0, Body());
   } else {
@@ -374,7 +388,7 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
   for (int c = 0; c < nch; ++c) {
     const int cur = c & 1;
     const int k1 = (c + 1) * KC;
-    const bool body1 = k1 + KC <= m;   // the next chunk needs no clamping
+    const bool body1 = body_chunk(k1);
     if (c + 1 < nch) {
       if (body1) load(k1, Body());
       else load(k1, Tail());
@@ -481,29 +495,40 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
     epilogue(std::false_type{});
 }
 
-__global__ void fold_factor(double* __restrict__ Ff, const double* __restrict__ E, int n) {
+// Folds the n x n block q of E (row stride lde, blocks es apart) into Ff (row stride ldff,
+// blocks fs apart): Es rows 0..f-1, Ed rows f..2f-1, fold_ld(n) columns (padding zero).
+__global__ void fold_factor(double* __restrict__ Ff, int ldff, int64_t fs, const double* __restrict__ E, int lde,
+                            int64_t es, int n) {
   const int m = n >> 1, f = n - m, ld = fold_ld(n);
   const int64_t q = (int64_t)blockIdx.y;
-  const double* Eq = E + q * n * n;
-  double* Fq = Ff + q * 2 * f * ld;
+  const double* Eq = E + q * es;
+  double* Fq = Ff + q * fs;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < f * ld; e += gridDim.x * blockDim.x) {
     const int i = e / ld, r = e - i * ld;
     if (r >= f) {   // row padding
-      Fq[i * ld + r] = 0.0;
-      Fq[(f + i) * ld + r] = 0.0;
+      Fq[(int64_t)i * ldff + r] = 0.0;
+      Fq[(int64_t)(f + i) * ldff + r] = 0.0;
       continue;
     }
-    const double x = Eq[i * n + r], y = Eq[i * n + n - 1 - r];
-    Fq[i * ld + r] = r < m ? 0.5 * (x + y) : x;
-    Fq[(f + i) * ld + r] = r < m ? 0.5 * (x - y) : 0.0;
+    const double x = Eq[(int64_t)i * lde + r], y = Eq[(int64_t)i * lde + n - 1 - r];
+    Fq[(int64_t)i * ldff + r] = r < m ? 0.5 * (x + y) : x;
+    Fq[(int64_t)(f + i) * ldff + r] = r < m ? 0.5 * (x - y) : 0.0;
   }
 }
 
 hipError_t launch_fold_factor(double* Ff, const double* E, int n, int count, hipStream_t s) {
   if (!Ff || !E || n < 1 || count < 1 || count > 65535) return hipErrorInvalidValue;
-  const int f = n - n / 2;
-  const int blocks = std::min(1024, (f * fold_ld(n) + 255) / 256);
-  fold_factor<<<dim3(blocks, count), dim3(256), 0, s>>>(Ff, E, n);
+  const int f = n - n / 2, ld = fold_ld(n);
+  const int blocks = std::min(1024, (f * ld + 255) / 256);
+  fold_factor<<<dim3(blocks, count), dim3(256), 0, s>>>(Ff, ld, (int64_t)2 * f * ld, E, n, (int64_t)n * n, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_stacked(double* Ff, const double* E, int n, int G, hipStream_t s) {
+  if (!Ff || !E || n < 1 || G < 1 || G > 65535) return hipErrorInvalidValue;
+  const int f = n - n / 2, ld = fold_ld(n);
+  const int blocks = std::min(1024, (f * ld + 255) / 256);
+  fold_factor<<<dim3(blocks, G), dim3(256), 0, s>>>(Ff, G * ld, ld, E, G * n, n, n);
   return hipGetLastError();
 }
 
@@ -897,9 +922,13 @@ int choose_tile(const GemmArgs& g, int prec) {
   return prec == MM_FP64 && t64 < kComputeUnits ? 32 : 64;
 }
 
+// stacked factor blocks of a folded launch (0 counts as one)
+int fold_blocks(const GemmArgs& g) { return g.fold_blocks > 1 ? g.fold_blocks : 1; }
+
 // Folded FP64 launch: 128 x 64 tiles (grid x folded positions).
 hipError_t launch_fold(GemmArgs& g, hipStream_t s) {
-  const int f = g.K - g.K / 2;
+  g.fold_blocks = fold_blocks(g);
+  const int f = g.K / g.fold_blocks - g.K / g.fold_blocks / 2;
   g.tiles_m = g.b_trans ? (f + 63) / 64 : (g.M + 127) / 128;
   g.tiles_n = g.b_trans ? (g.N + 127) / 128 : (f + 63) / 64;
   const int64_t total = (int64_t)g.tiles_m * g.tiles_n * g.inner * g.groups;
@@ -926,13 +955,14 @@ constexpr int64_t kFoldMinTiles = 192;
 // alone and in a grouped launch with other problems (folded and plain products round
 // differently).
 int64_t fold_tiles(const GemmArgs& g) {
-  const int f = g.K - g.K / 2;
+  const int n = g.K / fold_blocks(g), f = n - n / 2;
   return (int64_t)(g.b_trans ? (f + 63) / 64 * ((g.N + 127) / 128) : (g.M + 127) / 128 * ((f + 63) / 64)) * g.inner;
 }
 
 bool use_fold(const GemmArgs& g, int prec) {
   if (prec != MM_FP64 || g.fold == 0 || g.in_f32 || g.out_f32) return false;
-  if ((g.b_trans ? g.M : g.N) != g.K) return false;
+  const int G = fold_blocks(g);
+  if (g.K % G != 0 || (g.b_trans ? g.M : g.N) != g.K / G || (G > 1 && !g.b_trans)) return false;
   for (int i = 0; i < g.groups; ++i)
     if (!g.Ff[i]) return false;
   return g.fold == 2 || fold_tiles(g) >= kFoldMinTiles;
@@ -960,8 +990,8 @@ hipError_t launch_gemm(int prec, GemmArgs& g, hipStream_t s) {
     return launch_gemm_sliced(g, s);
   }
   if (use_fold(g, prec)) {
-    const int f = g.K - g.K / 2;
-    if (g.ldf < f || g.ldf % 2 != 0 || (int64_t)2 * f * g.ldf >= lim) return hipErrorInvalidValue;
+    const int G = fold_blocks(g), n = g.K / G, f = n - n / 2;
+    if (g.ldf < G * fold_ld(n) || g.ldf % 2 != 0 || (int64_t)2 * f * g.ldf >= lim) return hipErrorInvalidValue;
     return launch_fold(g, s);
   }
   if (prec != MM_FP64) {

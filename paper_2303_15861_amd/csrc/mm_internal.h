@@ -56,6 +56,10 @@ struct GemmArgs {
   const double* Ff[kMaxGroups];
   int ldf;
   int fold;
+  // modes 2/3 only: the factor stacks fold_blocks n x n blocks along k (K = fold_blocks n,
+  // each block centrosymmetric; the grid operand stacks as many vectors), folded block by
+  // block side by side (launch_fold_stacked; ldf = fold_blocks fold_ld(n)); 0 or 1: one
+  int fold_blocks;
   // filled by the launcher
   int tiles_m, tiles_n, total, per_xcd;
 };
@@ -165,6 +169,10 @@ __host__ __device__ inline int fold_ld(int n) {
 // m = n/2: Es_ir = (E_ir + E_i,n-1-r)/2 and Ed_ir = (E_ir - E_i,n-1-r)/2 for r < m, and for
 // odd n Es_im = E_im, Ed_im = 0. `count` matrices n^2 apart in E, 2 f fold_ld(n) apart in Ff.
 hipError_t launch_fold_factor(double* Ff, const double* E, int n, int count, hipStream_t s);
+// Folded form of a stacked factor [E_0 | ... | E_{G-1}] (n rows, row stride G n, every
+// block centrosymmetric) into Ff: 2f rows of G fold_ld(n) values, block g's Es and Ed in
+// columns g fold_ld(n) .. +fold_ld(n).
+hipError_t launch_fold_stacked(double* Ff, const double* E, int n, int G, hipStream_t s);
 // Whether launch_gemm runs g as a folded product (FP64, a folded factor for every group,
 // a square factor, and fold = 2 or enough tiles to fill the chip).
 bool use_fold(const GemmArgs& g, int prec);
@@ -349,6 +357,10 @@ struct mm_op {
   std::vector<double*> ffold;
   std::vector<bool> ffold_owned;
   int nfold = 0;
+  // folded forms of the stacked last-axis ERK factors (null unless that axis folds)
+  double* f3_stage1_fold = nullptr;
+  double* f3_stage2_fold = nullptr;
+  double* f3_phi_fold = nullptr;
   double* f3_stage1 = nullptr;         // ERK: [E3(1) | tau w_j E3(theta_j)] or [tau w_j E3]
   double* f3_stage2 = nullptr;         // ERK: [tau/2 w_j E3(theta_j)]
   double* f3_phi = nullptr;            // [w_j E3(theta_j)] for mumode_phi1v

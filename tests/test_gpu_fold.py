@@ -94,6 +94,21 @@ def test_folded_in_place_and_quadrature_factor(mm, ctx):
     assert relerr(got2, oracle_op(p).expv(th[1], V)) <= FP64_TOL
 
 
+@pytest.mark.parametrize("n,q", [((12, 11), 4), ((16, 9, 13), 4), ((20, 18, 21), 6)])
+def test_folded_stacked_phi1(mm, ctx, n, q):
+    """The quadrature φ1 action: its last mode contracts the stacked weighted factors
+    [w_j E(θ_j)], which fold block by block (odd and even last axes, two and three dims)."""
+    p = synth.smooth_problem(n, 38, tau=2e-3, scheme="etd2rk", q=q)
+    ctx.set_fold(2)
+    op = mm.setup_problem(ctx, p)
+    V = np.random.default_rng(39).standard_normal(p.shape)
+    out = dev(np.zeros(p.shape))
+    mm.mumode_phi1v(op, dev(V), out)
+    got = host(out)
+    op.close()
+    assert relerr(got, oracle_op(p).phi1v_quad(V, q)) <= FP64_TOL
+
+
 def test_axes_without_symmetry_stay_plain(mm, ctx):
     """advection in A (nonsymmetric factors) on some axes: with fold = 2 those axes keep
     the plain product (a folded product of a nonsymmetric factor would miss the oracle by
