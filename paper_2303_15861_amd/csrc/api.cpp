@@ -231,8 +231,11 @@ hipError_t timed_launch(mm_ctx* ctx, int kind, double work, hipStream_t s, F&& l
 // two half-size products (2 f x f factor values against the grid's other dimension).
 double gemm_work(const GemmArgs& g, int prec) {
   if (use_fold(g, prec)) {
-    const double f = g.K - g.K / 2;
-    return 4.0 * f * f * (g.b_trans ? (double)g.N : (double)g.M) * g.inner * g.groups;
+    // each of the fold_blocks stacked n x n factors contributes a half-size pair
+    const int G = g.fold_blocks > 1 ? g.fold_blocks : 1;
+    const int n = g.K / G;
+    const double f = n - n / 2;
+    return 4.0 * f * f * G * (g.b_trans ? (double)g.N : (double)g.M) * g.inner * g.groups;
   }
   return 2.0 * g.M * (double)g.N * g.K * g.inner * g.groups;
 }
