@@ -300,19 +300,22 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
   const bool gpair = BT ? gcol + 1 < N : true;                  // both columns inside
   const int gc0 = min(gcol, N - 1), gc1 = min(gcol + 1, N - 1);
   d2 rf, q1, q2;   // raw factor pair; grid values and their mirror partners
-  // the block and in-block position of folded position kk (past the end: the last block)
-  auto split = [&](int kk, int& g0, int& r) {
-    g0 = min(kk / fl, G - 1);
-    r = kk - g0 * fl;
-  };
+  // modes 2/3: the block lg0 and in-block position lr0 of this thread's folded position
+  // k0 + gk in the next chunk to load (past the end: the last block), advanced by KC per
+  // chunk without a division; sr0 keeps the loaded chunk's position for its store
+  int lg0 = min(gk / fl, G - 1), lr0 = gk - lg0 * fl, sr0 = 0;
   auto load = [&](int k0, auto tail) {
     constexpr bool T = decltype(tail)::value;
     // (an index past the factor row is clamped; its values are zeroed when stored)
     rf = *reinterpret_cast<const d2*>(fbase + (T ? min(k0 + kq, kf - 2) : k0 + kq));
     if (BT) {
-      int g0, r;
-      split(k0 + gk, g0, r);
-      const int base = g0 * n;
+      const int r = lr0, base = lg0 * n;
+      sr0 = lr0;
+      lr0 += KC;
+      while (lr0 >= fl && lg0 < G - 1) {
+        lr0 -= fl;
+        ++lg0;
+      }
       if (!T && gpair) {
         q1 = *reinterpret_cast<const d2u*>(X + (base + r) * ldx + gcol);
         q2 = *reinterpret_cast<const d2u*>(X + (base + n - 1 - r) * ldx + gcol);
@@ -345,8 +348,7 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
       sf.y = k0 + kq + 1 < kf ? rf.y : 0.0;
     }
     if (BT) {
-      int g0, rr;
-      split(k0 + gk, g0, rr);
+      const int rr = sr0;
       const bool live = k0 + gk < kf;
       if (!T || (live && rr < m)) {
         rs = q1 + q2;
@@ -375,9 +377,16 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
   using Body = std::false_type;
 
   // a chunk needs no clamping or zeroing when its positions lie in one block, below m
-  auto body_chunk = [&](int k0) { return (k0 % fl) + KC <= m; };
+  // (km: the first position of the next chunk modulo fl, advanced without a division)
+  int km = 0;
+  auto next_body = [&]() {
+    const bool body = km + KC <= m;
+    km += KC;
+    while (km >= fl) km -= fl;
+    return body;
+  };
   const int nch = (kf + KC - 1) / KC;
-  if (body_chunk(0)) {
+  if (next_body()) {
     load(0, Body());
     store(0, 0, Body());
   } else {
@@ -388,7 +397,7 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
   for (int c = 0; c < nch; ++c) {
     const int cur = c & 1;
     const int k1 = (c + 1) * KC;
-    const bool body1 = body_chunk(k1);
+    const bool body1 = next_body();
     if (c + 1 < nch) {
       if (body1) load(k1, Body());
       else load(k1, Tail());
