@@ -177,31 +177,72 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
   const double* __restrict__ a = p.a;
   // uu[y][z][k] = u at (x + k, y0 - 1 + y, z0 - 1 + z) (2D: z0 + z); zero outside the grid
   double uu[YH][ZH][P], aa[YH][ZH][P];
+  // the rows of u and a at (x2, x3) = (i2, i3) into cu, ca (zero outside the grid)
+  auto load_rows = [&](double (&cu)[P], double (&ca)[P], int i2, int i3, bool need) {
+    const bool urow = need && ucnt > 0 && i2 >= 0 && i2 < n2 && i3 >= 0 && i3 < n3;
+    const bool arow = need && acnt > 0 && i2 >= -1 && i2 <= n2 && (D == 2 || (i3 >= -1 && i3 <= n3));
+    if (urow) {
+      load_row<P>(cu, u, x + s2 * i2 + s3 * i3, nu, ucnt);
+#pragma unroll
+      for (int k = 0; k < P; ++k)
+        if (k >= ucnt) cu[k] = 0.0;
+    } else {
+#pragma unroll
+      for (int k = 0; k < P; ++k) cu[k] = 0.0;
+    }
+    if (arow) {
+      load_row<P>(ca, a, (x + 1) + t2 * (i2 + 1) + ((D == 3) ? t3 * (i3 + 1) : 0), na, acnt);
+    } else {
+#pragma unroll
+      for (int k = 0; k < P; ++k) ca[k] = 0.0;
+    }
+  };
+  // 3D: the x2 neighbours of a wave's centre rows are the centre rows of the waves beside
+  // it in the block, shared through LDS (the 2 ZT rows just outside the block are brought
+  // by the first 2 ZT waves): per array and wave, five row loads instead of eight (ZT = 2)
+  // or three or four instead of five (ZT = 1)
+  constexpr bool SHARE = (D == 3);
 #pragma unroll
   for (int y = 0; y < YH; ++y)
 #pragma unroll
     for (int z = 0; z < ZH; ++z) {
-      const int i2 = y0 - 1 + y;
-      const int i3 = (D == 3) ? z0 - 1 + z : 0;
+      if (SHARE && y != 1) continue;
       const bool need = (D == 3) ? !((y == 0 || y == YH - 1) && (z == 0 || z == ZH - 1)) : true;
-      const bool urow = need && ucnt > 0 && i2 >= 0 && i2 < n2 && i3 >= 0 && i3 < n3;
-      const bool arow = need && acnt > 0 && i2 >= -1 && i2 <= n2 && (D == 2 || (i3 >= -1 && i3 <= n3));
-      if (urow) {
-        load_row<P>(uu[y][z], u, x + s2 * i2 + s3 * i3, nu, ucnt);
-#pragma unroll
-        for (int k = 0; k < P; ++k)
-          if (k >= ucnt) uu[y][z][k] = 0.0;
-      } else {
-#pragma unroll
-        for (int k = 0; k < P; ++k) uu[y][z][k] = 0.0;
-      }
-      if (arow) {
-        load_row<P>(aa[y][z], a, (x + 1) + t2 * (i2 + 1) + ((D == 3) ? t3 * (i3 + 1) : 0), na, acnt);
-      } else {
-#pragma unroll
-        for (int k = 0; k < P; ++k) aa[y][z][k] = 0.0;
-      }
+      load_rows(uu[y][z], aa[y][z], y0 - 1 + y, (D == 3) ? z0 - 1 + z : 0, need);
     }
+  if constexpr (SHARE) {
+    // slot ZT (r + 1) + (z - 1): block row r (-1..SW, x2 = by SW + r) at centre plane z
+    constexpr int NS = ZT * (SW + 2);
+    __shared__ __attribute__((aligned(16))) double Lu[NS][64 * P], La[NS][64 * P];
+    auto put = [&](double (&L)[NS][64 * P], int slot, const double (&v)[P]) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) L[slot][P * tx + k] = v[k];
+    };
+    auto get = [&](double (&L)[NS][64 * P], int slot, double (&v)[P]) {
+#pragma unroll
+      for (int k = 0; k < P; ++k) v[k] = L[slot][P * tx + k];
+    };
+    if (w < 2 * ZT) {
+      const int r = (w < ZT) ? -1 : SW, zo = 1 + w % ZT;
+      double ou[P], oa[P];
+      load_rows(ou, oa, by * SW + r, z0 - 1 + zo, true);
+      put(Lu, ZT * (r + 1) + zo - 1, ou);
+      put(La, ZT * (r + 1) + zo - 1, oa);
+    }
+#pragma unroll
+    for (int z = 1; z <= ZT; ++z) {
+      put(Lu, ZT * (w + 1) + z - 1, uu[1][z]);
+      put(La, ZT * (w + 1) + z - 1, aa[1][z]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int z = 1; z <= ZT; ++z) {
+      get(Lu, ZT * w + z - 1, uu[0][z]);
+      get(La, ZT * w + z - 1, aa[0][z]);
+      get(Lu, ZT * (w + 2) + z - 1, uu[2][z]);
+      get(La, ZT * (w + 2) + z - 1, aa[2][z]);
+    }
+  }
   const bool edge = (tx == 0) || (tx == 63);
   const int xe = (tx == 0) ? x0 - 1 : x0 + 64 * P;   // the segment's outside neighbour
   const bool useg = sg.nxs > 1;                      // u beyond the segment can be nonzero
