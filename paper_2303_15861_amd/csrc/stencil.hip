@@ -197,22 +197,22 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
       for (int k = 0; k < P; ++k) ca[k] = 0.0;
     }
   };
-  // 3D: the x2 neighbours of a wave's centre rows are the centre rows of the waves beside
-  // it in the block, shared through LDS (the 2 ZT rows just outside the block are brought
-  // by the first 2 ZT waves): per array and wave, five row loads instead of eight (ZT = 2)
-  // or three or four instead of five (ZT = 1)
-  constexpr bool SHARE = (D == 3);
+  // The x2 halo rows of a wave are centre rows of the waves beside it in the block, shared
+  // through LDS (the 2 ZT rows just outside the block are brought by the first 2 ZT
+  // waves). Per array and wave: 3D five row loads instead of eight (1 x 2 patch) or three
+  // or four instead of five (1 x 1); 2D two or three instead of four.
+  constexpr int ZB = (D == 3) ? 1 : 0;   // index in uu of the first centre plane
 #pragma unroll
-  for (int y = 0; y < YH; ++y)
+  for (int y = 1; y <= YT; ++y)
 #pragma unroll
     for (int z = 0; z < ZH; ++z) {
-      if (SHARE && y != 1) continue;
       const bool need = (D == 3) ? !((y == 0 || y == YH - 1) && (z == 0 || z == ZH - 1)) : true;
       load_rows(uu[y][z], aa[y][z], y0 - 1 + y, (D == 3) ? z0 - 1 + z : 0, need);
     }
-  if constexpr (SHARE) {
-    // slot ZT (r + 1) + (z - 1): block row r (-1..SW, x2 = by SW + r) at centre plane z
-    constexpr int NS = ZT * (SW + 2);
+  {
+    // slot ZT (r + 1) + zi: block row r (-1..BR, x2 = by BR + r) at centre plane zi
+    constexpr int BR = YT * SW;
+    constexpr int NS = ZT * (BR + 2);
     __shared__ __attribute__((aligned(16))) double Lu[NS][64 * P], La[NS][64 * P];
     auto put = [&](double (&L)[NS][64 * P], int slot, const double (&v)[P]) {
 #pragma unroll
@@ -223,24 +223,26 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
       for (int k = 0; k < P; ++k) v[k] = L[slot][P * tx + k];
     };
     if (w < 2 * ZT) {
-      const int r = (w < ZT) ? -1 : SW, zo = 1 + w % ZT;
+      const int r = (w < ZT) ? -1 : BR, zi = w % ZT;
       double ou[P], oa[P];
-      load_rows(ou, oa, by * SW + r, z0 - 1 + zo, true);
-      put(Lu, ZT * (r + 1) + zo - 1, ou);
-      put(La, ZT * (r + 1) + zo - 1, oa);
+      load_rows(ou, oa, by * BR + r, (D == 3) ? z0 + zi : 0, true);
+      put(Lu, ZT * (r + 1) + zi, ou);
+      put(La, ZT * (r + 1) + zi, oa);
     }
 #pragma unroll
-    for (int z = 1; z <= ZT; ++z) {
-      put(Lu, ZT * (w + 1) + z - 1, uu[1][z]);
-      put(La, ZT * (w + 1) + z - 1, aa[1][z]);
-    }
+    for (int y = 1; y <= YT; ++y)
+#pragma unroll
+      for (int zi = 0; zi < ZT; ++zi) {
+        put(Lu, ZT * (w * YT + y) + zi, uu[y][ZB + zi]);
+        put(La, ZT * (w * YT + y) + zi, aa[y][ZB + zi]);
+      }
     __syncthreads();
 #pragma unroll
-    for (int z = 1; z <= ZT; ++z) {
-      get(Lu, ZT * w + z - 1, uu[0][z]);
-      get(La, ZT * w + z - 1, aa[0][z]);
-      get(Lu, ZT * (w + 2) + z - 1, uu[2][z]);
-      get(La, ZT * (w + 2) + z - 1, aa[2][z]);
+    for (int zi = 0; zi < ZT; ++zi) {
+      get(Lu, ZT * (w * YT) + zi, uu[0][ZB + zi]);
+      get(La, ZT * (w * YT) + zi, aa[0][ZB + zi]);
+      get(Lu, ZT * (w * YT + YT + 1) + zi, uu[YT + 1][ZB + zi]);
+      get(La, ZT * (w * YT + YT + 1) + zi, aa[YT + 1][ZB + zi]);
     }
   }
   const bool edge = (tx == 0) || (tx == 63);
