@@ -297,7 +297,10 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
   const int gk = BT ? (tid >> 6) : kq;                          // grid k within the chunk
   const int gcol = BT ? c0 + 2 * (tid & 63) : 0;                // modes 2/3: first column
   const int grow = BT ? 0 : min(r0 + (tid >> 2), M - 1);        // mode 1: grid row
-  const bool gpair = BT ? gcol + 1 < N : true;                  // both columns inside
+  // modes 2/3: both columns of the pair inside the row (with a padded row stride the
+  // second may be padding: it then feeds only masked outputs, and no lane of the last
+  // column tile leaves the 16-byte path)
+  const bool gpair = BT ? gcol + 1 < ldx : true;
   const int gc0 = min(gcol, N - 1), gc1 = min(gcol + 1, N - 1);
   d2 rf, q1, q2;   // raw factor pair; grid values and their mirror partners
   // modes 2/3: the block lg0 and in-block position lr0 of this thread's folded position
