@@ -242,7 +242,11 @@ constexpr int PFN = 128 + 4;   // [k][n] pitch of the modes-2/3 grid tiles
 template <int BT>
 __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
   constexpr int KC = 8;        // folded k per chunk
-  constexpr int PF = KC + 2;   // [row][k] pitch in doubles (16-byte aligned rows)
+  constexpr int PF = KC;       // [row][k] pitch in doubles: rows of four 16-byte units
+  // [row][k] tiles: unit u = k/2 of row r sits at unit u ^ (r/4 mod 4), so that the 16-byte
+  // stores (four threads per row) and the fragment reads (sixteen rows at one unit) both
+  // spread over all banks (k even)
+  auto rk = [](int r, int k) { return r * PF + ((((k >> 1) ^ (r >> 2)) & 3) << 1); };
   const int L = blockIdx.x;
   const int P = (L & 7) * p.per_xcd + (L >> 3);
   if (P >= p.total) return;
@@ -371,8 +375,8 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
         rd[q] = rr < m ? q1[q] - q2[q] : 0.0;
       }
     }
-    *reinterpret_cast<d2*>(&Fs[buf][fr * PF + kq]) = sf;
-    const int gi = BT ? gk * PFN + 2 * (tid & 63) : (tid >> 2) * PF + kq;
+    *reinterpret_cast<d2*>(&Fs[buf][rk(fr, kq)]) = sf;
+    const int gi = BT ? gk * PFN + 2 * (tid & 63) : rk(tid >> 2, kq);
     *reinterpret_cast<d2*>(&Gs[buf][0][gi]) = rs;
     *reinterpret_cast<d2*>(&Gs[buf][1][gi]) = rd;
   };
@@ -413,8 +417,8 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
       const int kb = (KC / 4) * lg + 2 * h;
       if (BT) {
         // wave: folded rows 16 wr + [0, 16) of Es and of Ed, columns 64 wc + [0, 64)
-        const d2 as = *reinterpret_cast<const d2*>(fs + (16 * wr + lr) * PF + kb);
-        const d2 ad = *reinterpret_cast<const d2*>(fs + (64 + 16 * wr + lr) * PF + kb);
+        const d2 as = *reinterpret_cast<const d2*>(fs + rk(16 * wr + lr, kb));
+        const d2 ad = *reinterpret_cast<const d2*>(fs + rk(64 + 16 * wr + lr, kb));
         // the Es products against the s tile, then the Ed products against the d tile (one
         // set of grid fragments live at a time)
 #pragma unroll
@@ -438,12 +442,12 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
         d2 as[2], ad[2], bf[4];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          as[i] = *reinterpret_cast<const d2*>(gs + (32 * wr + 16 * i + lr) * PF + kb);
-          ad[i] = *reinterpret_cast<const d2*>(gd + (32 * wr + 16 * i + lr) * PF + kb);
+          as[i] = *reinterpret_cast<const d2*>(gs + rk(32 * wr + 16 * i + lr, kb));
+          ad[i] = *reinterpret_cast<const d2*>(gd + rk(32 * wr + 16 * i + lr, kb));
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          bf[j] = *reinterpret_cast<const d2*>(fs + ((j >> 1) * 64 + 32 * wc + 16 * (j & 1) + lr) * PF + kb);
+          bf[j] = *reinterpret_cast<const d2*>(fs + rk((j >> 1) * 64 + 32 * wc + 16 * (j & 1) + lr, kb));
 #pragma unroll
         for (int st = 0; st < 2; ++st)
 #pragma unroll
