@@ -301,10 +301,20 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
   const int gk = BT ? (tid >> 6) : kq;                          // grid k within the chunk
   const int gcol = BT ? c0 + 2 * (tid & 63) : 0;                // modes 2/3: first column
   const int grow = BT ? 0 : min(r0 + (tid >> 2), M - 1);        // mode 1: grid row
-  // modes 2/3: both columns of the pair inside the row (with a padded row stride the
-  // second may be padding: it then feeds only masked outputs, and no lane of the last
-  // column tile leaves the 16-byte path)
-  const bool gpair = BT ? gcol + 1 < ldx : true;
+  // modes 2/3: the body chunks read the 16-byte column pair at gpc. Values that feed only
+  // masked outputs may come from anywhere inside the operand, so that no lane of the last
+  // column tile leaves the 16-byte path: the second column may be row padding (gcol + 1 <
+  // ldx), a pair starting at the last column of an unpadded row takes the next row's first
+  // value (not in the operand's last slab, where no row may follow), and a pair wholly
+  // past the last column reads the last two columns
+  int gpc = gcol;
+  bool gpair = true;
+  if (BT && gcol + 1 >= ldx) {
+    if (gcol >= N && N >= 2)
+      gpc = N - 2;
+    else
+      gpair = gcol + 1 == ldx && b + 1 < p.inner;
+  }
   const int gc0 = min(gcol, N - 1), gc1 = min(gcol + 1, N - 1);
   d2 rf, q1, q2;   // raw factor pair; grid values and their mirror partners
   // modes 2/3: the block lg0 and in-block position lr0 of this thread's folded position
@@ -324,8 +334,8 @@ __global__ __launch_bounds__(512, 4) void gemm_f64_fold(GemmArgs p) {
         ++lg0;
       }
       if (!T && gpair) {
-        q1 = *reinterpret_cast<const d2u*>(X + (base + r) * ldx + gcol);
-        q2 = *reinterpret_cast<const d2u*>(X + (base + n - 1 - r) * ldx + gcol);
+        q1 = *reinterpret_cast<const d2u*>(X + (base + r) * ldx + gpc);
+        q2 = *reinterpret_cast<const d2u*>(X + (base + n - 1 - r) * ldx + gpc);
       } else {
         const int rc = base + min(r, f - 1), rm = base + n - 1 - min(r, f - 1);   // rm >= rc
         q1 = d2{X[rc * ldx + gc0], X[rc * ldx + gc1]};
