@@ -177,15 +177,14 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
   const double* __restrict__ a = p.a;
   // uu[y][z][k] = u at (x + k, y0 - 1 + y, z0 - 1 + z) (2D: z0 + z); zero outside the grid
   double uu[YH][ZH][P], aa[YH][ZH][P];
-  // the rows of u and a at (x2, x3) = (i2, i3) into cu, ca (zero outside the grid)
+  // the rows of u and a at (x2, x3) = (i2, i3) into cu, ca (zero outside the grid; the u
+  // values of a lane past the row's end are zeroed by zero_tail once every row's loads
+  // are in flight, so that no row waits for the one before)
   auto load_rows = [&](double (&cu)[P], double (&ca)[P], int i2, int i3, bool need) {
     const bool urow = need && ucnt > 0 && i2 >= 0 && i2 < n2 && i3 >= 0 && i3 < n3;
     const bool arow = need && acnt > 0 && i2 >= -1 && i2 <= n2 && (D == 2 || (i3 >= -1 && i3 <= n3));
     if (urow) {
       load_row<P>(cu, u, x + s2 * i2 + s3 * i3, nu, ucnt);
-#pragma unroll
-      for (int k = 0; k < P; ++k)
-        if (k >= ucnt) cu[k] = 0.0;
     } else {
 #pragma unroll
       for (int k = 0; k < P; ++k) cu[k] = 0.0;
@@ -197,11 +196,22 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
       for (int k = 0; k < P; ++k) ca[k] = 0.0;
     }
   };
+  auto zero_tail = [&](double (&cu)[P]) {
+#pragma unroll
+    for (int k = 0; k < P; ++k)
+      if (k >= ucnt) cu[k] = 0.0;
+  };
   // The x2 halo rows of a wave are centre rows of the waves beside it in the block, shared
   // through LDS (the 2 ZT rows just outside the block are brought by the first 2 ZT
   // waves). Per array and wave: 3D five row loads instead of eight (1 x 2 patch) or three
   // or four instead of five (1 x 1); 2D two or three instead of four.
   constexpr int ZB = (D == 3) ? 1 : 0;   // index in uu of the first centre plane
+  // the row just outside the block that this wave brings (first 2 ZT waves), loaded first
+  constexpr int BR = YT * SW;
+  const bool outw = w < 2 * ZT;
+  const int orr = (w < ZT) ? -1 : BR, ozi = w % ZT;
+  double ou[P], oa[P];
+  load_rows(ou, oa, by * BR + orr, (D == 3) ? z0 + ozi : 0, outw);
 #pragma unroll
   for (int y = 1; y <= YT; ++y)
 #pragma unroll
@@ -209,9 +219,13 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
       const bool need = (D == 3) ? !((y == 0 || y == YH - 1) && (z == 0 || z == ZH - 1)) : true;
       load_rows(uu[y][z], aa[y][z], y0 - 1 + y, (D == 3) ? z0 - 1 + z : 0, need);
     }
+#pragma unroll
+  for (int y = 1; y <= YT; ++y)
+#pragma unroll
+    for (int z = 0; z < ZH; ++z) zero_tail(uu[y][z]);
+  zero_tail(ou);
   {
     // slot ZT (r + 1) + zi: block row r (-1..BR, x2 = by BR + r) at centre plane zi
-    constexpr int BR = YT * SW;
     constexpr int NS = ZT * (BR + 2);
     __shared__ __attribute__((aligned(16))) double Lu[NS][64 * P], La[NS][64 * P];
     auto put = [&](double (&L)[NS][64 * P], int slot, const double (&v)[P]) {
@@ -222,12 +236,9 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
 #pragma unroll
       for (int k = 0; k < P; ++k) v[k] = L[slot][P * tx + k];
     };
-    if (w < 2 * ZT) {
-      const int r = (w < ZT) ? -1 : BR, zi = w % ZT;
-      double ou[P], oa[P];
-      load_rows(ou, oa, by * BR + r, (D == 3) ? z0 + zi : 0, true);
-      put(Lu, ZT * (r + 1) + zi, ou);
-      put(La, ZT * (r + 1) + zi, oa);
+    if (outw) {
+      put(Lu, ZT * (orr + 1) + ozi, ou);
+      put(La, ZT * (orr + 1) + ozi, oa);
     }
 #pragma unroll
     for (int y = 1; y <= YT; ++y)
