@@ -219,46 +219,58 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
       const bool need = (D == 3) ? !((y == 0 || y == YH - 1) && (z == 0 || z == ZH - 1)) : true;
       load_rows(uu[y][z], aa[y][z], y0 - 1 + y, (D == 3) ? z0 - 1 + z : 0, need);
     }
+  // with the rows: the segment-end neighbours of the centre rows (lanes 0 and 63) and a
+  // separate stage base (base0 other than u), so that no load is issued after the rows
+  // have been waited for
+  const bool edge = (tx == 0) || (tx == 63);
+  const int xe = (tx == 0) ? x0 - 1 : x0 + 64 * P;   // the segment's outside neighbour
+  const bool useg = sg.nxs > 1;                      // u beyond the segment can be nonzero
+  const bool wpre = p.base0 != nullptr && p.base0 != u;
+  double ue_c[YT][ZT], ae_c[YT][ZT], wb[YT][ZT][P];
+#pragma unroll
+  for (int y = 1; y <= YT; ++y)
+#pragma unroll
+    for (int zi = 0; zi < ZT; ++zi) {
+      const int i2 = y0 - 1 + y;
+      const int i3 = (D == 3) ? z0 + zi : 0;
+      const bool live_row = i2 < n2 && i3 < n3;
+      ue_c[y - 1][zi] = 0.0;
+      ae_c[y - 1][zi] = 0.0;
+      if (edge) {
+        if (useg && live_row && xe >= 0 && xe < n1) ue_c[y - 1][zi] = u[s2 * i2 + s3 * i3 + xe];
+        if (live_row && xe >= -1 && xe <= n1)
+          ae_c[y - 1][zi] = a[t2 * (i2 + 1) + ((D == 3) ? t3 * (i3 + 1) : 0) + xe + 1];
+      }
+      if (wpre && live_row && ucnt > 0) load_row<P>(wb[y - 1][zi], p.base0, x + s2 * i2 + s3 * i3, nu, ucnt);
+    }
 #pragma unroll
   for (int y = 1; y <= YT; ++y)
 #pragma unroll
     for (int z = 0; z < ZH; ++z) zero_tail(uu[y][z]);
   zero_tail(ou);
-  {
-    // slot ZT (r + 1) + zi: block row r (-1..BR, x2 = by BR + r) at centre plane zi
-    constexpr int NS = ZT * (BR + 2);
-    __shared__ __attribute__((aligned(16))) double Lu[NS][64 * P], La[NS][64 * P];
-    auto put = [&](double (&L)[NS][64 * P], int slot, const double (&v)[P]) {
+  // slot ZT (r + 1) + zi: block row r (-1..BR, x2 = by BR + r) at centre plane zi
+  constexpr int NS = ZT * (BR + 2);
+  __shared__ __attribute__((aligned(16))) double Lu[NS][64 * P], La[NS][64 * P];
+  auto put = [&](double (&L)[NS][64 * P], int slot, const double (&v)[P]) {
 #pragma unroll
-      for (int k = 0; k < P; ++k) L[slot][P * tx + k] = v[k];
-    };
-    auto get = [&](double (&L)[NS][64 * P], int slot, double (&v)[P]) {
+    for (int k = 0; k < P; ++k) L[slot][P * tx + k] = v[k];
+  };
+  auto get = [&](double (&L)[NS][64 * P], int slot, double (&v)[P]) {
 #pragma unroll
-      for (int k = 0; k < P; ++k) v[k] = L[slot][P * tx + k];
-    };
-    if (outw) {
-      put(Lu, ZT * (orr + 1) + ozi, ou);
-      put(La, ZT * (orr + 1) + ozi, oa);
-    }
+    for (int k = 0; k < P; ++k) v[k] = L[slot][P * tx + k];
+  };
+  if (outw) {
+    put(Lu, ZT * (orr + 1) + ozi, ou);
+    put(La, ZT * (orr + 1) + ozi, oa);
+  }
 #pragma unroll
-    for (int y = 1; y <= YT; ++y)
-#pragma unroll
-      for (int zi = 0; zi < ZT; ++zi) {
-        put(Lu, ZT * (w * YT + y) + zi, uu[y][ZB + zi]);
-        put(La, ZT * (w * YT + y) + zi, aa[y][ZB + zi]);
-      }
-    __syncthreads();
+  for (int y = 1; y <= YT; ++y)
 #pragma unroll
     for (int zi = 0; zi < ZT; ++zi) {
-      get(Lu, ZT * (w * YT) + zi, uu[0][ZB + zi]);
-      get(La, ZT * (w * YT) + zi, aa[0][ZB + zi]);
-      get(Lu, ZT * (w * YT + YT + 1) + zi, uu[YT + 1][ZB + zi]);
-      get(La, ZT * (w * YT + YT + 1) + zi, aa[YT + 1][ZB + zi]);
+      put(Lu, ZT * (w * YT + y) + zi, uu[y][ZB + zi]);
+      put(La, ZT * (w * YT + y) + zi, aa[y][ZB + zi]);
     }
-  }
-  const bool edge = (tx == 0) || (tx == 63);
-  const int xe = (tx == 0) ? x0 - 1 : x0 + 64 * P;   // the segment's outside neighbour
-  const bool useg = sg.nxs > 1;                      // u beyond the segment can be nonzero
+  __syncthreads();
   const double la = p.lam_amax;
 #pragma unroll
   for (int y = 1; y <= YT; ++y)
@@ -268,15 +280,23 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
       const int i3 = (D == 3) ? z0 - 1 + z : 0;
       const bool live_row = i2 < n2 && i3 < n3;
       const int64_t urow = s2 * i2 + s3 * i3;
-      const int64_t arow = t2 * (i2 + 1) + ((D == 3) ? t3 * (i3 + 1) : 0);
+      // the x2 halo rows of this centre row from LDS (read where they are used, so that
+      // only one centre row's halo is held at a time)
+      if (y == 1) {
+        get(Lu, ZT * (w * YT) + z - ZB, uu[0][z]);
+        get(La, ZT * (w * YT) + z - ZB, aa[0][z]);
+      }
+      if (y == YT) {
+        get(Lu, ZT * (w * YT + YT + 1) + z - ZB, uu[YT + 1][z]);
+        get(La, ZT * (w * YT + YT + 1) + z - ZB, aa[YT + 1][z]);
+      }
       const double* uc = uu[y][z];
       const double* ac = aa[y][z];
       // x1 neighbours across lanes (every lane takes part), then the segment ends
       double ul = wave::from_prev(uc[P - 1]), ur = wave::from_next(uc[0]);
       double al = wave::from_prev(ac[P - 1]), ar = wave::from_next(ac[0]);
       if (edge) {
-        const double ue = (useg && live_row && xe >= 0 && xe < n1) ? u[urow + xe] : 0.0;
-        const double ae = (live_row && xe >= -1 && xe <= n1) ? a[arow + xe + 1] : 0.0;
+        const double ue = ue_c[y - 1][z - ZB], ae = ae_c[y - 1][z - ZB];
         if (tx == 0) {
           ul = ue;
           al = ae;
@@ -340,9 +360,8 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& p, const Stencil
 #pragma unroll
         for (int k = 0; k < P; ++k) o[k] = uc[k] + p.c0 * g[k];
       } else {
-        load_row<P>(o, p.base0, idx, nu, ucnt);
 #pragma unroll
-        for (int k = 0; k < P; ++k) o[k] += p.c0 * g[k];
+        for (int k = 0; k < P; ++k) o[k] = wb[y - 1][z - ZB][k] + p.c0 * g[k];
       }
       if (p.flag) {
         bool bad = false;
