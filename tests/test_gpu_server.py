@@ -59,7 +59,10 @@ def test_alone_equals_mix_and_oracle(mm):
     target = synth.smooth_problem((24, 20, 16), 11, tau=2e-3, steps=20, scheme="l2b", beta=(3, -2, 1))
     others = [synth.smooth_problem((31, 31, 31), 21, tau=1e-3, steps=30),
               synth.smooth_problem((63, 63), 22, tau=1e-3, steps=40, beta=(5, 1)),
-              synth.smooth_problem((24, 20, 16), 27, tau=1e-3, steps=35, beta=(0, 4, 8)),
+              # (long enough to be still running when the target and the later requests of
+              # its class are admitted, so that grouped launches occur whatever the speed of
+              # the kernels and of the host's submissions)
+              synth.smooth_problem((24, 20, 16), 27, tau=1e-4, steps=800, beta=(0, 4, 8)),
               synth.smooth_problem((40, 33, 28), 23, tau=1e-3, steps=25),
               synth.smooth_problem((24, 20, 16), 28, tau=4e-3, steps=7),
               synth.smooth_problem((127, 127), 24, tau=5e-4, steps=50, beta=(0, 9)),
